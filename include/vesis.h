@@ -1,0 +1,228 @@
+/*
+ * vesis.h - C ABI of the MI355X (gfx950) VESIS hot path.
+ *
+ * The operations follow the statement of the problem in arXiv 2208.05524:
+ * solute atoms with positions r_i, charges Q_i and solute-water LJ
+ * parameters (sigma_i, eps_i) sit in the box Omega = (c - L, c + L)^3
+ * (Sec. "A Binary Level-Set Method"), which carries a uniform grid of n^3
+ * cells of edge h = 2L/n.  A binary level set phi labels every cell solute
+ * (-1) or solvent (+1).  The discrete free energy is Eq. "4flip": the kernel
+ * surface energy, h^3 times the energy density U (Eq. "Ur": rho_w-weighted
+ * LJ plus the Coulomb-field approximation) summed over solvent cells, and
+ * the integral of U over R^3 outside the box.  The interface is relaxed by
+ * flipping band cells whose energy change (Eqs. "dGj1", "dGj2") is negative;
+ * atoms move by adaptive-mobility gradient descent (Eq. "eq:moveatoms",
+ * Eq. "eq:adjustmml" and Steps 3.1-3.4 of the algorithm).
+ *
+ * Conventions for every call:
+ *  - Pointers named in the argument lists are host pointers unless stated.
+ *    Host inputs are copied before the call returns; the library never keeps
+ *    a caller pointer.  Arrays of atoms are row-major (atom, xyz), FP64.
+ *  - Cell (i, j, k) has centre c - L + (i + 1/2, j + 1/2, k + 1/2) h and
+ *    linear index i + n (j + n k) (x fastest).  Labels are int8: -1 solute,
+ *    +1 solvent.  Cells outside the box count as solvent and never flip.
+ *  - All device work runs on the stream given to vesis_create, in order.
+ *    Calls that return host data synchronise that stream before returning.
+ *  - Device memory: one caller-provided workspace (vesis_workspace_size /
+ *    vesis_set_workspace); the library allocates no device memory itself.
+ *  - Every call returns a vesis_status; negative values are errors and the
+ *    per-context message is available from vesis_last_error.  After an error
+ *    the context stays usable; device state may be partly updated only for
+ *    VESIS_E_DEVICE.
+ *  - Call order: vesis_set_params, vesis_set_grid, vesis_set_atoms,
+ *    vesis_set_workspace, vesis_init_labels; a call made before its inputs
+ *    exist returns VESIS_E_STATE.  Changing the grid or the atom count
+ *    invalidates the workspace and the labels.
+ *  - One host thread per context at a time; separate contexts are independent.
+ */
+#ifndef VESIS_H
+#define VESIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vesis_ctx vesis_ctx;
+
+typedef enum {
+    VESIS_OK = 0,
+    VESIS_NOT_CONVERGED = 1,   /* minimisation stopped at max_sweeps; state valid, resumable */
+    VESIS_E_ARG = -1,          /* bad argument (null pointer, size, range) */
+    VESIS_E_STATE = -2,        /* call made before its inputs were set */
+    VESIS_E_OUT_OF_BOX = -3,   /* an atom lies outside the box */
+    VESIS_E_NONFINITE = -4,    /* NaN or Inf in an input */
+    VESIS_E_NO_DEVICE = -5,    /* no usable gfx950 device */
+    VESIS_E_DEVICE = -6,       /* HIP runtime error */
+    VESIS_E_WORKSPACE = -7     /* workspace missing or too small */
+} vesis_status;
+
+/* Model constants, in one consistent unit system (e.g. nm, kJ/mol, e).
+ * rho_w, gamma0, eps_m, eps_w: Table "Model parameters" of the paper;
+ * coulomb_k = 1/(4 pi eps0) so the CFA prefactor 1/(32 pi^2 eps0)(1/eps_w -
+ * 1/eps_m) of Eq. "G_VISM" equals coulomb_k/(8 pi)(1/eps_w - 1/eps_m);
+ * rho_s = delta/h, the kernel radius in cells (1 < rho_s <= 3; the paper
+ * writes delta = lambda sqrt(h)); r2_min floors |x - r_i|^2 (> 0);
+ * far_nf, far_ntau: Gauss-Legendre orders of the far-field quadrature over
+ * R^3 outside the box (per face axis and radially, 1..128);
+ * precision: 32 (FP32 density sums, FP64 totals and FP64 near-tie
+ * decisions) or 64 (FP64 density throughout). */
+typedef struct {
+    double rho_w;
+    double gamma0;
+    double eps_m;
+    double eps_w;
+    double coulomb_k;
+    double rho_s;
+    double r2_min;
+    int32_t far_nf;
+    int32_t far_ntau;
+    int32_t precision;
+    int32_t reserved;
+} vesis_params;
+
+/* Energy parts of Eq. "4flip" plus the harmonic bond term of Eq. "Gss":
+ * geom = surface energy, *_in = h^3 sum over solvent cells, *_far = integral
+ * over R^3 outside the box. */
+typedef struct {
+    double geom, vdw_in, vdw_far, elec_in, elec_far, bond, total;
+} vesis_energy_parts;
+
+/* Interface minimisation report.  sweeps counts colour sweeps run, the last
+ * one (flipping nothing) included when converged; near_ties counts flip
+ * candidates whose FP32 energy change fell inside its error bound and were
+ * decided in FP64; fp64_recomputes counts cells whose density was recomputed
+ * in FP64 for that (each at most once per atom configuration). */
+typedef struct {
+    int32_t sweeps;
+    int32_t converged;
+    int64_t flips;
+    int64_t band_cells;
+    int64_t near_ties;
+    int64_t fp64_recomputes;
+} vesis_min_stats;
+
+/* State of the adaptive-mobility descent (Sec. "Adaptive-Mobility Gradient
+ * Descent"): M (starts at 1), alpha (1/sqrt 2), dt, dG_frac (delta G* =
+ * dG_frac |G_old|, 0.05), M_min (give up below), G_old (energy at the
+ * accepted positions, written by the step), N_cnt (consecutive steps with
+ * the same M), N_cnt_max (N_cnt*, 5), k (accepted steps), max_retries. */
+typedef struct {
+    double M, alpha, dt, dG_frac, M_min, G_old;
+    int32_t N_cnt, N_cnt_max, k, max_retries;
+} vesis_mobility;
+
+typedef struct {
+    int32_t accepted, retries;
+    double G_old, G_new, max_grad, omega;
+} vesis_step_info;
+
+/* Create a context on HIP device `device`, issuing all work on `stream`
+ * (a hipStream_t; NULL = the null stream).  Returns VESIS_E_NO_DEVICE when
+ * the device does not exist or is not gfx950.  *out is NULL on error. */
+vesis_status vesis_create(int32_t device, void* stream, vesis_ctx** out);
+
+/* Destroy a context (NULL is a no-op).  Does not free the workspace, which
+ * belongs to the caller. */
+void vesis_destroy(vesis_ctx* ctx);
+
+/* Message of the last error on this context ("" if none).  The string lives
+ * until the next call on the context. */
+const char* vesis_last_error(const vesis_ctx* ctx);
+
+/* Set the model constants (see vesis_params).  Invalidates densities. */
+vesis_status vesis_set_params(vesis_ctx* ctx, const vesis_params* p);
+
+/* Set the cubic box and grid: n cells per edge (4 <= n <= 1024), centre
+ * c = center[0..2], cell edge h > 0 (Sec. "A Binary Level-Set Method").
+ * Invalidates the workspace and labels. */
+vesis_status vesis_set_grid(vesis_ctx* ctx, int32_t n, const double center[3], double h);
+
+/* Set the solute atoms: n >= 1 atoms, xyz (n x 3), charges q, LJ sigma > 0
+ * and eps >= 0 (Eq. "eq:LJpotential"); movable (n bytes, nonzero = moves in
+ * vesis_atom_step) may be NULL (all move).  Every atom must lie inside the
+ * box (VESIS_E_OUT_OF_BOX).  A new atom count invalidates the workspace. */
+vesis_status vesis_set_atoms(vesis_ctx* ctx, int64_t n, const double* xyz, const double* q,
+                             const double* sigma, const double* eps, const uint8_t* movable);
+
+/* Replace the atom positions (n x 3, same count).  on_device != 0 means xyz
+ * is a device pointer (copied device to device on the context stream). */
+vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_device);
+
+/* Copy the current atom positions (n x 3) to host memory. */
+vesis_status vesis_get_positions(vesis_ctx* ctx, double* xyz);
+
+/* Harmonic bonds of Eq. "Gss", (1/2) k (r_ij - r0)^2: nb bonds, ij (nb x 2
+ * atom indices), rest lengths r0 and constants k.  nb = 0 removes bonds.
+ * Must be called after vesis_set_atoms; takes effect at the next
+ * vesis_set_workspace if the bond count grew. */
+vesis_status vesis_set_bonds(vesis_ctx* ctx, int64_t nb, const int32_t* ij, const double* r0,
+                             const double* k);
+
+/* Bytes of device workspace needed for the current grid, atoms and bonds. */
+vesis_status vesis_workspace_size(vesis_ctx* ctx, size_t* bytes);
+
+/* Hand the context a device buffer of `bytes` bytes (256-byte aligned),
+ * owned by the caller and kept alive while the context uses it.
+ * VESIS_E_WORKSPACE when smaller than vesis_workspace_size. */
+vesis_status vesis_set_workspace(vesis_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Initial labels (Sec. "Initial surfaces").  mode 0: loose sphere, solute
+ * iff |x - c| <= param (param > 0); mode 1: tight surface, solute iff
+ * min_i (|x - r_i| - param * sigma_i) <= 0 (param > 0); mode 2: the caller's
+ * labels `user` (n^3 int8, each -1 or +1). */
+vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const int8_t* user);
+
+/* Relax the interface at fixed atoms (Step 2 of the algorithm): colour
+ * sweeps over the band (cells with a face neighbour of the other label),
+ * each sweep visiting the p^3 colours (i mod p) + p (j mod p) + p^2 (k mod p),
+ * p = ceil(rho_s), in order; within a colour every band cell whose energy
+ * change is negative flips (cells of one colour do not interact).  Stops
+ * after a sweep with no flip (VESIS_OK) or after max_sweeps sweeps
+ * (VESIS_NOT_CONVERGED; calling again resumes).  Recomputes the density
+ * first if the atoms moved.  out may be NULL. */
+vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out);
+
+/* Discrete free energy of the current labels and atoms (Eq. "4flip" plus
+ * bonds). */
+vesis_status vesis_energy(vesis_ctx* ctx, vesis_energy_parts* out);
+
+/* Forces F_n = -grad_{r_n} G at fixed labels (solvent and far-field terms of
+ * the Appendix gradient, taken as the exact derivative of the discrete
+ * energy, plus bonds), written to f_out (n x 3 host array). */
+vesis_status vesis_forces(vesis_ctx* ctx, double* f_out);
+
+/* One adaptive-mobility step at fixed labels (Steps 3.1-3.4): gradient at
+ * the current positions, omega = 1 / max |dG/dr| over movable atoms, trial
+ * R' = R - dt omega M grad G, rejected (M *= alpha, N_cnt = 0, retry from R)
+ * iff dG > dG* or (N_cnt >= N_cnt_max and 0 < dG <= dG*) with
+ * dG* = dG_frac |G_old|; otherwise accepted (N_cnt += 1).  Returns VESIS_OK
+ * on acceptance, VESIS_NOT_CONVERGED when M fell below M_min or the retries
+ * ran out (positions unchanged) or the gradient is zero. */
+vesis_status vesis_atom_step(vesis_ctx* ctx, vesis_mobility* state, vesis_step_info* out);
+
+/* Copy the labels (n^3 int8, -1/+1) to host memory. */
+vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);
+
+/* Copy the per-cell density parts U_LJ and U_CFA (n^3 FP64 each) and,
+ * if bound != NULL, the per-cell bound on |U_computed - U_exact| used for
+ * near-tie decisions (n^3 FP64; +inf marks cells always decided in FP64). */
+vesis_status vesis_get_density(vesis_ctx* ctx, double* u_lj, double* u_cfa, double* bound);
+
+/* Kernel timing for measurement: enable != 0 records HIP events around
+ * every launch of each kernel kind on the context stream. */
+vesis_status vesis_profile(vesis_ctx* ctx, int32_t enable);
+
+/* Accumulated device time (ms) and launch count of kernel kind `kind`
+ * since profiling was enabled: 0 density (grid), 1 far-field density,
+ * 2 initial labels, 3 flip passes, 4 energy reductions, 5 force adjoint,
+ * 6 other.  Synchronises the stream. */
+vesis_status vesis_profile_read(vesis_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VESIS_H */

@@ -1,0 +1,959 @@
+// Host runtime and C ABI of libvesis (see include/vesis.h).
+//
+// The context keeps host copies of the inputs, validates them, lays out the
+// caller's device workspace, and sequences the kernels on the caller's
+// stream.  All arithmetic of the hot path runs in the kernels; the host does
+// bookkeeping, the adaptive-mobility accept/reject logic on a handful of
+// scalars, and the trial positions R - dt omega M grad G.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vesis.h"
+#include "internal.h"
+
+using namespace vesis;
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;   // partial sums per reduction
+constexpr int SWEEP_BATCH = 8;     // colour sweeps launched between host checks
+constexpr double PI = 3.14159265358979323846;
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_m from
+// the asymptotic first guess, P_m and P_m' from the three-term recurrence.
+void gauss_legendre_rule(int m, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(m, 0.0);
+    w.assign(m, 0.0);
+    for (int i = 0; i < (m + 1) / 2; ++i) {
+        double z = std::cos(PI * (i + 0.75) / (m + 0.5));
+        double pm = 0.0, dpm = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            double a = 1.0, b = z;  // P_0, P_1
+            for (int k = 2; k <= m; ++k) {
+                const double c = ((2 * k - 1) * z * b - (k - 1) * a) / k;
+                a = b;
+                b = c;
+            }
+            pm = (m == 1) ? z : b;
+            const double pm1 = (m == 1) ? 1.0 : a;
+            dpm = m * (pm1 - z * pm) / (1.0 - z * z);
+            const double step = pm / dpm;
+            z -= step;
+            if (std::fabs(step) <= 1e-16 * std::fabs(z) + 1e-300) break;
+        }
+        double a = 1.0, b = z;
+        for (int k = 2; k <= m; ++k) {
+            const double c = ((2 * k - 1) * z * b - (k - 1) * a) / k;
+            a = b;
+            b = c;
+        }
+        const double pm1 = (m == 1) ? 1.0 : a;
+        pm = (m == 1) ? z : b;
+        dpm = m * (pm1 - z * pm) / (1.0 - z * z);
+        x[i] = -z;
+        x[m - 1 - i] = z;
+        w[i] = w[m - 1 - i] = 2.0 / ((1.0 - z * z) * dpm * dpm);
+    }
+}
+
+struct Layout {
+    size_t pos, prm64, prm32, pos_stage;
+    size_t boff, bother, br0, bk;
+    size_t ulj, ucfa, ex, ey, ez, bound, u64cache;
+    size_t bits;
+    size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez;
+    size_t red_d, red_i, scal_d, scal_i, sweep_flips;
+    size_t fpart, fout;
+    size_t total;
+    int64_t fchunks;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__global__ void pack_positions(const double* xyz, int64_t n, double4* pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos[i] = make_double4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], 0.0);
+}
+
+struct PendingEvent {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vesis_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    bool has_params = false;
+    vesis_params prm{};
+    bool has_grid = false;
+    Grid g{};
+    Stencil sc{};
+    bool has_atoms = false;
+    int64_t na = 0;
+    std::vector<double> xyz, q, sigma, eps;
+    std::vector<uint8_t> movable;
+    int64_t nb = 0;
+    std::vector<int32_t> b_off, b_other;
+    std::vector<double> b_r0, b_k;
+    std::vector<double> far_host;  // x, y, z, w per node
+    int64_t nfar = 0;
+
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool has_ws = false;
+    Layout lay{};
+    int64_t lay_na = -1, lay_nb = -1, lay_nfar = -1;
+    int lay_n = -1;
+
+    bool has_labels = false;
+    bool atoms_uploaded = false;
+    bool far_uploaded = false;
+    bool bonds_uploaded = false;
+    bool dens_valid = false;
+
+    bool prof = false;
+    double prof_ms[K_NKINDS] = {0};
+    int64_t prof_n[K_NKINDS] = {0};
+    std::vector<PendingEvent> pending;
+};
+
+namespace {
+
+vesis_status fail(vesis_ctx* c, vesis_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define CK(call)                                                                             \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, VESIS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_all(const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+template <typename T>
+T* at(vesis_ctx* c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+Atoms dev_atoms(vesis_ctx* c) {
+    Atoms a;
+    a.n = c->na;
+    a.pos = at<double4>(c, c->lay.pos);
+    a.prm64 = at<double4>(c, c->lay.prm64);
+    a.prm32 = at<float4>(c, c->lay.prm32);
+    return a;
+}
+
+Physics dev_physics(vesis_ctx* c) {
+    Physics ph;
+    ph.ccfa = c->prm.coulomb_k / (8.0 * PI) * (1.0 / c->prm.eps_w - 1.0 / c->prm.eps_m);
+    ph.r2min = c->prm.r2_min;
+    ph.rho_w = c->prm.rho_w;
+    ph.h3 = c->g.h * c->g.h * c->g.h;
+    return ph;
+}
+
+Bonds dev_bonds(vesis_ctx* c) {
+    Bonds b;
+    b.nb = c->nb;
+    b.off = at<int32_t>(c, c->lay.boff);
+    b.other = at<int32_t>(c, c->lay.bother);
+    b.r0 = at<double>(c, c->lay.br0);
+    b.k = at<double>(c, c->lay.bk);
+    return b;
+}
+
+// Kernel timing: record events around a launch when profiling is on.
+struct Timed {
+    vesis_ctx* c;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(vesis_ctx* c_, int k) : c(c_), kind(k) {
+        if (c->prof) {
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (c->prof) {
+            (void)hipEventRecord(b, c->stream);
+            c->pending.push_back({kind, a, b});
+        }
+    }
+};
+
+void drain_events(vesis_ctx* c) {
+    for (auto& e : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            c->prof_ms[e.kind] += ms;
+            c->prof_n[e.kind] += 1;
+        }
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    c->pending.clear();
+}
+
+void compute_stencil(vesis_ctx* c) {
+    const double rs = c->prm.rho_s;
+    for (int s = 0; s < 9; ++s) {
+        const double r = std::sqrt((double)s) / rs;
+        double v = 0.0;
+        if (s > 0 && (double)s < rs * rs) {
+            const double sn = std::sin(PI * r);
+            v = sn * sn;
+        }
+        c->sc.w[s] = v;
+    }
+    const double C0 = 8.0 * PI / (PI * PI - 3.0);  // = 1 / (pi int_0^1 r^3 sin^2(pi r) dr)
+    const double h = c->g.h;
+    c->sc.c = c->prm.gamma0 * C0 * h * h / (rs * rs * rs * rs);  // gamma0 C0 h^6 / delta^4
+    c->sc.p = (int)std::ceil(rs);
+}
+
+void compute_far_nodes(vesis_ctx* c) {
+    std::vector<double> gx, gw, tx, tw;
+    const int nf = c->prm.far_nf, nt = c->prm.far_ntau;
+    gauss_legendre_rule(nf, gx, gw);
+    gauss_legendre_rule(nt, tx, tw);
+    const double L = c->g.L;
+    const double ctr[3] = {c->g.cx, c->g.cy, c->g.cz};
+    c->nfar = 6LL * nf * nf * nt;
+    c->far_host.assign(4 * c->nfar, 0.0);
+    int64_t m = 0;
+    for (int face = 0; face < 6; ++face) {
+        const int ax = face / 2;
+        const double sg = (face & 1) ? -1.0 : 1.0;
+        const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+        for (int it = 0; it < nt; ++it) {
+            const double tau = 0.5 * (tx[it] + 1.0), wt = 0.5 * tw[it];
+            for (int iv = 0; iv < nf; ++iv)
+                for (int iu = 0; iu < nf; ++iu) {
+                    double y[3];
+                    y[ax] = sg * L;
+                    y[a1] = L * gx[iu];
+                    y[a2] = L * gx[iv];
+                    double* o = &c->far_host[4 * m];
+                    for (int d = 0; d < 3; ++d) o[d] = ctr[d] + y[d] / tau;
+                    // dV = L tau^-4 du dv dtau on the cone over a face
+                    o[3] = (L * gw[iu]) * (L * gw[iv]) * wt * L / (tau * tau * tau * tau);
+                    ++m;
+                }
+        }
+    }
+    c->far_uploaded = false;
+}
+
+Layout plan(const vesis_ctx* c) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o += align256(bytes ? bytes : 1);
+        return r;
+    };
+    const int64_t na = c->na, ncell = c->g.ncell(), nfar = c->nfar;
+    const int64_t nbi = 2 * c->nb;
+    L.pos = take(32 * na);
+    L.prm64 = take(32 * na);
+    L.prm32 = take(16 * na);
+    L.pos_stage = take(24 * na);
+    L.boff = take(4 * (na + 1));
+    L.bother = take(4 * nbi);
+    L.br0 = take(8 * nbi);
+    L.bk = take(8 * nbi);
+    L.ulj = take(8 * ncell);
+    L.ucfa = take(8 * ncell);
+    L.ex = take(8 * ncell);
+    L.ey = take(8 * ncell);
+    L.ez = take(8 * ncell);
+    L.bound = take(8 * ncell);
+    L.u64cache = take(8 * ncell);
+    L.bits = take(4 * c->g.nwords());
+    L.far_pts = take(32 * nfar);
+    L.far_ulj = take(8 * nfar);
+    L.far_ucfa = take(8 * nfar);
+    L.far_ex = take(8 * nfar);
+    L.far_ey = take(8 * nfar);
+    L.far_ez = take(8 * nfar);
+    L.red_d = take(8 * 2 * RED_BLOCKS);
+    L.red_i = take(8 * 8 * RED_BLOCKS);
+    L.scal_d = take(8 * 16);
+    L.scal_i = take(8 * 16);
+    L.sweep_flips = take(4 * SWEEP_BATCH);
+    L.fchunks = force_partial_chunks(c->g, na, nfar);
+    L.fpart = take(8 * 3 * (size_t)L.fchunks * na);
+    L.fout = take(8 * 3 * na);
+    L.total = o;
+    return L;
+}
+
+// scalar slots
+enum { SD_VOL = 0, SD_FAR = 2, SD_BOND = 4 };
+enum { SI_GEOM = 0, SI_BAND = 8, SI_CNT = 10 };
+
+vesis_status need(vesis_ctx* ctx, bool labels) {
+    if (!ctx->has_params) return fail(ctx, VESIS_E_STATE, "parameters not set");
+    if (!ctx->has_grid) return fail(ctx, VESIS_E_STATE, "grid not set");
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    if (!ctx->has_ws) return fail(ctx, VESIS_E_WORKSPACE, "workspace not set");
+    if (labels && !ctx->has_labels) return fail(ctx, VESIS_E_STATE, "labels not initialised");
+    return VESIS_OK;
+}
+
+vesis_status upload_inputs(vesis_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    if (!ctx->atoms_uploaded) {
+        const int64_t n = ctx->na;
+        std::vector<double> pos(4 * n), p64(4 * n);
+        std::vector<float> p32(4 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            pos[4 * i + 0] = ctx->xyz[3 * i + 0];
+            pos[4 * i + 1] = ctx->xyz[3 * i + 1];
+            pos[4 * i + 2] = ctx->xyz[3 * i + 2];
+            pos[4 * i + 3] = 0.0;
+            const double s2 = ctx->sigma[i] * ctx->sigma[i];
+            const double e4 = 4.0 * ctx->prm.rho_w * ctx->eps[i];
+            p64[4 * i + 0] = s2;
+            p64[4 * i + 1] = e4;
+            p64[4 * i + 2] = ctx->q[i];
+            p64[4 * i + 3] = ctx->sigma[i];
+            p32[4 * i + 0] = (float)s2;
+            p32[4 * i + 1] = (float)e4;
+            p32[4 * i + 2] = (float)ctx->q[i];
+            p32[4 * i + 3] = (float)std::fabs(ctx->q[i]);
+        }
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.pos, pos.data(), 32 * n, hipMemcpyHostToDevice, st));
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.prm64, p64.data(), 32 * n, hipMemcpyHostToDevice, st));
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.prm32, p32.data(), 16 * n, hipMemcpyHostToDevice, st));
+        CK(hipStreamSynchronize(st));
+        ctx->atoms_uploaded = true;
+    }
+    if (!ctx->bonds_uploaded) {
+        if (ctx->nb > 0) {
+            const size_t nbi = ctx->b_other.size();
+            CK(hipMemcpyAsync(ctx->ws + ctx->lay.boff, ctx->b_off.data(), 4 * (ctx->na + 1),
+                              hipMemcpyHostToDevice, st));
+            CK(hipMemcpyAsync(ctx->ws + ctx->lay.bother, ctx->b_other.data(), 4 * nbi,
+                              hipMemcpyHostToDevice, st));
+            CK(hipMemcpyAsync(ctx->ws + ctx->lay.br0, ctx->b_r0.data(), 8 * nbi,
+                              hipMemcpyHostToDevice, st));
+            CK(hipMemcpyAsync(ctx->ws + ctx->lay.bk, ctx->b_k.data(), 8 * nbi,
+                              hipMemcpyHostToDevice, st));
+            CK(hipStreamSynchronize(st));
+        }
+        ctx->bonds_uploaded = true;
+    }
+    if (!ctx->far_uploaded) {
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.far_pts, ctx->far_host.data(), 32 * ctx->nfar,
+                          hipMemcpyHostToDevice, st));
+        CK(hipStreamSynchronize(st));
+        ctx->far_uploaded = true;
+    }
+    return VESIS_OK;
+}
+
+// U, E and the error bound on every cell, the far field at every node, and
+// the far-field sums; resets the FP64 near-tie cache.
+vesis_status ensure_density(vesis_ctx* ctx) {
+    vesis_status s = upload_inputs(ctx);
+    if (s != VESIS_OK) return s;
+    if (ctx->dens_valid) return VESIS_OK;
+    hipStream_t st = ctx->stream;
+    const Atoms a = dev_atoms(ctx);
+    const Physics ph = dev_physics(ctx);
+    CellFields cf;
+    cf.ulj = at<double>(ctx, ctx->lay.ulj);
+    cf.ucfa = at<double>(ctx, ctx->lay.ucfa);
+    cf.ex = at<double>(ctx, ctx->lay.ex);
+    cf.ey = at<double>(ctx, ctx->lay.ey);
+    cf.ez = at<double>(ctx, ctx->lay.ez);
+    cf.bound = at<double>(ctx, ctx->lay.bound);
+    {
+        Timed t(ctx, K_DENSITY);
+        CK(launch_density_grid(ctx->g, a, ph, ctx->prm.precision, cf, st));
+    }
+    {
+        Timed t(ctx, K_OTHER);
+        CK(launch_fill_f64(at<double>(ctx, ctx->lay.u64cache), ctx->g.ncell(), NAN, st));
+    }
+    {
+        Timed t(ctx, K_FAR);
+        CK(launch_density_points(at<double4>(ctx, ctx->lay.far_pts), ctx->nfar, a, ph,
+                                 ctx->prm.precision, at<double>(ctx, ctx->lay.far_ulj),
+                                 at<double>(ctx, ctx->lay.far_ucfa), at<double>(ctx, ctx->lay.far_ex),
+                                 at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
+                                 st));
+        CK(launch_weighted_sum2(at<double4>(ctx, ctx->lay.far_pts), at<double>(ctx, ctx->lay.far_ulj),
+                                at<double>(ctx, ctx->lay.far_ucfa), ctx->nfar,
+                                at<double>(ctx, ctx->lay.red_d), RED_BLOCKS,
+                                at<double>(ctx, ctx->lay.scal_d) + SD_FAR, st));
+    }
+    ctx->dens_valid = true;
+    return VESIS_OK;
+}
+
+vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
+    vesis_status s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    const uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
+    {
+        Timed t(ctx, K_ENERGY);
+        CK(launch_energy_volume(ctx->g, bits, at<double>(ctx, ctx->lay.ulj),
+                                at<double>(ctx, ctx->lay.ucfa), at<double>(ctx, ctx->lay.red_d),
+                                RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
+        CK(launch_geom_counts(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,
+                              at<int64_t>(ctx, ctx->lay.scal_i) + SI_GEOM, st));
+        if (ctx->nb > 0)
+            CK(launch_bond_energy(dev_atoms(ctx), dev_bonds(ctx), at<double>(ctx, ctx->lay.red_d),
+                                  RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_BOND, st));
+    }
+    double sd[8];
+    int64_t si[16];
+    CK(hipMemcpyAsync(sd, ctx->ws + ctx->lay.scal_d, sizeof(sd), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(si, ctx->ws + ctx->lay.scal_i, sizeof(si), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const double h3 = ctx->g.h * ctx->g.h * ctx->g.h;
+    double geom = 0.0;
+    for (int s2 = 1; s2 <= 8; ++s2) geom += ctx->sc.w[s2] * (double)si[SI_GEOM + s2 - 1];
+    out->geom = ctx->sc.c * geom;
+    out->vdw_in = h3 * sd[SD_VOL];
+    out->elec_in = h3 * sd[SD_VOL + 1];
+    out->vdw_far = sd[SD_FAR];
+    out->elec_far = sd[SD_FAR + 1];
+    out->bond = ctx->nb > 0 ? sd[SD_BOND] : 0.0;
+    out->total = out->geom + out->vdw_in + out->vdw_far + out->elec_in + out->elec_far + out->bond;
+    return VESIS_OK;
+}
+
+vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
+    vesis_status s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    const Physics ph = dev_physics(ctx);
+    {
+        Timed t(ctx, K_FORCE);
+        CK(launch_forces(ctx->g, dev_atoms(ctx), ph, ctx->prm.precision,
+                         at<uint32_t>(ctx, ctx->lay.bits), at<double>(ctx, ctx->lay.ex),
+                         at<double>(ctx, ctx->lay.ey), at<double>(ctx, ctx->lay.ez),
+                         at<double4>(ctx, ctx->lay.far_pts), at<double>(ctx, ctx->lay.far_ex),
+                         at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
+                         ctx->nfar, dev_bonds(ctx), at<double>(ctx, ctx->lay.fpart),
+                         ctx->lay.fchunks, at<double>(ctx, ctx->lay.fout), st));
+    }
+    CK(hipMemcpyAsync(f_host, ctx->ws + ctx->lay.fout, 24 * ctx->na, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return VESIS_OK;
+}
+
+vesis_status put_positions(vesis_ctx* ctx, const double* xyz) {
+    std::memcpy(ctx->xyz.data(), xyz, sizeof(double) * 3 * ctx->na);
+    std::vector<double> pos(4 * ctx->na);
+    for (int64_t i = 0; i < ctx->na; ++i) {
+        pos[4 * i] = xyz[3 * i];
+        pos[4 * i + 1] = xyz[3 * i + 1];
+        pos[4 * i + 2] = xyz[3 * i + 2];
+        pos[4 * i + 3] = 0.0;
+    }
+    CK(hipMemcpyAsync(ctx->ws + ctx->lay.pos, pos.data(), 32 * ctx->na, hipMemcpyHostToDevice,
+                      ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->dens_valid = false;
+    return VESIS_OK;
+}
+
+bool inside_box(const vesis_ctx* c, const double* xyz, int64_t n) {
+    const double ctr[3] = {c->g.cx, c->g.cy, c->g.cz};
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d)
+            if (!(std::fabs(xyz[3 * i + d] - ctr[d]) < c->g.L)) return false;
+    return true;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+vesis_status vesis_create(int32_t device, void* stream, vesis_ctx** out) {
+    if (!out) return VESIS_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return VESIS_E_NO_DEVICE;
+    if (device < 0 || device >= count) return VESIS_E_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return VESIS_E_NO_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return VESIS_E_NO_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return VESIS_E_DEVICE;
+    vesis_ctx* c = new vesis_ctx();
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    *out = c;
+    return VESIS_OK;
+}
+
+void vesis_destroy(vesis_ctx* ctx) {
+    if (!ctx) return;
+    if (!ctx->pending.empty()) drain_events(ctx);
+    delete ctx;
+}
+
+const char* vesis_last_error(const vesis_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+vesis_status vesis_set_params(vesis_ctx* ctx, const vesis_params* p) {
+    if (!ctx || !p) return fail(ctx, VESIS_E_ARG, "null argument");
+    const double v[7] = {p->rho_w, p->gamma0, p->eps_m, p->eps_w, p->coulomb_k, p->rho_s, p->r2_min};
+    if (!finite_all(v, 7)) return fail(ctx, VESIS_E_NONFINITE, "non-finite parameter");
+    if (p->rho_w < 0 || p->gamma0 < 0 || p->eps_m <= 0 || p->eps_w <= 0 || p->r2_min <= 0)
+        return fail(ctx, VESIS_E_ARG, "rho_w, gamma0 >= 0, eps_m, eps_w, r2_min > 0 required");
+    if (!(p->rho_s > 1.0 && p->rho_s <= 3.0))
+        return fail(ctx, VESIS_E_ARG, "rho_s = delta/h must lie in (1, 3]");
+    if (p->far_nf < 1 || p->far_nf > 128 || p->far_ntau < 1 || p->far_ntau > 128)
+        return fail(ctx, VESIS_E_ARG, "far_nf, far_ntau must lie in [1, 128]");
+    if (p->precision != 32 && p->precision != 64)
+        return fail(ctx, VESIS_E_ARG, "precision must be 32 or 64");
+    const bool far_changed = !ctx->has_params || p->far_nf != ctx->prm.far_nf ||
+                             p->far_ntau != ctx->prm.far_ntau;
+    const bool rho_changed = !ctx->has_params || p->rho_w != ctx->prm.rho_w;
+    ctx->prm = *p;
+    ctx->has_params = true;
+    ctx->dens_valid = false;
+    if (rho_changed) ctx->atoms_uploaded = false;
+    if (ctx->has_grid) {
+        compute_stencil(ctx);
+        if (far_changed) {
+            compute_far_nodes(ctx);
+            ctx->has_ws = ctx->has_ws && ctx->lay_nfar == ctx->nfar;
+        }
+    }
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_grid(vesis_ctx* ctx, int32_t n, const double center[3], double h) {
+    if (!ctx || !center) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_params) return fail(ctx, VESIS_E_STATE, "parameters not set");
+    if (n < 4 || n > 1024) return fail(ctx, VESIS_E_ARG, "n must lie in [4, 1024]");
+    const double v[4] = {center[0], center[1], center[2], h};
+    if (!finite_all(v, 4)) return fail(ctx, VESIS_E_NONFINITE, "non-finite grid");
+    if (!(h > 0)) return fail(ctx, VESIS_E_ARG, "h must be positive");
+    Grid& g = ctx->g;
+    g.n = n;
+    g.nwin = (n + 31) / 32;
+    g.W = g.nwin + 2;
+    g.rdim = n + 4;
+    g.h = h;
+    g.L = 0.5 * (double)n * h;
+    g.cx = center[0];
+    g.cy = center[1];
+    g.cz = center[2];
+    g.x0 = (g.cx - g.L) + 0.5 * h;
+    g.y0 = (g.cy - g.L) + 0.5 * h;
+    g.z0 = (g.cz - g.L) + 0.5 * h;
+    ctx->has_grid = true;
+    compute_stencil(ctx);
+    compute_far_nodes(ctx);
+    ctx->has_ws = false;
+    ctx->has_labels = false;
+    ctx->dens_valid = false;
+    if (ctx->has_atoms && !inside_box(ctx, ctx->xyz.data(), ctx->na)) {
+        ctx->has_atoms = false;
+        return fail(ctx, VESIS_E_OUT_OF_BOX, "an atom lies outside the new box; set atoms again");
+    }
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_atoms(vesis_ctx* ctx, int64_t n, const double* xyz, const double* q,
+                             const double* sigma, const double* eps, const uint8_t* movable) {
+    if (!ctx || !xyz || !q || !sigma || !eps) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_grid) return fail(ctx, VESIS_E_STATE, "grid not set");
+    if (n < 1 || n > (1LL << 26)) return fail(ctx, VESIS_E_ARG, "atom count out of range");
+    if (!finite_all(xyz, 3 * n) || !finite_all(q, n) || !finite_all(sigma, n) || !finite_all(eps, n))
+        return fail(ctx, VESIS_E_NONFINITE, "non-finite atom data");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(sigma[i] > 0) || eps[i] < 0) return fail(ctx, VESIS_E_ARG, "sigma > 0, eps >= 0 required");
+    if (!inside_box(ctx, xyz, n)) return fail(ctx, VESIS_E_OUT_OF_BOX, "an atom lies outside the box");
+    if (n != ctx->na) {
+        ctx->has_ws = false;
+        ctx->nb = 0;
+        ctx->b_off.assign(n + 1, 0);
+        ctx->b_other.clear();
+        ctx->b_r0.clear();
+        ctx->b_k.clear();
+    }
+    ctx->na = n;
+    ctx->xyz.assign(xyz, xyz + 3 * n);
+    ctx->q.assign(q, q + n);
+    ctx->sigma.assign(sigma, sigma + n);
+    ctx->eps.assign(eps, eps + n);
+    ctx->movable.assign(n, 1);
+    if (movable)
+        for (int64_t i = 0; i < n; ++i) ctx->movable[i] = movable[i] ? 1 : 0;
+    if (ctx->b_off.size() != (size_t)(n + 1)) ctx->b_off.assign(n + 1, 0);
+    ctx->has_atoms = true;
+    ctx->atoms_uploaded = false;
+    ctx->bonds_uploaded = false;
+    ctx->dens_valid = false;
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_device) {
+    if (!ctx || !xyz) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    if (on_device) {
+        if (!ctx->has_ws) return fail(ctx, VESIS_E_WORKSPACE, "workspace not set");
+        vesis_status s = upload_inputs(ctx);
+        if (s != VESIS_OK) return s;
+        hipStream_t st = ctx->stream;
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.pos_stage, xyz, 24 * ctx->na, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(pack_positions, dim3((unsigned)((ctx->na + 255) / 256)), dim3(256), 0, st,
+                           at<double>(ctx, ctx->lay.pos_stage), ctx->na, at<double4>(ctx, ctx->lay.pos));
+        CK(hipGetLastError());
+        CK(hipMemcpyAsync(ctx->xyz.data(), ctx->ws + ctx->lay.pos_stage, 24 * ctx->na,
+                          hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        ctx->dens_valid = false;
+        return VESIS_OK;
+    }
+    if (!finite_all(xyz, 3 * ctx->na)) return fail(ctx, VESIS_E_NONFINITE, "non-finite positions");
+    if (!inside_box(ctx, xyz, ctx->na)) return fail(ctx, VESIS_E_OUT_OF_BOX, "an atom lies outside the box");
+    if (!ctx->has_ws || !ctx->atoms_uploaded) {
+        ctx->xyz.assign(xyz, xyz + 3 * ctx->na);
+        ctx->atoms_uploaded = false;
+        ctx->dens_valid = false;
+        return VESIS_OK;
+    }
+    return put_positions(ctx, xyz);
+}
+
+vesis_status vesis_get_positions(vesis_ctx* ctx, double* xyz) {
+    if (!ctx || !xyz) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    std::memcpy(xyz, ctx->xyz.data(), sizeof(double) * 3 * ctx->na);
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_bonds(vesis_ctx* ctx, int64_t nb, const int32_t* ij, const double* r0,
+                             const double* k) {
+    if (!ctx) return VESIS_E_ARG;
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    if (nb < 0 || (nb > 0 && (!ij || !r0 || !k))) return fail(ctx, VESIS_E_ARG, "bad bond arrays");
+    if (nb > 0 && (!finite_all(r0, nb) || !finite_all(k, nb)))
+        return fail(ctx, VESIS_E_NONFINITE, "non-finite bond data");
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t i = ij[2 * b], j = ij[2 * b + 1];
+        if (i < 0 || j < 0 || i >= ctx->na || j >= ctx->na || i == j)
+            return fail(ctx, VESIS_E_ARG, "bond atom index out of range");
+    }
+    const int64_t n = ctx->na;
+    std::vector<int32_t> deg(n + 1, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        deg[ij[2 * b]]++;
+        deg[ij[2 * b + 1]]++;
+    }
+    std::vector<int32_t> off(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + deg[i];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1), other(2 * nb);
+    std::vector<double> rr(2 * nb), kk(2 * nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t i = ij[2 * b], j = ij[2 * b + 1];
+        other[fill[i]] = j;
+        rr[fill[i]] = r0[b];
+        kk[fill[i]++] = k[b];
+        other[fill[j]] = i;
+        rr[fill[j]] = r0[b];
+        kk[fill[j]++] = k[b];
+    }
+    if (nb > ctx->lay_nb) ctx->has_ws = false;
+    ctx->nb = nb;
+    ctx->b_off = off;
+    ctx->b_other = other;
+    ctx->b_r0 = rr;
+    ctx->b_k = kk;
+    ctx->bonds_uploaded = false;
+    return VESIS_OK;
+}
+
+vesis_status vesis_workspace_size(vesis_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_params || !ctx->has_grid || !ctx->has_atoms)
+        return fail(ctx, VESIS_E_STATE, "params, grid and atoms must be set first");
+    *bytes = plan(ctx).total;
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_workspace(vesis_ctx* ctx, void* device_ptr, size_t bytes) {
+    if (!ctx || !device_ptr) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (!ctx->has_params || !ctx->has_grid || !ctx->has_atoms)
+        return fail(ctx, VESIS_E_STATE, "params, grid and atoms must be set first");
+    if (reinterpret_cast<uintptr_t>(device_ptr) & 255)
+        return fail(ctx, VESIS_E_ARG, "workspace must be 256-byte aligned");
+    const Layout L = plan(ctx);
+    if (bytes < L.total)
+        return fail(ctx, VESIS_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                                " bytes, got " + std::to_string(bytes));
+    const bool same = ctx->has_ws && ctx->ws == device_ptr && ctx->lay_n == ctx->g.n;
+    ctx->ws = static_cast<char*>(device_ptr);
+    ctx->ws_bytes = bytes;
+    ctx->lay = L;
+    ctx->lay_na = ctx->na;
+    ctx->lay_nb = ctx->nb;
+    ctx->lay_nfar = ctx->nfar;
+    ctx->lay_n = ctx->g.n;
+    ctx->has_ws = true;
+    ctx->atoms_uploaded = false;
+    ctx->bonds_uploaded = false;
+    ctx->far_uploaded = false;
+    ctx->dens_valid = false;
+    if (!same) ctx->has_labels = false;
+    return VESIS_OK;
+}
+
+vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const int8_t* user) {
+    if (!ctx) return VESIS_E_ARG;
+    vesis_status s = need(ctx, false);
+    if (s != VESIS_OK) return s;
+    if (mode < 0 || mode > 2) return fail(ctx, VESIS_E_ARG, "mode must be 0, 1 or 2");
+    if (mode != 2 && (!std::isfinite(param) || !(param > 0)))
+        return fail(ctx, VESIS_E_ARG, "param must be positive and finite");
+    if (mode == 2 && !user) return fail(ctx, VESIS_E_ARG, "user labels missing");
+    s = upload_inputs(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    const Grid& g = ctx->g;
+    uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
+    if (mode == 2) {
+        const int64_t nc = g.ncell();
+        for (int64_t c = 0; c < nc; ++c)
+            if (user[c] != 1 && user[c] != -1) return fail(ctx, VESIS_E_ARG, "labels must be -1 or +1");
+        std::vector<uint32_t> host(g.nwords(), 0xffffffffu);
+        for (int z = 0; z < g.n; ++z)
+            for (int y = 0; y < g.n; ++y)
+                for (int x = 0; x < g.n; ++x)
+                    if (user[x + (int64_t)g.n * (y + (int64_t)g.n * z)] == -1)
+                        host[g.row(y, z) + 1 + (x >> 5)] &= ~(1u << (x & 31));
+        CK(hipMemcpyAsync(bits, host.data(), 4 * host.size(), hipMemcpyHostToDevice, st));
+        CK(hipStreamSynchronize(st));
+    } else {
+        Timed t(ctx, K_INIT);
+        CK(launch_fill_u32(bits, g.nwords(), 0xffffffffu, st));
+        if (mode == 0)
+            CK(launch_init_loose(g, param, bits, st));
+        else
+            CK(launch_init_tight(g, dev_atoms(ctx), param, bits, st));
+    }
+    ctx->has_labels = true;
+    return VESIS_OK;
+}
+
+vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out) {
+    if (!ctx) return VESIS_E_ARG;
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    if (max_sweeps < 1) return fail(ctx, VESIS_E_ARG, "max_sweeps must be >= 1");
+    s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    const Atoms a = dev_atoms(ctx);
+    const Physics ph = dev_physics(ctx);
+    const int ncol = ctx->sc.p * ctx->sc.p * ctx->sc.p;
+    uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
+    int* flips = at<int>(ctx, ctx->lay.sweep_flips);
+    int64_t* counters = at<int64_t>(ctx, ctx->lay.scal_i) + SI_CNT;
+    CK(launch_fill_i64(counters, 2, 0, st));
+    int64_t total_flips = 0;
+    int sweeps = 0;
+    bool converged = false;
+    while (sweeps < max_sweeps && !converged) {
+        const int nb = std::min(SWEEP_BATCH, max_sweeps - sweeps);
+        CK(launch_fill_u32(reinterpret_cast<uint32_t*>(flips), SWEEP_BATCH, 0u, st));
+        {
+            Timed t(ctx, K_FLIP);
+            for (int sw = 0; sw < nb; ++sw)
+                for (int c = 0; c < ncol; ++c)
+                    CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw, bits,
+                                        at<double>(ctx, ctx->lay.ulj), at<double>(ctx, ctx->lay.ucfa),
+                                        at<double>(ctx, ctx->lay.bound),
+                                        at<double>(ctx, ctx->lay.u64cache), flips, counters, st));
+        }
+        int hf[SWEEP_BATCH];
+        CK(hipMemcpyAsync(hf, flips, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int sw = 0; sw < nb; ++sw) {
+            total_flips += hf[sw];
+            ++sweeps;
+            if (hf[sw] == 0) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    if (out) {
+        int64_t cnt[2] = {0, 0}, band = 0;
+        CK(launch_band_count(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,
+                             at<int64_t>(ctx, ctx->lay.scal_i) + SI_BAND, st));
+        CK(hipMemcpyAsync(cnt, counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        CK(hipMemcpyAsync(&band, ctx->ws + ctx->lay.scal_i + 8 * SI_BAND, sizeof(band),
+                          hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        out->sweeps = sweeps;
+        out->converged = converged ? 1 : 0;
+        out->flips = total_flips;
+        out->band_cells = band;
+        out->near_ties = cnt[0];
+        out->fp64_recomputes = cnt[1];
+    }
+    return converged ? VESIS_OK : VESIS_NOT_CONVERGED;
+}
+
+vesis_status vesis_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
+    if (!ctx || !out) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    return compute_energy(ctx, out);
+}
+
+vesis_status vesis_forces(vesis_ctx* ctx, double* f_out) {
+    if (!ctx || !f_out) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    return compute_forces(ctx, f_out);
+}
+
+vesis_status vesis_atom_step(vesis_ctx* ctx, vesis_mobility* st, vesis_step_info* info) {
+    if (!ctx || !st || !info) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    const double sv[6] = {st->M, st->alpha, st->dt, st->dG_frac, st->M_min, 0.0};
+    if (!finite_all(sv, 6) || !(st->M > 0) || !(st->alpha > 0 && st->alpha < 1) || !(st->dt > 0) ||
+        st->dG_frac < 0 || st->N_cnt_max < 0 || st->max_retries < 0)
+        return fail(ctx, VESIS_E_ARG, "bad mobility state");
+    const int64_t n = ctx->na;
+    vesis_energy_parts e{};
+    s = compute_energy(ctx, &e);
+    if (s != VESIS_OK) return s;
+    const double G_old = e.total;
+    std::vector<double> f(3 * n), R(ctx->xyz), trial(3 * n);
+    s = compute_forces(ctx, f.data());
+    if (s != VESIS_OK) return s;
+    double gmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!ctx->movable[i]) continue;
+        for (int d = 0; d < 3; ++d) gmax = std::max(gmax, std::fabs(f[3 * i + d]));
+    }
+    info->accepted = 0;
+    info->retries = 0;
+    info->G_old = G_old;
+    info->G_new = G_old;
+    info->max_grad = gmax;
+    info->omega = 0.0;
+    if (gmax == 0.0) {
+        st->G_old = G_old;
+        return fail(ctx, VESIS_NOT_CONVERGED, "zero gradient");
+    }
+    const double omega = 1.0 / gmax;
+    info->omega = omega;
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const double gr = -f[3 * i + d];
+                trial[3 * i + d] = ctx->movable[i] ? R[3 * i + d] - st->dt * omega * st->M * gr
+                                                   : R[3 * i + d];
+            }
+        s = put_positions(ctx, trial.data());
+        if (s != VESIS_OK) return s;
+        s = compute_energy(ctx, &e);
+        if (s != VESIS_OK) return s;
+        const double dG = e.total - G_old;
+        const double dGs = st->dG_frac * std::fabs(G_old);
+        const bool reject = (dG > dGs) || (st->N_cnt >= st->N_cnt_max && dG > 0.0 && dG <= dGs);
+        info->G_new = e.total;
+        if (!reject) {
+            st->N_cnt += 1;
+            st->k += 1;
+            st->G_old = e.total;
+            info->accepted = 1;
+            return VESIS_OK;
+        }
+        st->M *= st->alpha;
+        st->N_cnt = 0;
+        info->retries += 1;
+        if (st->M < st->M_min || info->retries > st->max_retries) {
+            st->G_old = G_old;
+            s = put_positions(ctx, R.data());
+            if (s != VESIS_OK) return s;
+            return fail(ctx, VESIS_NOT_CONVERGED, "mobility fell below M_min or retries ran out");
+        }
+    }
+}
+
+vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out) {
+    if (!ctx || !out) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    const Grid& g = ctx->g;
+    std::vector<uint32_t> host(g.nwords());
+    CK(hipMemcpyAsync(host.data(), ctx->ws + ctx->lay.bits, 4 * host.size(), hipMemcpyDeviceToHost,
+                      ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int z = 0; z < g.n; ++z)
+        for (int y = 0; y < g.n; ++y)
+            for (int x = 0; x < g.n; ++x)
+                out[x + (int64_t)g.n * (y + (int64_t)g.n * z)] =
+                    ((host[g.row(y, z) + 1 + (x >> 5)] >> (x & 31)) & 1u) ? 1 : -1;
+    return VESIS_OK;
+}
+
+vesis_status vesis_get_density(vesis_ctx* ctx, double* u_lj, double* u_cfa, double* bound) {
+    if (!ctx || !u_lj || !u_cfa) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, false);
+    if (s != VESIS_OK) return s;
+    s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    const size_t nb = 8 * (size_t)ctx->g.ncell();
+    CK(hipMemcpyAsync(u_lj, ctx->ws + ctx->lay.ulj, nb, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(u_cfa, ctx->ws + ctx->lay.ucfa, nb, hipMemcpyDeviceToHost, ctx->stream));
+    if (bound) CK(hipMemcpyAsync(bound, ctx->ws + ctx->lay.bound, nb, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return VESIS_OK;
+}
+
+vesis_status vesis_profile(vesis_ctx* ctx, int32_t enable) {
+    if (!ctx) return VESIS_E_ARG;
+    if (!ctx->pending.empty()) drain_events(ctx);
+    ctx->prof = enable != 0;
+    for (int k = 0; k < K_NKINDS; ++k) {
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_n[k] = 0;
+    }
+    return VESIS_OK;
+}
+
+vesis_status vesis_profile_read(vesis_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
+    if (!ctx || !total_ms || !launches) return fail(ctx, VESIS_E_ARG, "null argument");
+    if (kind < 0 || kind >= K_NKINDS) return fail(ctx, VESIS_E_ARG, "kind out of range");
+    drain_events(ctx);
+    *total_ms = ctx->prof_ms[kind];
+    *launches = ctx->prof_n[kind];
+    return VESIS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,407 @@
+// Energy density U over the cell grid and over far-field quadrature nodes.
+//
+// U(x) = rho_w sum_i 4 eps_i [(sigma_i/r)^12 - (sigma_i/r)^6]
+//        + Ccfa |sum_i Q_i (x - r_i) / r^3|^2,   r = |x - r_i|   (Eq. "Ur")
+//
+// The grid kernel is the hot loop of the method (the paper's grid-parallel
+// evaluation, Sec. "GPU Implementation"): every cell against every atom.
+// Layout on gfx950:
+//  * a workgroup of 256 lanes owns a 16 x 8 x 8 brick of cells, 4 cells per
+//    lane stacked along z, so the x/y part of each distance is shared by the
+//    lane's four cells;
+//  * atoms stream through LDS in tiles of 256: each lane stages one atom,
+//    rebased in FP64 to the brick centre and rounded to FP32 (cell offsets
+//    inside the brick are small, so the FP32 differences keep ~7 digits even
+//    for the nearest atoms); all four wavefronts then read the tile by LDS
+//    broadcast;
+//  * each tile's FP32 partial sums are folded into FP64 accumulators, so
+//    no FP32 sum runs over more than 256 terms;
+//  * beside U the kernel keeps the absolute sums sum 4 eps (s^6 + s^3) and
+//    sum |Q|/r^2 and the nearest squared distance, from which the epilogue
+//    writes a bound on |U_fp32 - U_exact| per cell; flip decisions inside
+//    that bound are redone in FP64.
+#include "internal.h"
+#include "reduce.h"
+
+namespace vesis {
+namespace {
+
+constexpr int DWG = 256;
+constexpr int BX = 16, BY = 8, BZ = 8, KC = 4;
+constexpr int TILE = 256;
+
+// Error-bound constants.  With the nearest atom at least 2h from the cell
+// centre (else the bound is +inf), the relative error of one FP32 pair term
+// is below ~300 u from coordinate rounding, rsqrt (1 ulp) and the s^6 power
+// chain, and a 256-term FP32 partial adds at most 255 u of the absolute sum;
+// 640 covers both with margin.  FP64 sums run over all atoms sequentially.
+constexpr double U32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
+constexpr double KAPPA32 = 640.0;
+
+__device__ inline double cell_bound(double kappa_u, double absLJ, double absE, double ex,
+                                    double ey, double ez, double ccfa, float rmin2,
+                                    float guard2) {
+    if (rmin2 < guard2) return INFINITY;
+    const double d = 1.7320508075688772 * kappa_u * absE * 1.001;  // |E_err| <= sqrt(3) k u A_E
+    const double emag = sqrt(ex * ex + ey * ey + ez * ez);
+    return kappa_u * absLJ * 1.001 + fabs(ccfa) * (2.0 * emag * d + d * d);
+}
+
+__global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics ph,
+                                                        CellFields out) {
+    __shared__ float4 spos[TILE];
+    __shared__ float4 sprm[TILE];
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = (t >> 4) & 7, tz = t >> 7;
+    const int nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int bz = b / nby;
+    const int i = bx * BX + tx, j = by * BY + ty, k0 = bz * BZ + tz * KC;
+
+    // brick centre in FP64; lane cell offsets from it in FP32
+    const double ox = g.x0 + (bx * BX + 0.5 * (BX - 1)) * g.h;
+    const double oy = g.y0 + (by * BY + 0.5 * (BY - 1)) * g.h;
+    const double oz = g.z0 + (bz * BZ + 0.5 * (BZ - 1)) * g.h;
+    const float cx = (float)((tx - 0.5 * (BX - 1)) * g.h);
+    const float cy = (float)((ty - 0.5 * (BY - 1)) * g.h);
+    float cz[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) cz[k] = (float)((tz * KC + k - 0.5 * (BZ - 1)) * g.h);
+
+    const float r2min = (float)ph.r2min;
+    double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dAE[KC];
+    float rmin[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        dP[k] = dQ[k] = dEx[k] = dEy[k] = dEz[k] = dAE[k] = 0.0;
+        rmin[k] = INFINITY;
+    }
+
+    for (int64_t base = 0; base < a.n; base += TILE) {
+        __syncthreads();
+        const int64_t ai = base + t;
+        if (ai < a.n) {
+            const double4 p = a.pos[ai];
+            const float4 q = a.prm32[ai];
+            spos[t] = make_float4((float)(p.x - ox), (float)(p.y - oy), (float)(p.z - oz), q.x);
+            sprm[t] = make_float4(q.y, q.z, q.w, 0.f);
+        } else {
+            spos[t] = make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
+            sprm[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
+        float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.f;
+#pragma unroll 2
+        for (int m = 0; m < cnt; ++m) {
+            const float4 p = spos[m];
+            const float4 q = sprm[m];
+            const float dx = cx - p.x, dy = cy - p.y;
+            const float dxy = fmaf(dx, dx, dy * dy);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const float dz = cz[k] - p.z;
+                float r2 = fmaf(dz, dz, dxy);
+                rmin[k] = fminf(rmin[k], r2);
+                r2 = fmaxf(r2, r2min);
+                const float ir = __builtin_amdgcn_rsqf(r2);
+                const float ir2 = ir * ir;
+                const float s = p.w * ir2;
+                const float s3 = s * s * s;
+                const float es3 = q.x * s3;
+                P[k] = fmaf(es3, s3, P[k]);
+                Q[k] += es3;
+                const float qr3 = q.y * (ir2 * ir);
+                Ex[k] = fmaf(qr3, dx, Ex[k]);
+                Ey[k] = fmaf(qr3, dy, Ey[k]);
+                Ez[k] = fmaf(qr3, dz, Ez[k]);
+                AE[k] = fmaf(q.z, ir2, AE[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            dP[k] += P[k];
+            dQ[k] += Q[k];
+            dEx[k] += Ex[k];
+            dEy[k] += Ey[k];
+            dEz[k] += Ez[k];
+            dAE[k] += AE[k];
+        }
+    }
+
+    if (i >= g.n || j >= g.n) return;
+    const float guard2 = (float)(4.0 * g.h * g.h);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int kk = k0 + k;
+        if (kk >= g.n) continue;
+        const int64_t c = (int64_t)i + (int64_t)g.n * (j + (int64_t)g.n * kk);
+        const double e2 = dEx[k] * dEx[k] + dEy[k] * dEy[k] + dEz[k] * dEz[k];
+        out.ulj[c] = dP[k] - dQ[k];
+        out.ucfa[c] = ph.ccfa * e2;
+        out.ex[c] = dEx[k];
+        out.ey[c] = dEy[k];
+        out.ez[c] = dEz[k];
+        out.bound[c] = cell_bound(KAPPA32 * U32, dP[k] + dQ[k], dAE[k], dEx[k], dEy[k], dEz[k],
+                                  ph.ccfa, rmin[k], guard2);
+    }
+}
+
+// FP64 variant: same brick and tiling, FP64 arithmetic and accumulation
+// throughout, correctly rounded sqrt and division.
+__global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics ph,
+                                                        CellFields out) {
+    __shared__ double4 spos[TILE];
+    __shared__ double4 sprm[TILE];
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = (t >> 4) & 7, tz = t >> 7;
+    const int nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int bz = b / nby;
+    const int i = bx * BX + tx, j = by * BY + ty, k0 = bz * BZ + tz * KC;
+    const double x = g.x0 + i * g.h, y = g.y0 + j * g.h;
+    double z[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) z[k] = g.z0 + (k0 + k) * g.h;
+
+    double P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC], rmin[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.0;
+        rmin[k] = INFINITY;
+    }
+    for (int64_t base = 0; base < a.n; base += TILE) {
+        __syncthreads();
+        const int64_t ai = base + t;
+        if (ai < a.n) {
+            const double4 p = a.pos[ai];
+            const double4 q = a.prm64[ai];
+            spos[t] = make_double4(p.x, p.y, p.z, q.x);
+            sprm[t] = make_double4(q.y, q.z, fabs(q.z), 0.0);
+        } else {
+            spos[t] = make_double4(1.0e6, 1.0e6, 1.0e6, 0.0);
+            sprm[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+        __syncthreads();
+        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
+        for (int m = 0; m < cnt; ++m) {
+            const double4 p = spos[m];
+            const double4 q = sprm[m];
+            const double dx = x - p.x, dy = y - p.y;
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const double dz = z[k] - p.z;
+                double r2 = dx * dx + dy * dy + dz * dz;
+                rmin[k] = fmin(rmin[k], r2);
+                r2 = fmax(r2, ph.r2min);
+                const double ir2 = 1.0 / r2;
+                const double ir = sqrt(ir2);
+                const double s = p.w * ir2;
+                const double s3 = s * s * s;
+                const double es3 = q.x * s3;
+                P[k] += es3 * s3;
+                Q[k] += es3;
+                const double qr3 = q.y * (ir2 * ir);
+                Ex[k] += qr3 * dx;
+                Ey[k] += qr3 * dy;
+                Ez[k] += qr3 * dz;
+                AE[k] += q.z * ir2;
+            }
+        }
+    }
+    if (i >= g.n || j >= g.n) return;
+    const double kappa = (double)a.n + 4096.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int kk = k0 + k;
+        if (kk >= g.n) continue;
+        const int64_t c = (int64_t)i + (int64_t)g.n * (j + (int64_t)g.n * kk);
+        out.ulj[c] = P[k] - Q[k];
+        out.ucfa[c] = ph.ccfa * (Ex[k] * Ex[k] + Ey[k] * Ey[k] + Ez[k] * Ez[k]);
+        out.ex[c] = Ex[k];
+        out.ey[c] = Ey[k];
+        out.ez[c] = Ez[k];
+        out.bound[c] = cell_bound(kappa * U64, P[k] + Q[k], AE[k], Ex[k], Ey[k], Ez[k], ph.ccfa,
+                                  (float)rmin[k], (float)(4.0 * g.h * g.h));
+    }
+}
+
+// Density at arbitrary points (far-field quadrature nodes): one point per
+// lane, atoms staged through LDS rebased to the block's first point.
+constexpr int PWG = 256;
+
+__global__ __launch_bounds__(PWG) void density_points_f32(const double4* pts, int64_t np,
+                                                          Atoms a, Physics ph, double* ulj,
+                                                          double* ucfa, double* ex, double* ey,
+                                                          double* ez) {
+    __shared__ float4 spos[TILE];
+    __shared__ float4 sprm[TILE];
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * PWG;
+    const int64_t pi = p0 + t;
+    const double4 o = pts[p0];
+    const double4 me = pts[pi < np ? pi : p0];
+    const float px = (float)(me.x - o.x), py = (float)(me.y - o.y), pz = (float)(me.z - o.z);
+    const float r2min = (float)ph.r2min;
+    double dP = 0, dQ = 0, dEx = 0, dEy = 0, dEz = 0;
+    for (int64_t base = 0; base < a.n; base += TILE) {
+        __syncthreads();
+        const int64_t ai = base + t;
+        if (ai < a.n) {
+            const double4 p = a.pos[ai];
+            const float4 q = a.prm32[ai];
+            spos[t] = make_float4((float)(p.x - o.x), (float)(p.y - o.y), (float)(p.z - o.z), q.x);
+            sprm[t] = make_float4(q.y, q.z, 0.f, 0.f);
+        } else {
+            spos[t] = make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
+            sprm[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
+        float P = 0.f, Q = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
+        for (int m = 0; m < cnt; ++m) {
+            const float4 p = spos[m];
+            const float4 q = sprm[m];
+            const float dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+            const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), r2min);
+            const float ir = __builtin_amdgcn_rsqf(r2);
+            const float ir2 = ir * ir;
+            const float s = p.w * ir2;
+            const float s3 = s * s * s;
+            const float es3 = q.x * s3;
+            P = fmaf(es3, s3, P);
+            Q += es3;
+            const float qr3 = q.y * (ir2 * ir);
+            Ex = fmaf(qr3, dx, Ex);
+            Ey = fmaf(qr3, dy, Ey);
+            Ez = fmaf(qr3, dz, Ez);
+        }
+        dP += P;
+        dQ += Q;
+        dEx += Ex;
+        dEy += Ey;
+        dEz += Ez;
+    }
+    if (pi >= np) return;
+    ulj[pi] = dP - dQ;
+    ucfa[pi] = ph.ccfa * (dEx * dEx + dEy * dEy + dEz * dEz);
+    ex[pi] = dEx;
+    ey[pi] = dEy;
+    ez[pi] = dEz;
+}
+
+__global__ __launch_bounds__(PWG) void density_points_f64(const double4* pts, int64_t np,
+                                                          Atoms a, Physics ph, double* ulj,
+                                                          double* ucfa, double* ex, double* ey,
+                                                          double* ez) {
+    __shared__ double4 spos[TILE];
+    __shared__ double2 sprm[TILE];
+    const int t = threadIdx.x;
+    const int64_t pi = (int64_t)blockIdx.x * PWG + t;
+    const double4 me = pts[pi < np ? pi : 0];
+    double P = 0, Q = 0, Ex = 0, Ey = 0, Ez = 0;
+    for (int64_t base = 0; base < a.n; base += TILE) {
+        __syncthreads();
+        const int64_t ai = base + t;
+        if (ai < a.n) {
+            const double4 p = a.pos[ai];
+            const double4 q = a.prm64[ai];
+            spos[t] = make_double4(p.x, p.y, p.z, q.x);
+            sprm[t] = make_double2(q.y, q.z);
+        } else {
+            spos[t] = make_double4(1.0e6, 1.0e6, 1.0e6, 0.0);
+            sprm[t] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
+        for (int m = 0; m < cnt; ++m) {
+            const double4 p = spos[m];
+            const double2 q = sprm[m];
+            const double dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+            const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
+            const double ir2 = 1.0 / r2;
+            const double ir = sqrt(ir2);
+            const double s = p.w * ir2;
+            const double s3 = s * s * s;
+            const double es3 = q.x * s3;
+            P += es3 * s3;
+            Q += es3;
+            const double qr3 = q.y * (ir2 * ir);
+            Ex += qr3 * dx;
+            Ey += qr3 * dy;
+            Ez += qr3 * dz;
+        }
+    }
+    if (pi >= np) return;
+    ulj[pi] = P - Q;
+    ucfa[pi] = ph.ccfa * (Ex * Ex + Ey * Ey + Ez * Ez);
+    ex[pi] = Ex;
+    ey[pi] = Ey;
+    ez[pi] = Ez;
+}
+
+// Deterministic two-level sum of w_p a_p and w_p b_p (w = pts[p].w).
+__global__ __launch_bounds__(RED_WG) void wsum2_stage1(const double4* pts, const double* a,
+                                                       const double* b, int64_t np,
+                                                       double* partial) {
+    __shared__ double sh[RED_WG];
+    double sa = 0.0, sb = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RED_WG;
+    for (int64_t p = (int64_t)blockIdx.x * RED_WG + threadIdx.x; p < np; p += stride) {
+        const double w = pts[p].w;
+        sa += w * a[p];
+        sb += w * b[p];
+    }
+    sa = block_sum(sa, sh);
+    sb = block_sum(sb, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sa;
+        partial[2 * blockIdx.x + 1] = sb;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph, int precision,
+                               CellFields out, hipStream_t st) {
+    const int nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY, nbz = (g.n + BZ - 1) / BZ;
+    const unsigned nblk = (unsigned)(nbx * nby * nbz);
+    if (precision == 64)
+        hipLaunchKernelGGL(density_grid_f64, dim3(nblk), dim3(DWG), 0, st, g, a, ph, out);
+    else
+        hipLaunchKernelGGL(density_grid_f32, dim3(nblk), dim3(DWG), 0, st, g, a, ph, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a, const Physics& ph,
+                                 int precision, double* ulj, double* ucfa, double* ex, double* ey,
+                                 double* ez, hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    const unsigned nblk = (unsigned)((np + PWG - 1) / PWG);
+    if (precision == 64)
+        hipLaunchKernelGGL(density_points_f64, dim3(nblk), dim3(PWG), 0, st, pts, np, a, ph, ulj,
+                           ucfa, ex, ey, ez);
+    else
+        hipLaunchKernelGGL(density_points_f32, dim3(nblk), dim3(PWG), 0, st, pts, np, a, ph, ulj,
+                           ucfa, ex, ey, ez);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum2(const double4* pts, const double* a, const double* b, int64_t np,
+                                double* partial, int nblocks, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(wsum2_stage1, dim3(nblocks), dim3(RED_WG), 0, st, pts, a, b, np, partial);
+    hipLaunchKernelGGL((reduce_partials<double, 2>), dim3(1), dim3(RED_WG), 0, st, partial, nblocks,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace vesis

@@ -1,0 +1,117 @@
+// Internal types shared by the HIP translation units of libvesis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vesis {
+
+// Cell grid and bit-packed label layout.
+//
+// Labels are one bit per cell, 1 = solvent (+1), 0 = solute (-1).  Every
+// x-row (fixed y, z) is `W` 32-bit words: word 0 is a padding word for
+// x in [-32, 0), words 1..nwin hold x in [0, n) (bits past n are padding),
+// word W-1 pads x >= 32 nwin.  Rows exist for y, z in [-2, n + 2); rows and
+// padding bits outside the box are all 1 (solvent) and never change, so a
+// 5x5x5 neighbourhood of any cell needs no bounds checks.
+struct Grid {
+    int n;        // cells per edge
+    int nwin;     // in-box words per row, ceil(n / 32)
+    int W;        // words per row, nwin + 2
+    int rdim;     // rows per edge including halo, n + 4
+    double h;     // cell edge
+    double x0, y0, z0;  // centre of cell (0, 0, 0)
+    double cx, cy, cz;  // box centre
+    double L;     // half edge
+
+    __host__ __device__ int64_t ncell() const { return (int64_t)n * n * n; }
+    __host__ __device__ int64_t nwords() const { return (int64_t)W * rdim * rdim; }
+    // index of the word holding bit x of row (y, z); x may be in [-32, 32 nwin + 32)
+    __host__ __device__ int64_t row(int y, int z) const {
+        return ((int64_t)(z + 2) * rdim + (y + 2)) * W;
+    }
+};
+
+// Surface-term constants: weight w[s] of squared offset s = 1..8
+// (w[s] = K(sqrt(s)/rho_s) inside the support, 0 outside), the prefactor
+// c = gamma0 C0 h^6 / delta^4, and the colour period p = ceil(rho_s).
+struct Stencil {
+    double w[9];
+    double c;
+    int p;
+};
+
+// Atom arrays on the device.
+struct Atoms {
+    int64_t n;
+    const double4* pos;   // x, y, z, 0
+    const double4* prm64; // sigma^2, 4 rho_w eps, Q, sigma
+    const float4* prm32;  // sigma^2, 4 rho_w eps, Q, |Q|
+};
+
+struct Physics {
+    double ccfa;     // CFA prefactor
+    double r2min;    // floor on r^2
+    double rho_w;
+    double h3;       // cell volume
+};
+
+// Per-cell outputs of the density kernel.
+struct CellFields {
+    double* ulj;
+    double* ucfa;
+    double* ex;
+    double* ey;
+    double* ez;
+    double* bound;   // bound on |U - U_exact| (U units); +inf forces FP64
+};
+
+enum KernelKind { K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6, K_NKINDS = 7 };
+
+// Launch wrappers (one per translation unit; all asynchronous on `st`).
+hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph, int precision,
+                               CellFields out, hipStream_t st);
+hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a, const Physics& ph,
+                                 int precision, double* ulj, double* ucfa, double* ex, double* ey,
+                                 double* ez, hipStream_t st);
+hipError_t launch_weighted_sum2(const double4* pts, const double* a, const double* b, int64_t np,
+                                double* partial, int nblocks, double* out, hipStream_t st);
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream_t st);
+hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
+                             hipStream_t st);
+hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
+                            int colour, int sweep, uint32_t* bits, const double* ulj,
+                            const double* ucfa, const double* bound, double* u64cache,
+                            int* sweep_flips, int64_t* counters, hipStream_t st);
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
+                                const double* ucfa, double* partial, int nblocks, double* out,
+                                hipStream_t st);
+hipError_t launch_geom_counts(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
+                              int64_t* out, hipStream_t st);
+hipError_t launch_band_count(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
+                             int64_t* out, hipStream_t st);
+
+struct Bonds {
+    int64_t nb;
+    const int32_t* off;     // CSR offsets per atom (n + 1)
+    const int32_t* other;   // partner atom per incidence
+    const double* r0;       // rest length per incidence
+    const double* k;        // constant per incidence
+};
+
+hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int precision,
+                         const uint32_t* bits, const double* ex, const double* ey,
+                         const double* ez, const double4* far_pts, const double* far_ex,
+                         const double* far_ey, const double* far_ez, int64_t nfar,
+                         const Bonds& bonds, double* partial, int64_t nchunk_cap,
+                         double* grad_out, hipStream_t st);
+int64_t force_partial_chunks(const Grid& g, int64_t natoms, int64_t nfar);
+
+hipError_t launch_bond_energy(const Atoms& a, const Bonds& bonds, double* partial, int nblocks,
+                              double* out, hipStream_t st);
+
+}  // namespace vesis

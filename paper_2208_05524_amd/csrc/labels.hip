@@ -1,0 +1,468 @@
+// Binary level set on the GPU: initial labels, colour flip passes, energy
+// reductions.  Labels are bit-packed (see Grid in internal.h).
+//
+// Flip pass (Eqs. "dGj1", "dGj2"; Step 2.2).  For one colour c = (a, b, cc)
+// only the x-rows with y = b (mod p), z = cc (mod p) hold candidates, and in
+// them the cells with x = a (mod p).  One lane owns one 32-cell word of such
+// a row: it forms the band mask of all 32 cells with a few shifts and XORs
+// (a cell is in the band when a face neighbour carries the other label),
+// keeps the colour-a cells, and for each candidate evaluates
+//     Delta E_j = phi_j (c S_j - h^3 U_j),  S_j = sum_{0<|o|<delta/h} phi_{j+o} K(|o|/rho_s)
+// (the two cases of the paper's flip energy in one expression).  S_j is
+// computed exactly as sum over squared offsets s of w_s * n_s with integer
+// counts n_s = #solvent - #solute, read from 5-bit windows of 25 neighbour
+// rows.  A candidate whose |Delta E| lies within h^3 times the density error
+// bound is a near tie: the wavefront recomputes U_j in FP64 (each lane a
+// strided share of the atoms, fixed butterfly sum), caches it, and decides.
+// Cells of one colour lie outside each other's kernel support, so all
+// decisions of a pass read only labels that the pass does not change.
+#include "internal.h"
+#include "reduce.h"
+
+namespace vesis {
+namespace {
+
+__global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void fill_f64(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void fill_i64(int64_t* p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// bits of a word for x = 32 w ... 32 w + 31 that lie inside the box
+__device__ inline uint32_t valid_mask(int n, int x0) {
+    const int m = n - x0;
+    return m >= 32 ? 0xffffffffu : ((1u << m) - 1u);
+}
+
+// bits b of the word starting at x0 with (x0 + b) mod p == a
+__device__ inline uint32_t colour_mask(int p, int a, int x0) {
+    uint32_t m = 0;
+    const int r = ((a - x0) % p + p) % p;
+    for (int b = r; b < 32; b += p) m |= 1u << b;
+    return m;
+}
+
+// Cell centre c - L + (i + 1/2) h per axis, the grid's definition, evaluated
+// without contraction so that label decisions on a sphere or a union of
+// spheres round exactly as the definition reads.
+__device__ inline double centre_coord(double c, double L, int i, double h) {
+#pragma clang fp contract(off)
+    return (c - L) + ((double)i + 0.5) * h;
+}
+
+// ---------------------------------------------------------------- init
+
+__global__ void init_loose_kernel(Grid g, double R0, uint32_t* bits) {
+#pragma clang fp contract(off)
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    if (tid >= total) return;
+    const int w = (int)(tid % g.nwin);
+    const int64_t r = tid / g.nwin;
+    const int y = (int)(r % g.n), z = (int)(r / g.n);
+    const double py = centre_coord(g.cy, g.L, y, g.h) - g.cy;
+    const double pz = centre_coord(g.cz, g.L, z, g.h) - g.cz;
+    uint32_t word = 0xffffffffu;
+    const int x0 = 32 * w;
+    for (int b = 0; b < 32 && x0 + b < g.n; ++b) {
+        const double px = centre_coord(g.cx, g.L, x0 + b, g.h) - g.cx;
+        if (sqrt(px * px + py * py + pz * pz) <= R0) word &= ~(1u << b);
+    }
+    bits[g.row(y, z) + 1 + w] = word;
+}
+
+// Tight surface: solute iff min_i (|x - r_i| - d_i) <= 0, d_i = scale sigma_i.
+// Atoms stream through LDS; an FP32 test against the word's 32-cell segment
+// skips atoms that cannot reach it, the rest are tested cell by cell in FP64.
+constexpr int IWG = 256;
+__global__ __launch_bounds__(IWG) void init_tight_kernel(Grid g, Atoms a, double scale,
+                                                         uint32_t* bits) {
+#pragma clang fp contract(off)
+    __shared__ double4 sat[IWG];
+    const int64_t tid = (int64_t)blockIdx.x * IWG + threadIdx.x;
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    const bool active = tid < total;
+    int w = 0, y = 0, z = 0;
+    if (active) {
+        w = (int)(tid % g.nwin);
+        const int64_t r = tid / g.nwin;
+        y = (int)(r % g.n);
+        z = (int)(r / g.n);
+    }
+    const int x0 = 32 * w;
+    const int xl = min(32, g.n - x0);
+    const double py = centre_coord(g.cy, g.L, y, g.h);
+    const double pz = centre_coord(g.cz, g.L, z, g.h);
+    const double xa = centre_coord(g.cx, g.L, x0, g.h);
+    const double xb = centre_coord(g.cx, g.L, x0 + xl - 1, g.h);
+    uint32_t solute = 0;
+    for (int64_t base = 0; base < a.n; base += IWG) {
+        __syncthreads();
+        const int64_t ai = base + threadIdx.x;
+        if (ai < a.n) {
+            const double4 p = a.pos[ai];
+            sat[threadIdx.x] = make_double4(p.x, p.y, p.z, scale * a.prm64[ai].w);
+        }
+        __syncthreads();
+        const int cnt = (int)((a.n - base) < IWG ? (a.n - base) : IWG);
+        if (!active) continue;
+        for (int m = 0; m < cnt; ++m) {
+            const double4 p = sat[m];
+            const double dy = py - p.y, dz = pz - p.z;
+            const double ex = p.x < xa ? xa - p.x : (p.x > xb ? p.x - xb : 0.0);
+            const double d2 = ex * ex + dy * dy + dz * dz;
+            const double lim = p.w * (1.0 + 1e-9) + 1e-12;
+            if (d2 > lim * lim) continue;
+            for (int b = 0; b < xl; ++b) {
+                const double dx = centre_coord(g.cx, g.L, x0 + b, g.h) - p.x;
+                if (sqrt(dx * dx + dy * dy + dz * dz) - p.w <= 0.0) solute |= 1u << b;
+            }
+        }
+    }
+    if (active) bits[g.row(y, z) + 1 + w] = ~solute;  // padding bits past n stay 1
+}
+
+// ------------------------------------------------------------- stencil
+
+// 5-bit window of row `r` at x-2 .. x+2 (bit 0 = x-2, bit 2 = x).
+__device__ inline uint32_t window5(const uint32_t* r, int x) {
+    const int gbit = x + 30;  // word 0 covers x in [-32, 0)
+    const int lo = gbit >> 5, sh = gbit & 31;
+    uint32_t v = r[lo] >> sh;
+    if (sh > 27) v |= r[lo + 1] << (32 - sh);
+    return v & 31u;
+}
+
+// S_j = sum over offsets 0 < |o|^2 <= 8 of w_{|o|^2} phi_{j+o}, via integer
+// counts per squared offset.
+__device__ inline double stencil_sum(const Grid& g, const Stencil& sc, const uint32_t* bits,
+                                     int x, int y, int z) {
+    int net[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) net[s] = 0;
+#pragma unroll
+    for (int dz = -2; dz <= 2; ++dz) {
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            const int q = dy * dy + dz * dz;
+            if (q > 8) continue;
+            const uint32_t v = window5(bits + g.row(y + dy, z + dz), x);
+            if (q > 0) net[q] += ((v >> 2) & 1u) ? 1 : -1;
+            if (q + 1 <= 8) net[q + 1] += 2 * __popc(v & 0xAu) - 2;
+            if (q + 4 <= 8) net[q + 4] += 2 * __popc(v & 0x11u) - 2;
+        }
+    }
+    double S = 0.0;
+#pragma unroll
+    for (int s = 1; s <= 8; ++s) S += sc.w[s] * (double)net[s];
+    return S;
+}
+
+// FP64 density at cell (x, y, z), summed by one wavefront: lane l takes atoms
+// l, l + 64, ...; the partial sums meet in a fixed xor butterfly, so every
+// lane ends with the same bits.
+__device__ inline double wave_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
+                                          int y, int z) {
+    const int lane = threadIdx.x & 63;
+    const double px = centre_coord(g.cx, g.L, x, g.h);
+    const double py = centre_coord(g.cy, g.L, y, g.h);
+    const double pz = centre_coord(g.cz, g.L, z, g.h);
+    double lj = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+    for (int64_t i = lane; i < a.n; i += 64) {
+        const double4 p = a.pos[i];
+        const double4 q = a.prm64[i];
+        const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+        const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
+        const double ir2 = 1.0 / r2;
+        const double ir = sqrt(ir2);
+        const double s = q.x * ir2;
+        const double s3 = s * s * s;
+        lj += q.y * (s3 * s3 - s3);
+        const double f = q.z * ir2 * ir;
+        ex += f * dx;
+        ey += f * dy;
+        ez += f * dz;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lj += __shfl_xor(lj, off);
+        ex += __shfl_xor(ex, off);
+        ey += __shfl_xor(ey, off);
+        ez += __shfl_xor(ez, off);
+    }
+    return lj + ph.ccfa * (ex * ex + ey * ey + ez * ez);
+}
+
+// --------------------------------------------------------------- flip pass
+
+constexpr int FWG = 64;  // one wavefront per workgroup
+
+__global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atoms a, Physics ph,
+                                                        int colour, int sweep, uint32_t* bits,
+                                                        const double* ulj, const double* ucfa,
+                                                        const double* bound, double* u64cache,
+                                                        int* sweep_flips, int64_t* counters) {
+    // a sweep that follows a sweep without flips has nothing to do
+    if (sweep > 0 && sweep_flips[sweep - 1] == 0) return;
+    const int p = sc.p;
+    const int ca = colour % p, cb = (colour / p) % p, cc = colour / (p * p);
+    const int ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
+    const int64_t total = (int64_t)g.nwin * ny * nz;
+    const int64_t tid = (int64_t)blockIdx.x * FWG + threadIdx.x;
+    const bool active = tid < total;
+    int w = 0, y = 0, z = 0;
+    if (active) {
+        w = (int)(tid % g.nwin);
+        const int64_t r = tid / g.nwin;
+        y = cb + p * (int)(r % ny);
+        z = cc + p * (int)(r / ny);
+    }
+    const int x0 = 32 * w;
+    uint32_t* rowc = bits + g.row(y, z);
+    uint32_t C = 0, cand = 0;
+    if (active) {
+        C = rowc[w + 1];
+        const uint32_t Lw = rowc[w], Rw = rowc[w + 2];
+        const uint32_t left = (C << 1) | (Lw >> 31);
+        const uint32_t right = (C >> 1) | (Rw << 31);
+        const uint32_t ym = bits[g.row(y - 1, z) + w + 1], yp = bits[g.row(y + 1, z) + w + 1];
+        const uint32_t zm = bits[g.row(y, z - 1) + w + 1], zp = bits[g.row(y, z + 1) + w + 1];
+        const uint32_t band = (C ^ left) | (C ^ right) | (C ^ ym) | (C ^ yp) | (C ^ zm) | (C ^ zp);
+        cand = band & colour_mask(p, ca, x0) & valid_mask(g.n, x0);
+    }
+    uint32_t flipmask = 0, tiemask = 0;
+    while (cand) {
+        const int b = __ffs(cand) - 1;
+        cand &= cand - 1;
+        const int x = x0 + b;
+        const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
+        const double S = stencil_sum(g, sc, bits, x, y, z);
+        const double phi = ((C >> b) & 1u) ? 1.0 : -1.0;
+        const double hU = ph.h3 * (ulj[c] + ucfa[c]);
+        const double cS = sc.c * S;
+        const double dE = phi * (cS - hU);
+        const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
+        if (!(fabs(dE) > tol))
+            tiemask |= 1u << b;
+        else if (dE < 0.0)
+            flipmask |= 1u << b;
+    }
+    // near ties: the whole wavefront resolves them one at a time in FP64
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const uint64_t bal = __ballot(tiemask != 0u);
+        if (bal == 0) break;
+        const int leader = __ffsll((unsigned long long)bal) - 1;
+        const int lb = tiemask ? __ffs(tiemask) - 1 : 0;
+        const int bL = __shfl(lb, leader);
+        const int xL = __shfl(x0, leader) + bL;
+        const int yL = __shfl(y, leader);
+        const int zL = __shfl(z, leader);
+        const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
+        double u64 = u64cache[cL];
+        if (isnan(u64)) {
+            u64 = wave_density_f64(g, a, ph, xL, yL, zL);
+            if (lane == leader) {
+                u64cache[cL] = u64;
+                atomicAdd((unsigned long long*)&counters[1], 1ull);
+            }
+        }
+        if (lane == leader) {
+            const double S = stencil_sum(g, sc, bits, xL, yL, zL);
+            const double phi = ((C >> bL) & 1u) ? 1.0 : -1.0;
+            const double dE = phi * (sc.c * S - ph.h3 * u64);
+            if (dE < 0.0) flipmask |= 1u << bL;
+            tiemask &= ~(1u << bL);
+            atomicAdd((unsigned long long*)&counters[0], 1ull);
+        }
+    }
+    if (flipmask) rowc[w + 1] = C ^ flipmask;
+    int nf = __popc(flipmask);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nf += __shfl_xor(nf, off);
+    if (lane == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
+}
+
+// ------------------------------------------------------------ reductions
+
+// h^3-less sums of U_LJ and U_CFA over solvent cells (FP64).
+__global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uint32_t* bits,
+                                                               const double* ulj,
+                                                               const double* ucfa,
+                                                               double* partial) {
+    __shared__ double sh[RED_WG];
+    double sa = 0.0, sb = 0.0;
+    const int64_t ncell = g.ncell();
+    const int64_t stride = (int64_t)gridDim.x * RED_WG;
+    for (int64_t c = (int64_t)blockIdx.x * RED_WG + threadIdx.x; c < ncell; c += stride) {
+        const int x = (int)(c % g.n);
+        const int64_t r = c / g.n;
+        const int y = (int)(r % g.n), z = (int)(r / g.n);
+        const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
+        if ((word >> (x & 31)) & 1u) {
+            sa += ulj[c];
+            sb += ucfa[c];
+        }
+    }
+    sa = block_sum(sa, sh);
+    sb = block_sum(sb, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sa;
+        partial[2 * blockIdx.x + 1] = sb;
+    }
+}
+
+// T_s = number of (solute j, solvent k) pairs with |x_k - x_j|^2 = s h^2,
+// s = 1..8, bit-parallel over the 32 cells of a word.
+__global__ __launch_bounds__(RED_WG) void geom_counts_kernel(Grid g, const uint32_t* bits,
+                                                             int64_t* partial) {
+    __shared__ int64_t sh[RED_WG];
+    int64_t cnt[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) cnt[s] = 0;
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    const int64_t stride = (int64_t)gridDim.x * RED_WG;
+    for (int64_t tid = (int64_t)blockIdx.x * RED_WG + threadIdx.x; tid < total; tid += stride) {
+        const int w = (int)(tid % g.nwin);
+        const int64_t r = tid / g.nwin;
+        const int y = (int)(r % g.n), z = (int)(r / g.n);
+        const uint32_t C = bits[g.row(y, z) + 1 + w];
+        const uint32_t m = ~C & valid_mask(g.n, 32 * w);
+        if (!m) continue;
+#pragma unroll
+        for (int dz = -2; dz <= 2; ++dz) {
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+                const int q = dy * dy + dz * dz;
+                if (q > 8) continue;
+                const uint32_t* rr = bits + g.row(y + dy, z + dz) + w;
+                const uint32_t L = rr[0], Cn = rr[1], R = rr[2];
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int s = q + dx * dx;
+                    if (s == 0 || s > 8) continue;
+                    uint32_t nb;
+                    if (dx > 0)
+                        nb = (Cn >> dx) | (R << (32 - dx));
+                    else if (dx < 0)
+                        nb = (Cn << (-dx)) | (L >> (32 + dx));
+                    else
+                        nb = Cn;
+                    cnt[s] += __popc(m & nb);
+                }
+            }
+        }
+    }
+    for (int s = 1; s <= 8; ++s) {
+        const int64_t v = block_sum(cnt[s], sh);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * 8 + (s - 1)] = v;
+    }
+}
+
+// number of band cells (face neighbour with the other label)
+__global__ __launch_bounds__(RED_WG) void band_count_kernel(Grid g, const uint32_t* bits,
+                                                            int64_t* partial) {
+    __shared__ int64_t sh[RED_WG];
+    int64_t cnt = 0;
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    const int64_t stride = (int64_t)gridDim.x * RED_WG;
+    for (int64_t tid = (int64_t)blockIdx.x * RED_WG + threadIdx.x; tid < total; tid += stride) {
+        const int w = (int)(tid % g.nwin);
+        const int64_t r = tid / g.nwin;
+        const int y = (int)(r % g.n), z = (int)(r / g.n);
+        const uint32_t* rc = bits + g.row(y, z);
+        const uint32_t C = rc[w + 1];
+        const uint32_t left = (C << 1) | (rc[w] >> 31);
+        const uint32_t right = (C >> 1) | (rc[w + 2] << 31);
+        const uint32_t band = (C ^ left) | (C ^ right) | (C ^ bits[g.row(y - 1, z) + w + 1]) |
+                              (C ^ bits[g.row(y + 1, z) + w + 1]) |
+                              (C ^ bits[g.row(y, z - 1) + w + 1]) |
+                              (C ^ bits[g.row(y, z + 1) + w + 1]);
+        cnt += __popc(band & valid_mask(g.n, 32 * w));
+    }
+    cnt = block_sum(cnt, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = cnt;
+}
+
+inline unsigned nblk(int64_t n, int wg) { return (unsigned)((n + wg - 1) / wg); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream_t st) {
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    hipLaunchKernelGGL(init_loose_kernel, dim3(nblk(total, 256)), dim3(256), 0, st, g, R0, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
+                             hipStream_t st) {
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    hipLaunchKernelGGL(init_tight_kernel, dim3(nblk(total, IWG)), dim3(IWG), 0, st, g, a, scale,
+                       bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
+                            int colour, int sweep, uint32_t* bits, const double* ulj,
+                            const double* ucfa, const double* bound, double* u64cache,
+                            int* sweep_flips, int64_t* counters, hipStream_t st) {
+    const int p = sc.p;
+    const int cb = (colour / p) % p, cc = colour / (p * p);
+    const int64_t ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
+    const int64_t total = (int64_t)g.nwin * ny * nz;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(flip_pass_kernel, dim3(nblk(total, FWG)), dim3(FWG), 0, st, g, sc, a, ph,
+                       colour, sweep, bits, ulj, ucfa, bound, u64cache, sweep_flips, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
+                                const double* ucfa, double* partial, int nblocks, double* out,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(energy_volume_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, ulj,
+                       ucfa, partial);
+    hipLaunchKernelGGL((reduce_partials<double, 2>), dim3(1), dim3(RED_WG), 0, st, partial,
+                       nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_geom_counts(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
+                              int64_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(geom_counts_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, partial);
+    hipLaunchKernelGGL((reduce_partials<int64_t, 8>), dim3(1), dim3(RED_WG), 0, st, partial,
+                       nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_count(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
+                             int64_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(band_count_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, partial);
+    hipLaunchKernelGGL((reduce_partials<int64_t, 1>), dim3(1), dim3(RED_WG), 0, st, partial,
+                       nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace vesis

@@ -1,0 +1,190 @@
+"""Python binding of libvesis (the MI355X VESIS hot path).
+
+Argument marshalling only.  PyTorch provides the device workspace (one uint8
+tensor) and the stream (the current torch stream of the device); every step
+of the method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import EnergyParts, MinStats, Mobility, Params, StepInfo, VesisError
+
+KERNEL_KINDS = {"density": 0, "far_field": 1, "init": 2, "flip": 3, "energy": 4, "force": 5,
+                "other": 6}
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def default_mobility(dt: float = 0.1) -> Mobility:
+    """M = 1, alpha = 1/sqrt 2, N_cnt* = 5, delta G* = 5 % (the paper's choices)."""
+    return Mobility(M=1.0, alpha=2.0 ** -0.5, dt=dt, dG_frac=0.05, M_min=1e-12, G_old=0.0,
+                    N_cnt=0, N_cnt_max=5, k=0, max_retries=200)
+
+
+class Context:
+    """One molecule on one grid on one GPU."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self._torch = torch
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = self.lib.vesis_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise VesisError(rc, "vesis_create failed")
+        self.h = h
+        self.workspace = None
+        self.n = 0
+        self.natoms = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vesis_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(0,)):
+        if rc not in allow:
+            msg = self.lib.vesis_last_error(self.h)
+            raise VesisError(rc, msg.decode() if msg else "")
+        return rc
+
+    # ------------------------------------------------------------ set-up
+    def set_params(self, p, precision: int = 32):
+        prm = Params(rho_w=p.rho_w, gamma0=p.gamma0, eps_m=p.eps_m, eps_w=p.eps_w,
+                     coulomb_k=p.coulomb_k, rho_s=p.rho_s, r2_min=p.r2_min, far_nf=p.far_nf,
+                     far_ntau=p.far_ntau, precision=precision, reserved=0)
+        self._check(self.lib.vesis_set_params(self.h, C.byref(prm)))
+
+    def set_grid(self, n: int, center, h: float):
+        c = _f64(center, (3,))
+        self._check(self.lib.vesis_set_grid(self.h, int(n), _ptr(c), float(h)))
+        self.n = int(n)
+
+    def set_atoms(self, xyz, q, sigma, eps, movable=None):
+        xyz = _f64(xyz, (-1, 3))
+        na = xyz.shape[0]
+        mv = None if movable is None else np.ascontiguousarray(movable, dtype=np.uint8)
+        self._check(self.lib.vesis_set_atoms(self.h, na, _ptr(xyz), _ptr(_f64(q)),
+                                             _ptr(_f64(sigma)), _ptr(_f64(eps)), _ptr(mv)))
+        self.natoms = na
+
+    def set_bonds(self, ij, r0, k):
+        ij = np.ascontiguousarray(ij, dtype=np.int32).reshape(-1, 2)
+        self._check(self.lib.vesis_set_bonds(self.h, ij.shape[0], _ptr(ij), _ptr(_f64(r0)),
+                                             _ptr(_f64(k))))
+
+    def set_positions(self, xyz):
+        """Host array (n x 3) or a CUDA float64 tensor of n x 3 (device copy)."""
+        t = self._torch
+        if isinstance(xyz, t.Tensor):
+            assert xyz.is_cuda and xyz.dtype == t.float64 and xyz.is_contiguous()
+            self._check(self.lib.vesis_set_positions(self.h, C.c_void_p(xyz.data_ptr()), 1))
+        else:
+            a = _f64(xyz, (-1, 3))
+            self._check(self.lib.vesis_set_positions(self.h, _ptr(a), 0))
+
+    def positions(self) -> np.ndarray:
+        out = np.zeros((self.natoms, 3))
+        self._check(self.lib.vesis_get_positions(self.h, _ptr(out)))
+        return out
+
+    def workspace_size(self) -> int:
+        n = C.c_size_t()
+        self._check(self.lib.vesis_workspace_size(self.h, C.byref(n)))
+        return int(n.value)
+
+    def allocate_workspace(self):
+        t = self._torch
+        nbytes = self.workspace_size()
+        self.workspace = t.empty(nbytes + 256, dtype=t.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(self.lib.vesis_set_workspace(self.h, C.c_void_p(aligned), nbytes))
+        return nbytes
+
+    def setup(self, w, precision=None, with_bonds: bool = False):
+        """Params, grid, atoms (and bonds) of a ``synth.Workload``, then workspace."""
+        self.set_params(w.params, precision if precision is not None else w.precision)
+        self.set_grid(w.n, w.center, w.h)
+        self.set_atoms(w.xyz, w.q, w.sigma, w.eps)
+        if with_bonds and len(w.bonds):
+            self.set_bonds(w.bonds, w.bond_r0, w.bond_k)
+        self.allocate_workspace()
+        return self
+
+    # ------------------------------------------------------------ operations
+    def init_labels(self, mode: str, param: float = 1.0, user=None):
+        m = {"loose": 0, "tight": 1, "user": 2}[mode]
+        u = None if user is None else np.ascontiguousarray(user, dtype=np.int8)
+        self._check(self.lib.vesis_init_labels(self.h, m, float(param), _ptr(u)))
+
+    def minimize(self, max_sweeps: int = 20000):
+        st = MinStats()
+        rc = self._check(self.lib.vesis_minimize_interface(self.h, int(max_sweeps), C.byref(st)),
+                         allow=(0, 1))
+        return rc, dict(sweeps=st.sweeps, converged=st.converged, flips=st.flips,
+                        band=st.band_cells, near_ties=st.near_ties,
+                        fp64_recomputes=st.fp64_recomputes)
+
+    def energy(self) -> dict:
+        e = EnergyParts()
+        self._check(self.lib.vesis_energy(self.h, C.byref(e)))
+        return {k: getattr(e, k) for k, _ in EnergyParts._fields_}
+
+    def forces(self) -> np.ndarray:
+        f = np.zeros((self.natoms, 3))
+        self._check(self.lib.vesis_forces(self.h, _ptr(f)))
+        return f
+
+    def atom_step(self, mobility: Mobility):
+        info = StepInfo()
+        rc = self._check(self.lib.vesis_atom_step(self.h, C.byref(mobility), C.byref(info)),
+                         allow=(0, 1))
+        return rc, info
+
+    def labels(self) -> np.ndarray:
+        out = np.zeros(self.n ** 3, np.int8)
+        self._check(self.lib.vesis_get_labels(self.h, _ptr(out)))
+        return out
+
+    def density(self, with_bound: bool = False):
+        m = self.n ** 3
+        a = np.zeros(m)
+        b = np.zeros(m)
+        c = np.zeros(m) if with_bound else None
+        self._check(self.lib.vesis_get_density(self.h, _ptr(a), _ptr(b), _ptr(c)))
+        return (a, b, c) if with_bound else (a, b)
+
+    def profile(self, enable: bool = True):
+        self._check(self.lib.vesis_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kind: str):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.vesis_profile_read(self.h, KERNEL_KINDS[kind], C.byref(ms),
+                                                C.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,56 @@
+"""Shared helpers of the GPU tests: build a GPU context and the matching
+oracle system from one seeded workload."""
+from __future__ import annotations
+
+import functools
+import sys
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_context(w, precision=None, with_bonds=False):
+    from paper_2208_05524_amd import Context
+    ctx = Context(0)
+    ctx.setup(w, precision=precision, with_bonds=with_bonds)
+    return ctx
+
+
+def oracle_system(w, with_bonds=False):
+    return oracle.System.from_workload(w, with_bonds=with_bonds)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_density(key, w_factory):
+    w = w_factory()
+    s = oracle_system(w)
+    ulj, ucfa = s.density_grid()
+    far = s.far_field()
+    return ulj, ucfa, far
+
+
+def energies_close(a: dict, b: dict, rel: float, keys=("geom", "vdw_in", "vdw_far", "elec_in",
+                                                       "elec_far", "total")):
+    scale = max(abs(a["total"]), 1e-30)
+    bad = {k: (a[k], b[k]) for k in keys if abs(a[k] - b[k]) > rel * scale}
+    return bad
+
+
+def ragged_small(seed=5, n=40, natoms=300, charged=True, h=0.06):
+    return synth.random_small(n, natoms, seed, h=h, charged=charged)
+
+
+def force_close(fg, fo, rel=1e-4):
+    """||dF_n|| <= rel * max(||F_n||, 1e-3 max_m ||F_m||) for every atom."""
+    nrm = np.linalg.norm(fo, axis=1)
+    floor = 1e-3 * nrm.max()
+    err = np.linalg.norm(fg - fo, axis=1)
+    lim = rel * np.maximum(nrm, floor)
+    return err <= lim, err / np.maximum(nrm, floor)
