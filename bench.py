@@ -69,7 +69,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU kernel set "
               "(the multi-GPU sharding is described, not built); run with --gpus 1",
@@ -161,6 +172,8 @@ def main():
         "sweeps": last["st"]["sweeps"],
         "flips": last["st"]["flips"],
         "near_ties": last["st"]["near_ties"],
+        "fp64_recomputes": last["st"]["fp64_recomputes"],
+        "atom_step": {"accepted": last["accepted"], "retries": last["retries"]},
         "G_total": last["e"]["total"],
     }
     if not args.no_cpu_baseline:

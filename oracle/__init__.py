@@ -94,6 +94,7 @@ def lib():
         L.orc_init_loose.argtypes = [sp, _D, _P]
         L.orc_init_tight.argtypes = [sp, _P, _P]
         L.orc_forces.argtypes = [sp, _P, _I64, _P, _P, _P, _P]
+        L.orc_forces_subset.argtypes = [sp, _P, _P, _I64, _P, _I64, _P, _P, _P, _P]
         L.orc_total_energy.argtypes = [sp, _P, _I64, _P, _P, _P, _P]
         L.orc_total_energy.restype = _D
         L.orc_atom_step.argtypes = [sp, _P, _P, _P, _I64, _P, _P, _P, C.POINTER(Mobility),
@@ -290,6 +291,17 @@ class System:
         f = np.zeros((self.xyz.shape[0], 3))
         lib().orc_forces(self.sref, _ptr(phi), len(self.bonds), _ptr(self.bonds),
                          _ptr(self.bond_r0), _ptr(self.bond_k), _ptr(f))
+        return f
+
+    def forces_subset(self, phi, efield, sel) -> np.ndarray:
+        """Forces on atoms `sel` given the grid field E (ncell x 3)."""
+        phi = np.ascontiguousarray(phi, dtype=np.int8)
+        e = np.ascontiguousarray(efield, dtype=np.float64)
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        f = np.zeros((len(sel), 3))
+        lib().orc_forces_subset(self.sref, _ptr(phi), _ptr(e), len(sel), _ptr(sel),
+                                len(self.bonds), _ptr(self.bonds), _ptr(self.bond_r0),
+                                _ptr(self.bond_k), _ptr(f))
         return f
 
     def total_energy(self, phi):

@@ -8,8 +8,8 @@
  * the HIP path.  Every function below states the passage of the paper it
  * writes out.  Loops are the definitions themselves: no blocking, no fusion,
  * no reordering beyond what the definition states.  OpenMP is used only
- * across independent cells or atoms; every sum is a sequential FP64 sum in
- * index order.
+ * across independent cells or atoms; every sum is an FP64 sum in a fixed
+ * order (index order, or per z-plane and then the planes in order).
  *
  * Readings of the paper taken here (the paper is silent or garbled at these
  * points):
@@ -258,8 +258,12 @@ double orc_geom_energy(const orc_sys* s, const int8_t* phi) {
     int64_t n = s->n;
     double h = s->h, delta = s->rho_s * s->h;
     int R = (int)ceil(s->rho_s);
-    double sum = 0.0;
-    for (int64_t k = 0; k < n; ++k)
+    /* one sequential partial sum per z-plane (planes in parallel), then the
+     * planes in order: a fixed summation order */
+    double* plane = calloc((size_t)n, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n; ++k) {
+        double sum = 0.0;
         for (int64_t j = 0; j < n; ++j)
             for (int64_t i = 0; i < n; ++i) {
                 if (phi[i + n * (j + n * k)] != -1) continue;
@@ -272,6 +276,11 @@ double orc_geom_energy(const orc_sys* s, const int8_t* phi) {
                                 sum += kernel_K(d / delta);
                         }
             }
+        plane[k] = sum;
+    }
+    double sum = 0.0;
+    for (int64_t k = 0; k < n; ++k) sum += plane[k];
+    free(plane);
     return orc_surface_prefactor(s) * sum;
 }
 
@@ -562,6 +571,10 @@ void orc_init_tight(const orc_sys* s, const double* d, int8_t* phi) {
         for (int64_t i = 0; i < s->na; ++i) {
             double dx = x[0] - s->xyz[3 * i], dy = x[1] - s->xyz[3 * i + 1],
                    dz = x[2] - s->xyz[3 * i + 2];
+            /* |dx| > d_i already gives |x - r_i| - d_i > 0: such an atom
+             * cannot make the minimum non-positive, so only the sign of the
+             * minimum (all that the label uses) is computed exactly */
+            if (fabs(dx) > d[i]) continue;
             double v = sqrt(dx * dx + dy * dy + dz * dz) - d[i];
             if (v < vmin) vmin = v;
         }
@@ -654,6 +667,58 @@ void orc_forces(const orc_sys* s, const int8_t* phi, int64_t nb, const int32_t* 
         f[3 * j + 0] += c * dx; f[3 * j + 1] += c * dy; f[3 * j + 2] += c * dz;
     }
     free(pts); free(w); free(e); free(tmp);
+}
+
+/* Forces on the atoms listed in sel (nsel of them) at fixed labels, given
+ * the field E on every grid cell (ncell x 3, e.g. from orc_density_grid):
+ * the same sum as orc_forces restricted to those atoms, for large grids where
+ * only a sample of atoms is checked.  f is nsel x 3. */
+void orc_forces_subset(const orc_sys* s, const int8_t* phi, const double* efield, int64_t nsel,
+                       const int64_t* sel, int64_t nb, const int32_t* ij, const double* r0,
+                       const double* kb, double* f) {
+    int64_t ncell = (int64_t)s->n * s->n * s->n;
+    double h3 = s->h * s->h * s->h, ccfa = orc_cfa_prefactor(s);
+    int64_t nfar = 6LL * s->far_nf * s->far_nf * s->far_ntau;
+    double* fpts = malloc(sizeof(double) * 3 * (size_t)nfar);
+    double* fw = malloc(sizeof(double) * (size_t)nfar);
+    double* fe = malloc(sizeof(double) * 3 * (size_t)nfar);
+    double* tmp = malloc(sizeof(double) * 2 * (size_t)nfar);
+    orc_far_nodes(s, fpts, fw);
+    orc_density_points(s, nfar, fpts, tmp, tmp + nfar, fe);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nsel; ++t) {
+        int64_t a = sel[t];
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int64_t c = 0; c < ncell; ++c) {
+            if (phi[c] != 1) continue;
+            double x[3], g[3];
+            orc_cell_center(s, c, x);
+            grad_u_atom(s, a, x, efield + 3 * c, ccfa, g);
+            gx += h3 * g[0];
+            gy += h3 * g[1];
+            gz += h3 * g[2];
+        }
+        for (int64_t p = 0; p < nfar; ++p) {
+            double g[3];
+            grad_u_atom(s, a, fpts + 3 * p, fe + 3 * p, ccfa, g);
+            gx += fw[p] * g[0];
+            gy += fw[p] * g[1];
+            gz += fw[p] * g[2];
+        }
+        for (int64_t b = 0; b < nb; ++b) {
+            int64_t i = ij[2 * b], j = ij[2 * b + 1];
+            if (i != a && j != a) continue;
+            double dx = s->xyz[3 * i] - s->xyz[3 * j], dy = s->xyz[3 * i + 1] - s->xyz[3 * j + 1],
+                   dz = s->xyz[3 * i + 2] - s->xyz[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double c = kb[b] * (r - r0[b]) / r * (i == a ? 1.0 : -1.0);
+            gx += c * dx; gy += c * dy; gz += c * dz;
+        }
+        f[3 * t + 0] = -gx;
+        f[3 * t + 1] = -gy;
+        f[3 * t + 2] = -gz;
+    }
+    free(fpts); free(fw); free(fe); free(tmp);
 }
 
 /* Total free energy at fixed labels: discrete VISM energy + bonds.

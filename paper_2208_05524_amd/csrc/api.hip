@@ -65,7 +65,7 @@ struct Layout {
     size_t boff, bother, br0, bk;
     size_t ulj, ucfa, ex, ey, ez, bound, u64cache;
     size_t bits;
-    size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez;
+    size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez, far_part;
     size_t red_d, red_i, scal_d, scal_i, sweep_flips;
     size_t fpart, fout;
     size_t total;
@@ -118,6 +118,7 @@ struct vesis_ctx {
     bool far_uploaded = false;
     bool bonds_uploaded = false;
     bool dens_valid = false;
+    bool forces_valid = false;
 
     bool prof = false;
     double prof_ms[K_NKINDS] = {0};
@@ -285,7 +286,7 @@ Layout plan(const vesis_ctx* c) {
     L.ey = take(8 * ncell);
     L.ez = take(8 * ncell);
     L.bound = take(8 * ncell);
-    L.u64cache = take(8 * ncell);
+    L.u64cache = take(16 * ncell);
     L.bits = take(4 * c->g.nwords());
     L.far_pts = take(32 * nfar);
     L.far_ulj = take(8 * nfar);
@@ -293,6 +294,7 @@ Layout plan(const vesis_ctx* c) {
     L.far_ex = take(8 * nfar);
     L.far_ey = take(8 * nfar);
     L.far_ez = take(8 * nfar);
+    L.far_part = take(8 * 4 * (size_t)POINT_SPLITS_MAX * nfar);
     L.red_d = take(8 * 2 * RED_BLOCKS);
     L.red_i = take(8 * 8 * RED_BLOCKS);
     L.scal_d = take(8 * 16);
@@ -392,12 +394,13 @@ vesis_status ensure_density(vesis_ctx* ctx) {
     }
     {
         Timed t(ctx, K_OTHER);
-        CK(launch_fill_f64(at<double>(ctx, ctx->lay.u64cache), ctx->g.ncell(), NAN, st));
+        CK(launch_fill_f64(at<double>(ctx, ctx->lay.u64cache), 2 * ctx->g.ncell(), NAN, st));
     }
     {
         Timed t(ctx, K_FAR);
         CK(launch_density_points(at<double4>(ctx, ctx->lay.far_pts), ctx->nfar, a, ph,
-                                 ctx->prm.precision, at<double>(ctx, ctx->lay.far_ulj),
+                                 ctx->prm.precision, at<double>(ctx, ctx->lay.far_part),
+                                 at<double>(ctx, ctx->lay.far_ulj),
                                  at<double>(ctx, ctx->lay.far_ucfa), at<double>(ctx, ctx->lay.far_ex),
                                  at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
                                  st));
@@ -417,9 +420,12 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     const uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
     {
         Timed t(ctx, K_ENERGY);
-        CK(launch_energy_volume(ctx->g, bits, at<double>(ctx, ctx->lay.ulj),
-                                at<double>(ctx, ctx->lay.ucfa), at<double>(ctx, ctx->lay.red_d),
-                                RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
+        CK(launch_energy_volume(ctx->g, dev_atoms(ctx), dev_physics(ctx), bits,
+                                at<double>(ctx, ctx->lay.ulj), at<double>(ctx, ctx->lay.ucfa),
+                                at<double>(ctx, ctx->lay.bound), at<double>(ctx, ctx->lay.u64cache),
+                                at<int64_t>(ctx, ctx->lay.scal_i) + SI_CNT + 2,
+                                at<double>(ctx, ctx->lay.red_d), RED_BLOCKS,
+                                at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
         CK(launch_geom_counts(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,
                               at<int64_t>(ctx, ctx->lay.scal_i) + SI_GEOM, st));
         if (ctx->nb > 0)
@@ -449,7 +455,7 @@ vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
     if (s != VESIS_OK) return s;
     hipStream_t st = ctx->stream;
     const Physics ph = dev_physics(ctx);
-    {
+    if (!ctx->forces_valid) {
         Timed t(ctx, K_FORCE);
         CK(launch_forces(ctx->g, dev_atoms(ctx), ph, ctx->prm.precision,
                          at<uint32_t>(ctx, ctx->lay.bits), at<double>(ctx, ctx->lay.ex),
@@ -458,6 +464,7 @@ vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
                          at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
                          ctx->nfar, dev_bonds(ctx), at<double>(ctx, ctx->lay.fpart),
                          ctx->lay.fchunks, at<double>(ctx, ctx->lay.fout), st));
+        ctx->forces_valid = true;
     }
     CK(hipMemcpyAsync(f_host, ctx->ws + ctx->lay.fout, 24 * ctx->na, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -477,6 +484,7 @@ vesis_status put_positions(vesis_ctx* ctx, const double* xyz) {
                       ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->dens_valid = false;
+    ctx->forces_valid = false;
     return VESIS_OK;
 }
 
@@ -537,6 +545,7 @@ vesis_status vesis_set_params(vesis_ctx* ctx, const vesis_params* p) {
     ctx->prm = *p;
     ctx->has_params = true;
     ctx->dens_valid = false;
+    ctx->forces_valid = false;
     if (rho_changed) ctx->atoms_uploaded = false;
     if (ctx->has_grid) {
         compute_stencil(ctx);
@@ -574,6 +583,7 @@ vesis_status vesis_set_grid(vesis_ctx* ctx, int32_t n, const double center[3], d
     ctx->has_ws = false;
     ctx->has_labels = false;
     ctx->dens_valid = false;
+    ctx->forces_valid = false;
     if (ctx->has_atoms && !inside_box(ctx, ctx->xyz.data(), ctx->na)) {
         ctx->has_atoms = false;
         return fail(ctx, VESIS_E_OUT_OF_BOX, "an atom lies outside the new box; set atoms again");
@@ -612,6 +622,7 @@ vesis_status vesis_set_atoms(vesis_ctx* ctx, int64_t n, const double* xyz, const
     ctx->atoms_uploaded = false;
     ctx->bonds_uploaded = false;
     ctx->dens_valid = false;
+    ctx->forces_valid = false;
     return VESIS_OK;
 }
 
@@ -631,6 +642,7 @@ vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_d
                           hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         ctx->dens_valid = false;
+    ctx->forces_valid = false;
         return VESIS_OK;
     }
     if (!finite_all(xyz, 3 * ctx->na)) return fail(ctx, VESIS_E_NONFINITE, "non-finite positions");
@@ -639,6 +651,7 @@ vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_d
         ctx->xyz.assign(xyz, xyz + 3 * ctx->na);
         ctx->atoms_uploaded = false;
         ctx->dens_valid = false;
+    ctx->forces_valid = false;
         return VESIS_OK;
     }
     return put_positions(ctx, xyz);
@@ -689,6 +702,7 @@ vesis_status vesis_set_bonds(vesis_ctx* ctx, int64_t nb, const int32_t* ij, cons
     ctx->b_r0 = rr;
     ctx->b_k = kk;
     ctx->bonds_uploaded = false;
+    ctx->forces_valid = false;
     return VESIS_OK;
 }
 
@@ -723,6 +737,7 @@ vesis_status vesis_set_workspace(vesis_ctx* ctx, void* device_ptr, size_t bytes)
     ctx->bonds_uploaded = false;
     ctx->far_uploaded = false;
     ctx->dens_valid = false;
+    ctx->forces_valid = false;
     if (!same) ctx->has_labels = false;
     return VESIS_OK;
 }
@@ -761,6 +776,7 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
             CK(launch_init_tight(g, dev_atoms(ctx), param, bits, st));
     }
     ctx->has_labels = true;
+    ctx->forces_valid = false;
     return VESIS_OK;
 }
 
@@ -806,6 +822,7 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
             }
         }
     }
+    if (total_flips > 0) ctx->forces_valid = false;
     if (out) {
         int64_t cnt[2] = {0, 0}, band = 0;
         CK(launch_band_count(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,

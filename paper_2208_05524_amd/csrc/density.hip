@@ -14,8 +14,8 @@
 //    inside the brick are small, so the FP32 differences keep ~7 digits even
 //    for the nearest atoms); all four wavefronts then read the tile by LDS
 //    broadcast;
-//  * each tile's FP32 partial sums are folded into FP64 accumulators, so
-//    no FP32 sum runs over more than 256 terms;
+//  * FP32 partial sums over 32 atoms are folded into FP64 accumulators, so
+//    no FP32 sum runs over more than 32 terms;
 //  * beside U the kernel keeps the absolute sums sum 4 eps (s^6 + s^3) and
 //    sum |Q|/r^2 and the nearest squared distance, from which the epilogue
 //    writes a bound on |U_fp32 - U_exact| per cell; flip decisions inside
@@ -30,22 +30,36 @@ constexpr int DWG = 256;
 constexpr int BX = 16, BY = 8, BZ = 8, KC = 4;
 constexpr int TILE = 256;
 
-// Error-bound constants.  With the nearest atom at least 2h from the cell
-// centre (else the bound is +inf), the relative error of one FP32 pair term
-// is below ~300 u from coordinate rounding, rsqrt (1 ulp) and the s^6 power
-// chain, and a 256-term FP32 partial adds at most 255 u of the absolute sum;
-// 640 covers both with margin.  FP64 sums run over all atoms sequentially.
+// Error bound of the FP32 path.  Cell offsets from the brick centre are at
+// most |c| <= 9h (16 x 8 x 8 brick); a cell whose nearest atom is closer than
+// 3h (or than 10 sqrt(r2_min)) gets an infinite bound and is always decided
+// in FP64.  Otherwise r >= 3h >= |c|/3 and, with u = 2^-24:
+//  * coordinates: d = fl(c - fl(r_i - O)) has |d_err| <= u (|a| + |c| + r)
+//    <= u (2|c| + 2r), so rel(r^2) <= 4u(|c|/r + 1) + 2u <= 18u;
+//  * rsqrt (1 ulp): rel(1/r) <= 10u; s = sigma^2/r^2: 21.5u; s^3: 65.5u;
+//    4 rho_w eps s^3: 66.5u; its square-weighted LJ term 133u;
+//  * a 32-term FP32 partial adds at most 31u of its absolute sum before it
+//    is folded into FP64.
+// So |U_LJ,fp32 - U_LJ| <= 164u sum 4 rho_w eps (s^6 + s^3) (KAPPA_LJ = 192
+// with margin), and each component of E carries <= 72u sum |Q|/r^2
+// (1/r^3: 31u, d: 8u relative to r; KAPPA_E = 96).
 constexpr double U32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
-constexpr double KAPPA32 = 640.0;
+constexpr double KAPPA_LJ = 192.0;
+constexpr double KAPPA_E = 96.0;
+constexpr int SUB = 32;                           // atoms per FP32 partial
 
-__device__ inline double cell_bound(double kappa_u, double absLJ, double absE, double ex,
+__device__ inline double cell_bound(double klj, double ke, double absLJ, double absE, double ex,
                                     double ey, double ez, double ccfa, float rmin2,
                                     float guard2) {
     if (rmin2 < guard2) return INFINITY;
-    const double d = 1.7320508075688772 * kappa_u * absE * 1.001;  // |E_err| <= sqrt(3) k u A_E
+    const double d = 1.7320508075688772 * ke * absE * 1.001;  // |E_err| <= sqrt(3) k u A_E
     const double emag = sqrt(ex * ex + ey * ey + ez * ez);
-    return kappa_u * absLJ * 1.001 + fabs(ccfa) * (2.0 * emag * d + d * d);
+    return 1.001 * (klj * absLJ + fabs(ccfa) * (2.0 * emag * d + d * d));
+}
+
+__host__ __device__ inline float guard_r2(double h, double r2min) {
+    return (float)fmax(9.0 * h * h, 100.0 * r2min);
 }
 
 __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics ph,
@@ -95,48 +109,51 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
         }
         __syncthreads();
         const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
-        float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
+        for (int m0 = 0; m0 < cnt; m0 += SUB) {
+            const int me = (m0 + SUB < cnt) ? m0 + SUB : cnt;
+            float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
 #pragma unroll
-        for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.f;
+            for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.f;
 #pragma unroll 2
-        for (int m = 0; m < cnt; ++m) {
-            const float4 p = spos[m];
-            const float4 q = sprm[m];
-            const float dx = cx - p.x, dy = cy - p.y;
-            const float dxy = fmaf(dx, dx, dy * dy);
+            for (int m = m0; m < me; ++m) {
+                const float4 p = spos[m];
+                const float4 q = sprm[m];
+                const float dx = cx - p.x, dy = cy - p.y;
+                const float dxy = fmaf(dx, dx, dy * dy);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const float dz = cz[k] - p.z;
+                    float r2 = fmaf(dz, dz, dxy);
+                    rmin[k] = fminf(rmin[k], r2);
+                    r2 = fmaxf(r2, r2min);
+                    const float ir = __builtin_amdgcn_rsqf(r2);
+                    const float ir2 = ir * ir;
+                    const float s = p.w * ir2;
+                    const float s3 = s * s * s;
+                    const float es3 = q.x * s3;
+                    P[k] = fmaf(es3, s3, P[k]);
+                    Q[k] += es3;
+                    const float qr3 = q.y * (ir2 * ir);
+                    Ex[k] = fmaf(qr3, dx, Ex[k]);
+                    Ey[k] = fmaf(qr3, dy, Ey[k]);
+                    Ez[k] = fmaf(qr3, dz, Ez[k]);
+                    AE[k] = fmaf(q.z, ir2, AE[k]);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                const float dz = cz[k] - p.z;
-                float r2 = fmaf(dz, dz, dxy);
-                rmin[k] = fminf(rmin[k], r2);
-                r2 = fmaxf(r2, r2min);
-                const float ir = __builtin_amdgcn_rsqf(r2);
-                const float ir2 = ir * ir;
-                const float s = p.w * ir2;
-                const float s3 = s * s * s;
-                const float es3 = q.x * s3;
-                P[k] = fmaf(es3, s3, P[k]);
-                Q[k] += es3;
-                const float qr3 = q.y * (ir2 * ir);
-                Ex[k] = fmaf(qr3, dx, Ex[k]);
-                Ey[k] = fmaf(qr3, dy, Ey[k]);
-                Ez[k] = fmaf(qr3, dz, Ez[k]);
-                AE[k] = fmaf(q.z, ir2, AE[k]);
+                dP[k] += P[k];
+                dQ[k] += Q[k];
+                dEx[k] += Ex[k];
+                dEy[k] += Ey[k];
+                dEz[k] += Ez[k];
+                dAE[k] += AE[k];
             }
-        }
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            dP[k] += P[k];
-            dQ[k] += Q[k];
-            dEx[k] += Ex[k];
-            dEy[k] += Ey[k];
-            dEz[k] += Ez[k];
-            dAE[k] += AE[k];
         }
     }
 
     if (i >= g.n || j >= g.n) return;
-    const float guard2 = (float)(4.0 * g.h * g.h);
+    const float guard2 = guard_r2(g.h, ph.r2min);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int kk = k0 + k;
@@ -148,8 +165,8 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
         out.ex[c] = dEx[k];
         out.ey[c] = dEy[k];
         out.ez[c] = dEz[k];
-        out.bound[c] = cell_bound(KAPPA32 * U32, dP[k] + dQ[k], dAE[k], dEx[k], dEy[k], dEz[k],
-                                  ph.ccfa, rmin[k], guard2);
+        out.bound[c] = cell_bound(KAPPA_LJ * U32, KAPPA_E * U32, dP[k] + dQ[k], dAE[k], dEx[k],
+                                  dEy[k], dEz[k], ph.ccfa, rmin[k], guard2);
     }
 }
 
@@ -219,7 +236,9 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
         }
     }
     if (i >= g.n || j >= g.n) return;
-    const double kappa = (double)a.n + 4096.0;
+    // FP64: one sequential sum over all atoms; coordinates are not rebased,
+    // so allow 1e5 u of relative error per term (|x| / r up to ~1e4)
+    const double kappa = ((double)a.n + 1.0e5) * U64;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int kk = k0 + k;
@@ -230,123 +249,121 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
         out.ex[c] = Ex[k];
         out.ey[c] = Ey[k];
         out.ez[c] = Ez[k];
-        out.bound[c] = cell_bound(kappa * U64, P[k] + Q[k], AE[k], Ex[k], Ey[k], Ez[k], ph.ccfa,
-                                  (float)rmin[k], (float)(4.0 * g.h * g.h));
+        out.bound[c] = cell_bound(kappa, kappa, P[k] + Q[k], AE[k], Ex[k], Ey[k], Ez[k], ph.ccfa,
+                                  (float)rmin[k], -1.0f);
     }
 }
 
-// Density at arbitrary points (far-field quadrature nodes): one point per
-// lane, atoms staged through LDS rebased to the block's first point.
+// Density at arbitrary points (far-field quadrature nodes).  The nodes are
+// few (6 nf^2 ntau) against the cells, so the atom range is split across
+// blockIdx.y to fill the chip: block (x, s) takes 256 nodes, one per lane,
+// and the s-th slice of the atoms, staged through LDS rebased to the block's
+// first node, with FP32 partials over 32 atoms folded into FP64.  Slices
+// write FP64 partial LJ sums and fields; points_combine adds the slices in
+// order and squares the field.
 constexpr int PWG = 256;
 
-__global__ __launch_bounds__(PWG) void density_points_f32(const double4* pts, int64_t np,
-                                                          Atoms a, Physics ph, double* ulj,
-                                                          double* ucfa, double* ex, double* ey,
-                                                          double* ez) {
-    __shared__ float4 spos[TILE];
-    __shared__ float4 sprm[TILE];
+template <typename T>
+struct PTypes;
+template <>
+struct PTypes<float> {
+    using T4 = float4;
+    static __device__ float4 mk(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+    static __device__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+};
+template <>
+struct PTypes<double> {
+    using T4 = double4;
+    static __device__ double4 mk(double a, double b, double c, double d) {
+        return make_double4(a, b, c, d);
+    }
+    static __device__ double rsq(double x) { return sqrt(1.0 / x); }
+};
+
+template <typename T>
+__global__ __launch_bounds__(PWG) void density_points_part(const double4* pts, int64_t np,
+                                                           Atoms a, Physics ph, int64_t chunk,
+                                                           int nsplit, double* part) {
+    using T4 = typename PTypes<T>::T4;
+    __shared__ T4 spos[TILE];
+    __shared__ T4 sprm[TILE];
     const int t = threadIdx.x;
+    const int sl = blockIdx.y;
+    const int64_t lo = (int64_t)sl * chunk;
+    const int64_t hi = (lo + chunk < a.n) ? lo + chunk : a.n;
     const int64_t p0 = (int64_t)blockIdx.x * PWG;
     const int64_t pi = p0 + t;
     const double4 o = pts[p0];
     const double4 me = pts[pi < np ? pi : p0];
-    const float px = (float)(me.x - o.x), py = (float)(me.y - o.y), pz = (float)(me.z - o.z);
-    const float r2min = (float)ph.r2min;
+    const T px = (T)(me.x - o.x), py = (T)(me.y - o.y), pz = (T)(me.z - o.z);
+    const T r2min = (T)ph.r2min;
     double dP = 0, dQ = 0, dEx = 0, dEy = 0, dEz = 0;
-    for (int64_t base = 0; base < a.n; base += TILE) {
+    for (int64_t base = lo; base < hi; base += TILE) {
         __syncthreads();
         const int64_t ai = base + t;
-        if (ai < a.n) {
-            const double4 p = a.pos[ai];
-            const float4 q = a.prm32[ai];
-            spos[t] = make_float4((float)(p.x - o.x), (float)(p.y - o.y), (float)(p.z - o.z), q.x);
-            sprm[t] = make_float4(q.y, q.z, 0.f, 0.f);
-        } else {
-            spos[t] = make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
-            sprm[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        __syncthreads();
-        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
-        float P = 0.f, Q = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
-        for (int m = 0; m < cnt; ++m) {
-            const float4 p = spos[m];
-            const float4 q = sprm[m];
-            const float dx = px - p.x, dy = py - p.y, dz = pz - p.z;
-            const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), r2min);
-            const float ir = __builtin_amdgcn_rsqf(r2);
-            const float ir2 = ir * ir;
-            const float s = p.w * ir2;
-            const float s3 = s * s * s;
-            const float es3 = q.x * s3;
-            P = fmaf(es3, s3, P);
-            Q += es3;
-            const float qr3 = q.y * (ir2 * ir);
-            Ex = fmaf(qr3, dx, Ex);
-            Ey = fmaf(qr3, dy, Ey);
-            Ez = fmaf(qr3, dz, Ez);
-        }
-        dP += P;
-        dQ += Q;
-        dEx += Ex;
-        dEy += Ey;
-        dEz += Ez;
-    }
-    if (pi >= np) return;
-    ulj[pi] = dP - dQ;
-    ucfa[pi] = ph.ccfa * (dEx * dEx + dEy * dEy + dEz * dEz);
-    ex[pi] = dEx;
-    ey[pi] = dEy;
-    ez[pi] = dEz;
-}
-
-__global__ __launch_bounds__(PWG) void density_points_f64(const double4* pts, int64_t np,
-                                                          Atoms a, Physics ph, double* ulj,
-                                                          double* ucfa, double* ex, double* ey,
-                                                          double* ez) {
-    __shared__ double4 spos[TILE];
-    __shared__ double2 sprm[TILE];
-    const int t = threadIdx.x;
-    const int64_t pi = (int64_t)blockIdx.x * PWG + t;
-    const double4 me = pts[pi < np ? pi : 0];
-    double P = 0, Q = 0, Ex = 0, Ey = 0, Ez = 0;
-    for (int64_t base = 0; base < a.n; base += TILE) {
-        __syncthreads();
-        const int64_t ai = base + t;
-        if (ai < a.n) {
+        if (ai < hi) {
             const double4 p = a.pos[ai];
             const double4 q = a.prm64[ai];
-            spos[t] = make_double4(p.x, p.y, p.z, q.x);
-            sprm[t] = make_double2(q.y, q.z);
-        } else {
-            spos[t] = make_double4(1.0e6, 1.0e6, 1.0e6, 0.0);
-            sprm[t] = make_double2(0.0, 0.0);
+            spos[t] = PTypes<T>::mk((T)(p.x - o.x), (T)(p.y - o.y), (T)(p.z - o.z), (T)q.x);
+            sprm[t] = PTypes<T>::mk((T)q.y, (T)q.z, (T)0, (T)0);
         }
         __syncthreads();
-        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
-        for (int m = 0; m < cnt; ++m) {
-            const double4 p = spos[m];
-            const double2 q = sprm[m];
-            const double dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
-            const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
-            const double ir2 = 1.0 / r2;
-            const double ir = sqrt(ir2);
-            const double s = p.w * ir2;
-            const double s3 = s * s * s;
-            const double es3 = q.x * s3;
-            P += es3 * s3;
-            Q += es3;
-            const double qr3 = q.y * (ir2 * ir);
-            Ex += qr3 * dx;
-            Ey += qr3 * dy;
-            Ez += qr3 * dz;
+        const int cnt = (int)((hi - base) < TILE ? (hi - base) : TILE);
+        for (int m0 = 0; m0 < cnt; m0 += SUB) {
+            const int me_ = (m0 + SUB < cnt) ? m0 + SUB : cnt;
+            T P = 0, Q = 0, Ex = 0, Ey = 0, Ez = 0;
+            for (int m = m0; m < me_; ++m) {
+                const T4 p = spos[m];
+                const T4 q = sprm[m];
+                const T dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+                T r2 = dx * dx + dy * dy + dz * dz;
+                r2 = r2 > r2min ? r2 : r2min;
+                const T ir = PTypes<T>::rsq(r2);
+                const T ir2 = ir * ir;
+                const T s = p.w * ir2;
+                const T s3 = s * s * s;
+                const T es3 = q.x * s3;
+                P += es3 * s3;
+                Q += es3;
+                const T qr3 = q.y * (ir2 * ir);
+                Ex += qr3 * dx;
+                Ey += qr3 * dy;
+                Ez += qr3 * dz;
+            }
+            dP += P;
+            dQ += Q;
+            dEx += Ex;
+            dEy += Ey;
+            dEz += Ez;
         }
     }
     if (pi >= np) return;
-    ulj[pi] = P - Q;
-    ucfa[pi] = ph.ccfa * (Ex * Ex + Ey * Ey + Ez * Ez);
-    ex[pi] = Ex;
-    ey[pi] = Ey;
-    ez[pi] = Ez;
+    const int64_t stride = (int64_t)nsplit * np;
+    const int64_t at = (int64_t)sl * np + pi;
+    part[at] = dP - dQ;
+    part[stride + at] = dEx;
+    part[2 * stride + at] = dEy;
+    part[3 * stride + at] = dEz;
+}
+
+__global__ void points_combine(int64_t np, int nsplit, const double* part, double ccfa,
+                               double* ulj, double* ucfa, double* ex, double* ey, double* ez) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int64_t stride = (int64_t)nsplit * np;
+    double lj = 0, x = 0, y = 0, z = 0;
+    for (int s = 0; s < nsplit; ++s) {
+        const int64_t at = (int64_t)s * np + p;
+        lj += part[at];
+        x += part[stride + at];
+        y += part[2 * stride + at];
+        z += part[3 * stride + at];
+    }
+    ulj[p] = lj;
+    ucfa[p] = ccfa * (x * x + y * y + z * z);
+    ex[p] = x;
+    ey[p] = y;
+    ez[p] = z;
 }
 
 // Deterministic two-level sum of w_p a_p and w_p b_p (w = pts[p].w).
@@ -382,17 +399,30 @@ hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph,
     return hipGetLastError();
 }
 
+int points_split(int64_t np, int64_t natoms) {
+    const int64_t nblk = (np + PWG - 1) / PWG;
+    int64_t s = (2048 + nblk - 1) / nblk;
+    s = s < 1 ? 1 : (s > POINT_SPLITS_MAX ? POINT_SPLITS_MAX : s);
+    const int64_t by_atoms = (natoms + 63) / 64;  // at least 64 atoms per slice
+    if (s > by_atoms) s = by_atoms < 1 ? 1 : by_atoms;
+    return (int)s;
+}
+
 hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a, const Physics& ph,
-                                 int precision, double* ulj, double* ucfa, double* ex, double* ey,
-                                 double* ez, hipStream_t st) {
+                                 int precision, double* part, double* ulj, double* ucfa,
+                                 double* ex, double* ey, double* ez, hipStream_t st) {
     if (np <= 0) return hipSuccess;
-    const unsigned nblk = (unsigned)((np + PWG - 1) / PWG);
+    const int nsplit = points_split(np, a.n);
+    const int64_t chunk = (a.n + nsplit - 1) / nsplit;
+    const dim3 grid((unsigned)((np + PWG - 1) / PWG), (unsigned)nsplit);
     if (precision == 64)
-        hipLaunchKernelGGL(density_points_f64, dim3(nblk), dim3(PWG), 0, st, pts, np, a, ph, ulj,
-                           ucfa, ex, ey, ez);
+        hipLaunchKernelGGL(density_points_part<double>, grid, dim3(PWG), 0, st, pts, np, a, ph,
+                           chunk, nsplit, part);
     else
-        hipLaunchKernelGGL(density_points_f32, dim3(nblk), dim3(PWG), 0, st, pts, np, a, ph, ulj,
-                           ucfa, ex, ey, ez);
+        hipLaunchKernelGGL(density_points_part<float>, grid, dim3(PWG), 0, st, pts, np, a, ph,
+                           chunk, nsplit, part);
+    hipLaunchKernelGGL(points_combine, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np,
+                       nsplit, part, ph.ccfa, ulj, ucfa, ex, ey, ez);
     return hipGetLastError();
 }
 

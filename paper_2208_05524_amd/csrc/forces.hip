@@ -12,9 +12,12 @@
 //
 // Layout: a workgroup owns 256 atoms (one per lane) and one chunk of cells
 // (a cubic brick of the grid, or a run of far-field nodes).  Cells stream
-// through LDS 256 at a time, each staged once as (position relative to the
-// chunk centre, w, w E) in FP32 and read by broadcast; every lane keeps FP32
-// partials per tile folded into FP64.  Each (chunk, atom) pair writes one
+// through LDS 256 at a time; the solvent cells of a tile (w != 0) are
+// compacted in cell order (wave ballots, so the summation order is fixed)
+// and staged once as (position relative to the chunk centre, w, w E) in FP32,
+// read by broadcast; every lane keeps FP32 partials per tile folded into
+// FP64.  Per pair the LJ term and the (E.d) d part of the CFA term share one
+// coefficient along d, the E/r^3 part is summed separately.  Each (chunk, atom) pair writes one
 // FP64 partial gradient; a second kernel sums the chunks of each atom in a
 // fixed order and adds the bond terms, so the result is deterministic.
 #include "internal.h"
@@ -80,7 +83,9 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     using T4 = typename V4<T>::type;
     __shared__ T4 scell[CT];
     __shared__ T4 sfld[CT];
+    __shared__ int wcnt[AWG / 64];
     const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
     const int64_t chunk = blockIdx.y;
     const int64_t atom = (int64_t)blockIdx.x * AWG + t;
     const bool has_atom = atom < f.a.n;
@@ -110,59 +115,79 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         ncells = rem < CT * FAR_TILES ? rem : CT * FAR_TILES;
     }
 
-    T ax = 0, ay = 0, az = 0, sig2 = 0;
+    // per-lane atom: position relative to the chunk origin and the two
+    // per-atom factors, 24 rho_w eps (LJ) and -2 Ccfa Q (CFA)
+    T ax = 0, ay = 0, az = 0, sig2 = 0, e24 = 0, k3 = 0;
+    double kq = 0.0;
     if (has_atom) {
         const double4 p = f.a.pos[atom];
+        const double4 q = f.a.prm64[atom];
         ax = (T)(p.x - ox);
         ay = (T)(p.y - oy);
         az = (T)(p.z - oz);
-        sig2 = (T)f.a.prm64[atom].x;
+        sig2 = (T)q.x;
+        e24 = (T)(6.0 * q.y);
+        kq = -2.0 * f.ph.ccfa * q.z;
+        k3 = (T)(3.0 * kq);
     }
     const T r2min = (T)f.ph.r2min;
-    double gl[3] = {0.0, 0.0, 0.0}, gc[3] = {0.0, 0.0, 0.0};
+    double gd[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
 
     for (int64_t base = 0; base < ncells; base += CT) {
-        __syncthreads();
-        {
-            const int64_t li = base + t;
-            T px = 0, py = 0, pz = 0, w = 0, wx = 0, wy = 0, wz = 0;
-            if (li < ncells) {
-                if (is_grid) {
-                    const int lx = (int)(li % f.cb), ly = (int)((li / f.cb) % f.cb),
-                              lz = (int)(li / ((int64_t)f.cb * f.cb));
-                    const int x = ci * f.cb + lx, y = cj * f.cb + ly, z = ck * f.cb + lz;
-                    if (x < g.n && y < g.n && z < g.n) {
-                        const uint32_t word = f.bits[g.row(y, z) + 1 + (x >> 5)];
-                        if ((word >> (x & 31)) & 1u) {
-                            const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-                            const double wd = f.ph.h3;
-                            px = (T)((lx - 0.5 * (f.cb - 1)) * g.h);
-                            py = (T)((ly - 0.5 * (f.cb - 1)) * g.h);
-                            pz = (T)((lz - 0.5 * (f.cb - 1)) * g.h);
-                            w = (T)wd;
-                            wx = (T)(wd * f.ex[c]);
-                            wy = (T)(wd * f.ey[c]);
-                            wz = (T)(wd * f.ez[c]);
-                        }
+        // stage the tile's cells with nonzero weight, in cell order
+        const int64_t li = base + t;
+        T px = 0, py = 0, pz = 0, w = 0, wx = 0, wy = 0, wz = 0;
+        bool keep = false;
+        if (li < ncells) {
+            if (is_grid) {
+                const int lx = (int)(li % f.cb), ly = (int)((li / f.cb) % f.cb),
+                          lz = (int)(li / ((int64_t)f.cb * f.cb));
+                const int x = ci * f.cb + lx, y = cj * f.cb + ly, z = ck * f.cb + lz;
+                if (x < g.n && y < g.n && z < g.n) {
+                    const uint32_t word = f.bits[g.row(y, z) + 1 + (x >> 5)];
+                    if ((word >> (x & 31)) & 1u) {
+                        const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
+                        const double wd = f.ph.h3;
+                        px = (T)((lx - 0.5 * (f.cb - 1)) * g.h);
+                        py = (T)((ly - 0.5 * (f.cb - 1)) * g.h);
+                        pz = (T)((lz - 0.5 * (f.cb - 1)) * g.h);
+                        w = (T)wd;
+                        wx = (T)(wd * f.ex[c]);
+                        wy = (T)(wd * f.ey[c]);
+                        wz = (T)(wd * f.ez[c]);
+                        keep = true;
                     }
-                } else {
-                    const int64_t pidx = far0 + li;
-                    const double4 p = f.far_pts[pidx];
-                    px = (T)(p.x - ox);
-                    py = (T)(p.y - oy);
-                    pz = (T)(p.z - oz);
-                    w = (T)p.w;
-                    wx = (T)(p.w * f.far_ex[pidx]);
-                    wy = (T)(p.w * f.far_ey[pidx]);
-                    wz = (T)(p.w * f.far_ez[pidx]);
                 }
+            } else {
+                const int64_t pidx = far0 + li;
+                const double4 p = f.far_pts[pidx];
+                px = (T)(p.x - ox);
+                py = (T)(p.y - oy);
+                pz = (T)(p.z - oz);
+                w = (T)p.w;
+                wx = (T)(p.w * f.far_ex[pidx]);
+                wy = (T)(p.w * f.far_ey[pidx]);
+                wz = (T)(p.w * f.far_ez[pidx]);
+                keep = true;
             }
-            scell[t] = mk4(px, py, pz, w);
-            sfld[t] = mk4(wx, wy, wz, (T)0);
+        }
+        const uint64_t bal = __ballot(keep);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        __syncthreads();  // previous tile fully consumed
+        if (lane == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, cnt = 0;
+#pragma unroll
+        for (int k = 0; k < AWG / 64; ++k) {
+            off += (k < wv) ? wcnt[k] : 0;
+            cnt += wcnt[k];
+        }
+        if (keep) {
+            scell[off + before] = mk4(px, py, pz, w);
+            sfld[off + before] = mk4(wx, wy, wz, (T)0);
         }
         __syncthreads();
-        const int cnt = (int)((ncells - base) < CT ? (ncells - base) : CT);
-        T lx = 0, ly = 0, lz = 0, cx = 0, cy = 0, cz = 0;
+        T dx_ = 0, dy_ = 0, dz_ = 0, ex_ = 0, ey_ = 0, ez_ = 0;
 #pragma unroll 2
         for (int m = 0; m < cnt; ++m) {
             const T4 c = scell[m];
@@ -170,41 +195,34 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
             const T dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
             const T r2 = dx * dx + dy * dy + dz * dz;
             const bool inside = r2 < r2min;
-            const T r2c = inside ? r2min : r2;
-            const T ir = rsq<T>(r2c);
+            const T ir = rsq<T>(inside ? r2min : r2);
             const T ir2 = ir * ir;
             const T ir3 = ir2 * ir;
             const T s = sig2 * ir2;
             const T s3 = s * s * s;
-            T lj = c.w * ir2 * (s3 * ((T)2 * s3 - (T)1));
+            const T lj = (c.w * ir2) * ((s3 + s3) * s3 - s3);
             const T ed = e.x * dx + e.y * dy + e.z * dz;
-            T t3 = (T)3 * ed * ir3 * ir2;
-            if (inside) {
-                lj = 0;
-                t3 = 0;
-            }
-            lx += lj * dx;
-            ly += lj * dy;
-            lz += lj * dz;
-            cx += e.x * ir3 - t3 * dx;
-            cy += e.y * ir3 - t3 * dy;
-            cz += e.z * ir3 - t3 * dz;
+            T coef = e24 * lj - k3 * (ed * (ir3 * ir2));
+            coef = inside ? (T)0 : coef;
+            dx_ += coef * dx;
+            dy_ += coef * dy;
+            dz_ += coef * dz;
+            ex_ += ir3 * e.x;
+            ey_ += ir3 * e.y;
+            ez_ += ir3 * e.z;
         }
-        gl[0] += lx;
-        gl[1] += ly;
-        gl[2] += lz;
-        gc[0] += cx;
-        gc[1] += cy;
-        gc[2] += cz;
+        gd[0] += dx_;
+        gd[1] += dy_;
+        gd[2] += dz_;
+        ge[0] += ex_;
+        ge[1] += ey_;
+        ge[2] += ez_;
     }
     if (!has_atom) return;
-    const double4 q = f.a.prm64[atom];
-    const double e24 = 6.0 * q.y;            // 24 rho_w eps = 6 (4 rho_w eps)
-    const double kq = -2.0 * f.ph.ccfa * q.z;
     double* out = f.partial + (chunk * f.a.n + atom) * 3;
-    out[0] = e24 * gl[0] + kq * gc[0];
-    out[1] = e24 * gl[1] + kq * gc[1];
-    out[2] = e24 * gl[2] + kq * gc[2];
+    out[0] = gd[0] + kq * ge[0];
+    out[1] = gd[1] + kq * ge[1];
+    out[2] = gd[2] + kq * ge[2];
 }
 
 // F_n = -(sum over chunks of the partial gradients + bond gradient).

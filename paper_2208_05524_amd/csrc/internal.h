@@ -71,9 +71,14 @@ enum KernelKind { K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4
 // Launch wrappers (one per translation unit; all asynchronous on `st`).
 hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph, int precision,
                                CellFields out, hipStream_t st);
+// Far-field node density: the atoms are split into at most POINT_SPLITS_MAX
+// slices whose FP64 partials (4 x nsplit x np doubles in `part`) are summed
+// in slice order.
+constexpr int POINT_SPLITS_MAX = 16;
+int points_split(int64_t np, int64_t natoms);
 hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a, const Physics& ph,
-                                 int precision, double* ulj, double* ucfa, double* ex, double* ey,
-                                 double* ez, hipStream_t st);
+                                 int precision, double* part, double* ulj, double* ucfa,
+                                 double* ex, double* ey, double* ez, hipStream_t st);
 hipError_t launch_weighted_sum2(const double4* pts, const double* a, const double* b, int64_t np,
                                 double* partial, int nblocks, double* out, hipStream_t st);
 
@@ -87,9 +92,11 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                             int colour, int sweep, uint32_t* bits, const double* ulj,
                             const double* ucfa, const double* bound, double* u64cache,
                             int* sweep_flips, int64_t* counters, hipStream_t st);
-hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
-                                const double* ucfa, double* partial, int nblocks, double* out,
-                                hipStream_t st);
+// u64cache: 2 x ncell FP64 (LJ parts, then CFA parts; NaN = not computed).
+hipError_t launch_energy_volume(const Grid& g, const Atoms& a, const Physics& ph,
+                                const uint32_t* bits, const double* ulj, const double* ucfa,
+                                const double* bound, double* u64cache, int64_t* counters,
+                                double* partial, int nblocks, double* out, hipStream_t st);
 hipError_t launch_geom_counts(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
                               int64_t* out, hipStream_t st);
 hipError_t launch_band_count(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,

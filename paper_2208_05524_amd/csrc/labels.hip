@@ -79,52 +79,68 @@ __global__ void init_loose_kernel(Grid g, double R0, uint32_t* bits) {
 }
 
 // Tight surface: solute iff min_i (|x - r_i| - d_i) <= 0, d_i = scale sigma_i.
-// Atoms stream through LDS; an FP32 test against the word's 32-cell segment
-// skips atoms that cannot reach it, the rest are tested cell by cell in FP64.
+// A workgroup owns one 32-cell word column (fixed w) of a 16 x 16 patch of
+// rows (y, z).  Atoms stream through in tiles of 256; each lane tests one
+// atom of the tile against the patch's bounding box and the survivors are
+// compacted into LDS, so every lane then visits only atoms that can reach
+// its row; those are tested cell by cell in FP64 exactly as defined.
 constexpr int IWG = 256;
 __global__ __launch_bounds__(IWG) void init_tight_kernel(Grid g, Atoms a, double scale,
                                                          uint32_t* bits) {
 #pragma clang fp contract(off)
     __shared__ double4 sat[IWG];
-    const int64_t tid = (int64_t)blockIdx.x * IWG + threadIdx.x;
-    const int64_t total = (int64_t)g.nwin * g.n * g.n;
-    const bool active = tid < total;
-    int w = 0, y = 0, z = 0;
-    if (active) {
-        w = (int)(tid % g.nwin);
-        const int64_t r = tid / g.nwin;
-        y = (int)(r % g.n);
-        z = (int)(r / g.n);
-    }
+    __shared__ int nsurv;
+    const int t = threadIdx.x;
+    const int npy = (g.n + 15) / 16;
+    int b = blockIdx.x;
+    const int w = b % g.nwin;
+    b /= g.nwin;
+    const int yb = b % npy, zb = b / npy;
+    const int y = yb * 16 + (t & 15), z = zb * 16 + (t >> 4);
+    const bool active = y < g.n && z < g.n;
     const int x0 = 32 * w;
     const int xl = min(32, g.n - x0);
-    const double py = centre_coord(g.cy, g.L, y, g.h);
-    const double pz = centre_coord(g.cz, g.L, z, g.h);
-    const double xa = centre_coord(g.cx, g.L, x0, g.h);
-    const double xb = centre_coord(g.cx, g.L, x0 + xl - 1, g.h);
+    const int ylo = yb * 16, yhi = min(yb * 16 + 15, g.n - 1);
+    const int zlo = zb * 16, zhi = min(zb * 16 + 15, g.n - 1);
+    // cell-centre bounding box of the patch
+    const double bx0 = centre_coord(g.cx, g.L, x0, g.h), bx1 = centre_coord(g.cx, g.L, x0 + xl - 1, g.h);
+    const double by0 = centre_coord(g.cy, g.L, ylo, g.h), by1 = centre_coord(g.cy, g.L, yhi, g.h);
+    const double bz0 = centre_coord(g.cz, g.L, zlo, g.h), bz1 = centre_coord(g.cz, g.L, zhi, g.h);
+    const double py = centre_coord(g.cy, g.L, active ? y : ylo, g.h);
+    const double pz = centre_coord(g.cz, g.L, active ? z : zlo, g.h);
     uint32_t solute = 0;
     for (int64_t base = 0; base < a.n; base += IWG) {
+        if (t == 0) nsurv = 0;
         __syncthreads();
-        const int64_t ai = base + threadIdx.x;
+        const int64_t ai = base + t;
         if (ai < a.n) {
             const double4 p = a.pos[ai];
-            sat[threadIdx.x] = make_double4(p.x, p.y, p.z, scale * a.prm64[ai].w);
-        }
-        __syncthreads();
-        const int cnt = (int)((a.n - base) < IWG ? (a.n - base) : IWG);
-        if (!active) continue;
-        for (int m = 0; m < cnt; ++m) {
-            const double4 p = sat[m];
-            const double dy = py - p.y, dz = pz - p.z;
-            const double ex = p.x < xa ? xa - p.x : (p.x > xb ? p.x - xb : 0.0);
-            const double d2 = ex * ex + dy * dy + dz * dz;
-            const double lim = p.w * (1.0 + 1e-9) + 1e-12;
-            if (d2 > lim * lim) continue;
-            for (int b = 0; b < xl; ++b) {
-                const double dx = centre_coord(g.cx, g.L, x0 + b, g.h) - p.x;
-                if (sqrt(dx * dx + dy * dy + dz * dz) - p.w <= 0.0) solute |= 1u << b;
+            const double d = scale * a.prm64[ai].w;
+            const double ex = p.x < bx0 ? bx0 - p.x : (p.x > bx1 ? p.x - bx1 : 0.0);
+            const double ey = p.y < by0 ? by0 - p.y : (p.y > by1 ? p.y - by1 : 0.0);
+            const double ez = p.z < bz0 ? bz0 - p.z : (p.z > bz1 ? p.z - bz1 : 0.0);
+            const double lim = d * (1.0 + 1e-9) + 1e-12;
+            if (ex * ex + ey * ey + ez * ez <= lim * lim) {
+                const int slot = atomicAdd(&nsurv, 1);
+                sat[slot] = make_double4(p.x, p.y, p.z, d);
             }
         }
+        __syncthreads();
+        const int cnt = nsurv;
+        if (active) {
+            for (int m = 0; m < cnt; ++m) {
+                const double4 p = sat[m];
+                const double dy = py - p.y, dz = pz - p.z;
+                const double ex = p.x < bx0 ? bx0 - p.x : (p.x > bx1 ? p.x - bx1 : 0.0);
+                const double lim = p.w * (1.0 + 1e-9) + 1e-12;
+                if (ex * ex + dy * dy + dz * dz > lim * lim) continue;
+                for (int bb = 0; bb < xl; ++bb) {
+                    const double dx = centre_coord(g.cx, g.L, x0 + bb, g.h) - p.x;
+                    if (sqrt(dx * dx + dy * dy + dz * dz) - p.w <= 0.0) solute |= 1u << bb;
+                }
+            }
+        }
+        __syncthreads();
     }
     if (active) bits[g.row(y, z) + 1 + w] = ~solute;  // padding bits past n stay 1
 }
@@ -140,23 +156,50 @@ __device__ inline uint32_t window5(const uint32_t* r, int x) {
     return v & 31u;
 }
 
-// S_j = sum over offsets 0 < |o|^2 <= 8 of w_{|o|^2} phi_{j+o}, via integer
-// counts per squared offset.
-__device__ inline double stencil_sum(const Grid& g, const Stencil& sc, const uint32_t* bits,
-                                     int x, int y, int z) {
+// The 25 x-rows (y + dy, z + dz) with dy^2 + dz^2 <= 8 around a word, three
+// words each (left, own, right), loaded once per lane.
+struct Rows25 {
+    uint32_t l[25], c[25], r[25];
+};
+
+__device__ inline void load_rows(const Grid& g, const uint32_t* bits, int w, int y, int z,
+                                 Rows25& R) {
+    int k = 0;
+#pragma unroll
+    for (int dz = -2; dz <= 2; ++dz) {
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            if (dy * dy + dz * dz > 8) continue;
+            const uint32_t* p = bits + g.row(y + dy, z + dz) + w;
+            R.l[k] = p[0];
+            R.c[k] = p[1];
+            R.r[k] = p[2];
+            ++k;
+        }
+    }
+}
+
+// S_j = sum over offsets 0 < |o|^2 <= 8 of w_{|o|^2} phi_{j+o} for the cell
+// at bit b of the lane's word, via integer counts per squared offset taken
+// from 5-bit windows (bit 0 = x-2, bit 2 = x) of the preloaded rows.
+__device__ inline double stencil_sum(const Stencil& sc, const Rows25& R, int b) {
     int net[9];
 #pragma unroll
     for (int s = 0; s < 9; ++s) net[s] = 0;
+    int k = 0;
 #pragma unroll
     for (int dz = -2; dz <= 2; ++dz) {
 #pragma unroll
         for (int dy = -2; dy <= 2; ++dy) {
             const int q = dy * dy + dz * dz;
             if (q > 8) continue;
-            const uint32_t v = window5(bits + g.row(y + dy, z + dz), x);
+            const uint32_t hi = b >= 2 ? R.r[k] : R.c[k];
+            const uint32_t lo = b >= 2 ? R.c[k] : R.l[k];
+            const uint32_t v = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b >= 2 ? b - 2 : b + 30)) & 31u;
             if (q > 0) net[q] += ((v >> 2) & 1u) ? 1 : -1;
             if (q + 1 <= 8) net[q + 1] += 2 * __popc(v & 0xAu) - 2;
             if (q + 4 <= 8) net[q + 4] += 2 * __popc(v & 0x11u) - 2;
+            ++k;
         }
     }
     double S = 0.0;
@@ -165,11 +208,11 @@ __device__ inline double stencil_sum(const Grid& g, const Stencil& sc, const uin
     return S;
 }
 
-// FP64 density at cell (x, y, z), summed by one wavefront: lane l takes atoms
-// l, l + 64, ...; the partial sums meet in a fixed xor butterfly, so every
-// lane ends with the same bits.
-__device__ inline double wave_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
-                                          int y, int z) {
+// FP64 density parts at cell (x, y, z), summed by one wavefront: lane l takes
+// atoms l, l + 64, ...; the partial sums meet in a fixed xor butterfly, so
+// every lane ends with the same bits.
+__device__ inline void wave_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
+                                        int y, int z, double& u_lj, double& u_cfa) {
     const int lane = threadIdx.x & 63;
     const double px = centre_coord(g.cx, g.L, x, g.h);
     const double py = centre_coord(g.cy, g.L, y, g.h);
@@ -180,8 +223,11 @@ __device__ inline double wave_density_f64(const Grid& g, const Atoms& a, const P
         const double4 q = a.prm64[i];
         const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
         const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
-        const double ir2 = 1.0 / r2;
-        const double ir = sqrt(ir2);
+        // 1/r from the hardware estimate and two Newton steps (full FP64 accuracy)
+        double ir = __builtin_amdgcn_rsq(r2);
+        ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+        ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+        const double ir2 = ir * ir;
         const double s = q.x * ir2;
         const double s3 = s * s * s;
         lj += q.y * (s3 * s3 - s3);
@@ -197,7 +243,26 @@ __device__ inline double wave_density_f64(const Grid& g, const Atoms& a, const P
         ey += __shfl_xor(ey, off);
         ez += __shfl_xor(ez, off);
     }
-    return lj + ph.ccfa * (ex * ex + ey * ey + ez * ez);
+    u_lj = lj;
+    u_cfa = ph.ccfa * (ex * ex + ey * ey + ez * ez);
+}
+
+// FP64 parts of cell c from the cache (2 x ncell doubles: LJ, then CFA; NaN =
+// not yet computed), computing and caching them if needed.  Whole wavefront.
+__device__ inline void cached_f64(const Grid& g, const Atoms& a, const Physics& ph, int x, int y,
+                                  int z, double* cache, int64_t* counters, double& lj,
+                                  double& cfa) {
+    const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
+    lj = cache[c];
+    cfa = cache[g.ncell() + c];
+    if (isnan(lj)) {
+        wave_density_f64(g, a, ph, x, y, z, lj, cfa);
+        if ((threadIdx.x & 63) == 0) {
+            cache[c] = lj;
+            cache[g.ncell() + c] = cfa;
+            atomicAdd((unsigned long long*)&counters[1], 1ull);
+        }
+    }
 }
 
 // --------------------------------------------------------------- flip pass
@@ -238,21 +303,25 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
         cand = band & colour_mask(p, ca, x0) & valid_mask(g.n, x0);
     }
     uint32_t flipmask = 0, tiemask = 0;
-    while (cand) {
-        const int b = __ffs(cand) - 1;
-        cand &= cand - 1;
-        const int x = x0 + b;
-        const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-        const double S = stencil_sum(g, sc, bits, x, y, z);
-        const double phi = ((C >> b) & 1u) ? 1.0 : -1.0;
-        const double hU = ph.h3 * (ulj[c] + ucfa[c]);
-        const double cS = sc.c * S;
-        const double dE = phi * (cS - hU);
-        const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
-        if (!(fabs(dE) > tol))
-            tiemask |= 1u << b;
-        else if (dE < 0.0)
-            flipmask |= 1u << b;
+    Rows25 R;
+    if (cand) {
+        load_rows(g, bits, w, y, z, R);
+        while (cand) {
+            const int b = __ffs(cand) - 1;
+            cand &= cand - 1;
+            const int x = x0 + b;
+            const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
+            const double S = stencil_sum(sc, R, b);
+            const double phi = ((C >> b) & 1u) ? 1.0 : -1.0;
+            const double hU = ph.h3 * (ulj[c] + ucfa[c]);
+            const double cS = sc.c * S;
+            const double dE = phi * (cS - hU);
+            const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
+            if (!(fabs(dE) > tol))
+                tiemask |= 1u << b;
+            else if (dE < 0.0)
+                flipmask |= 1u << b;
+        }
     }
     // near ties: the whole wavefront resolves them one at a time in FP64
     const int lane = threadIdx.x & 63;
@@ -265,19 +334,12 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
         const int xL = __shfl(x0, leader) + bL;
         const int yL = __shfl(y, leader);
         const int zL = __shfl(z, leader);
-        const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
-        double u64 = u64cache[cL];
-        if (isnan(u64)) {
-            u64 = wave_density_f64(g, a, ph, xL, yL, zL);
-            if (lane == leader) {
-                u64cache[cL] = u64;
-                atomicAdd((unsigned long long*)&counters[1], 1ull);
-            }
-        }
+        double lj, cfa;
+        cached_f64(g, a, ph, xL, yL, zL, u64cache, counters, lj, cfa);
         if (lane == leader) {
-            const double S = stencil_sum(g, sc, bits, xL, yL, zL);
+            const double S = stencil_sum(sc, R, bL);
             const double phi = ((C >> bL) & 1u) ? 1.0 : -1.0;
-            const double dE = phi * (sc.c * S - ph.h3 * u64);
+            const double dE = phi * (sc.c * S - ph.h3 * (lj + cfa));
             if (dE < 0.0) flipmask |= 1u << bL;
             tiemask &= ~(1u << bL);
             atomicAdd((unsigned long long*)&counters[0], 1ull);
@@ -293,9 +355,39 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
 // ------------------------------------------------------------ reductions
 
 // h^3-less sums of U_LJ and U_CFA over solvent cells (FP64).
+// Solvent cells whose density carries no FP32 bound (an atom closer than the
+// guard distance) enter the energy with their FP64 parts: one wavefront per
+// 64 cells fills the FP64 cache for every such cell first.
+__global__ __launch_bounds__(64) void guard_fixup_kernel(Grid g, Atoms a, Physics ph,
+                                                         const uint32_t* bits, const double* bound,
+                                                         double* cache, int64_t* counters) {
+    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    bool need = false;
+    int x = 0, y = 0, z = 0;
+    if (c < g.ncell()) {
+        x = (int)(c % g.n);
+        const int64_t r = c / g.n;
+        y = (int)(r % g.n);
+        z = (int)(r / g.n);
+        const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
+        need = ((word >> (x & 31)) & 1u) && isinf(bound[c]) && isnan(cache[c]);
+    }
+    for (;;) {
+        const uint64_t bal = __ballot(need);
+        if (bal == 0) break;
+        const int leader = __ffsll((unsigned long long)bal) - 1;
+        const int xL = __shfl(x, leader), yL = __shfl(y, leader), zL = __shfl(z, leader);
+        double lj, cfa;
+        cached_f64(g, a, ph, xL, yL, zL, cache, counters, lj, cfa);
+        if ((int)(threadIdx.x & 63) == leader) need = false;
+    }
+}
+
 __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uint32_t* bits,
                                                                const double* ulj,
                                                                const double* ucfa,
+                                                               const double* bound,
+                                                               const double* cache,
                                                                double* partial) {
     __shared__ double sh[RED_WG];
     double sa = 0.0, sb = 0.0;
@@ -307,8 +399,13 @@ __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uin
         const int y = (int)(r % g.n), z = (int)(r / g.n);
         const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
         if ((word >> (x & 31)) & 1u) {
-            sa += ulj[c];
-            sb += ucfa[c];
+            if (isinf(bound[c])) {
+                sa += cache[c];
+                sb += cache[ncell + c];
+            } else {
+                sa += ulj[c];
+                sb += ucfa[c];
+            }
         }
     }
     sa = block_sum(sa, sh);
@@ -419,8 +516,9 @@ hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream
 
 hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
                              hipStream_t st) {
-    const int64_t total = (int64_t)g.nwin * g.n * g.n;
-    hipLaunchKernelGGL(init_tight_kernel, dim3(nblk(total, IWG)), dim3(IWG), 0, st, g, a, scale,
+    const int64_t np = (g.n + 15) / 16;
+    const int64_t blocks = (int64_t)g.nwin * np * np;
+    hipLaunchKernelGGL(init_tight_kernel, dim3((unsigned)blocks), dim3(IWG), 0, st, g, a, scale,
                        bits);
     return hipGetLastError();
 }
@@ -439,11 +537,14 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     return hipGetLastError();
 }
 
-hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
-                                const double* ucfa, double* partial, int nblocks, double* out,
-                                hipStream_t st) {
+hipError_t launch_energy_volume(const Grid& g, const Atoms& a, const Physics& ph,
+                                const uint32_t* bits, const double* ulj, const double* ucfa,
+                                const double* bound, double* cache, int64_t* counters,
+                                double* partial, int nblocks, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(guard_fixup_kernel, dim3(nblk(g.ncell(), 64)), dim3(64), 0, st, g, a, ph,
+                       bits, bound, cache, counters);
     hipLaunchKernelGGL(energy_volume_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, ulj,
-                       ucfa, partial);
+                       ucfa, bound, cache, partial);
     hipLaunchKernelGGL((reduce_partials<double, 2>), dim3(1), dim3(RED_WG), 0, st, partial,
                        nblocks, out);
     return hipGetLastError();

@@ -1,0 +1,87 @@
+"""Parity at the benchmark's full size: two seeded 5,000-atom globules 1.5 nm
+apart on 256^3 cells of 0.05 nm, in the launch configuration bench.py times
+(FP32 densities, tight start, chain bonds).
+
+The oracle computes the whole grid here (density with field, initial
+labels, colour minimisation, energy) on the host cores, and forces on 64
+seeded atoms.  Every cell's density must lie inside the kernel's certified
+bound; labels, sweep and flip counts must match exactly when the oracle saw
+no decision inside 1e-9 |G|; energies within 1e-6 |G|; forces within 1e-4.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import energies_close, force_close, gpu_context, log, oracle_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    t0 = time.time()
+    w = synth.two_globules()
+    log("full size: workload", w.name, w.natoms, w.n)
+    ctx = gpu_context(w, precision=32, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    g_init = ctx.labels()
+    rc, gst = ctx.minimize()
+    out = dict(w=w, rc=rc, gst=gst, g_init=g_init, g_lab=ctx.labels(), g_e=ctx.energy(),
+               g_f=ctx.forces())
+    out["g_ulj"], out["g_ucfa"], out["g_bound"] = ctx.density(with_bound=True)
+    ctx.close()
+    log("gpu done", gst, f"{time.time() - t0:.1f}s")
+    s = oracle_system(w, with_bonds=True)
+    oulj, oucfa, oe = s.density_grid(efield=True)
+    log("oracle density done", f"{time.time() - t0:.1f}s")
+    far = s.far_field()
+    phi = s.init_tight()
+    out["o_init"] = phi.copy()
+    e0 = s.energy(phi, oulj, oucfa, far)["total"]
+    rc_o, ost, ties, _ = s.minimize_colour(phi, oulj + oucfa, tie_tol=1e-9 * abs(e0))
+    log("oracle minimisation done", ost, "ties", len(ties), f"{time.time() - t0:.1f}s")
+    e = s.energy(phi, oulj, oucfa, far)
+    e["bond"] = s.bond_energy()
+    e["total"] += e["bond"]
+    rng = synth.SplitMix64(3064)
+    sel = np.unique((rng.uniform(200) * w.natoms).astype(np.int64))[:64]
+    out.update(s=s, o_ulj=oulj, o_ucfa=oucfa, o_lab=phi, o_st=ost, o_ties=ties, o_e=e, sel=sel,
+               o_f=s.forces_subset(phi, oe, sel))
+    log("oracle forces done", f"{time.time() - t0:.1f}s")
+    return out
+
+
+def test_full_size_initial_labels(full):
+    assert np.array_equal(full["g_init"], full["o_init"])
+
+
+def test_full_size_density_inside_bound_everywhere(full):
+    err = np.abs((full["g_ulj"] + full["g_ucfa"]) - (full["o_ulj"] + full["o_ucfa"]))
+    b = full["g_bound"]
+    fin = np.isfinite(b)
+    log("cells with a bound:", fin.mean(), "max err/bound", float((err[fin] / b[fin]).max()))
+    assert np.all(err <= b)
+
+
+def test_full_size_labels_and_energy(full):
+    gst, ost = full["gst"], full["o_st"]
+    log("gpu", gst, "oracle", ost)
+    assert full["rc"] == 0 and gst["converged"] == 1 and ost["converged"] == 1
+    if len(full["o_ties"]) == 0:
+        assert np.array_equal(full["g_lab"], full["o_lab"])
+        assert (gst["sweeps"], gst["flips"], gst["band"]) == \
+            (ost["sweeps"], ost["flips"], ost["band"])
+    bad = energies_close(full["g_e"], full["o_e"], 1e-6, keys=("geom", "vdw_in", "vdw_far",
+                                                             "elec_in", "elec_far", "bond",
+                                                             "total"))
+    log("energy gpu", full["g_e"], "oracle", full["o_e"])
+    assert not bad, bad
+
+
+def test_full_size_forces_on_sampled_atoms(full):
+    fg = full["g_f"][full["sel"]]
+    ok, rel = force_close(fg, full["o_f"], 1e-4)
+    log("force max rel err", float(rel.max()))
+    assert ok.all()
