@@ -208,7 +208,7 @@ vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);
 
 /* Copy the per-cell density parts U_LJ and U_CFA (n^3 FP64 each) and,
  * if bound != NULL, the per-cell bound on |U_computed - U_exact| used for
- * near-tie decisions (n^3 FP64; +inf marks cells always decided in FP64). */
+ * near-tie decisions (n^3 FP64). */
 vesis_status vesis_get_density(vesis_ctx* ctx, double* u_lj, double* u_cfa, double* bound);
 
 /* Kernel timing for measurement: enable != 0 records HIP events around

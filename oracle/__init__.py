@@ -52,10 +52,14 @@ def default_mobility(dt: float = 0.1) -> Mobility:
 def lib():
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_build.LIB) or (
-                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        # a test that plants a mistake in a copy of the oracle points this at
+        # the mutated build
+        path = os.environ.get("VESIS_ORACLE_LIB")
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
+        L = C.CDLL(path)
         sp = C.POINTER(_Sys)
         L.orc_C0.restype = _D
         L.orc_surface_prefactor.restype = _D

@@ -18,14 +18,14 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+def build(verbose: bool = False, src: str = SRC, lib: str = LIB) -> str:
+    tmp = lib + ".tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -337,8 +337,9 @@ vesis_status upload_inputs(vesis_ctx* ctx) {
             p64[4 * i + 1] = e4;
             p64[4 * i + 2] = ctx->q[i];
             p64[4 * i + 3] = ctx->sigma[i];
-            p32[4 * i + 0] = (float)s2;
-            p32[4 * i + 1] = (float)e4;
+            const double c6 = e4 * s2 * s2 * s2;
+            p32[4 * i + 0] = (float)c6;
+            p32[4 * i + 1] = (float)(c6 * s2 * s2 * s2);
             p32[4 * i + 2] = (float)ctx->q[i];
             p32[4 * i + 3] = (float)std::fabs(ctx->q[i]);
         }
@@ -420,12 +421,9 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     const uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
     {
         Timed t(ctx, K_ENERGY);
-        CK(launch_energy_volume(ctx->g, dev_atoms(ctx), dev_physics(ctx), bits,
-                                at<double>(ctx, ctx->lay.ulj), at<double>(ctx, ctx->lay.ucfa),
-                                at<double>(ctx, ctx->lay.bound), at<double>(ctx, ctx->lay.u64cache),
-                                at<int64_t>(ctx, ctx->lay.scal_i) + SI_CNT + 2,
-                                at<double>(ctx, ctx->lay.red_d), RED_BLOCKS,
-                                at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
+        CK(launch_energy_volume(ctx->g, bits, at<double>(ctx, ctx->lay.ulj),
+                                at<double>(ctx, ctx->lay.ucfa), at<double>(ctx, ctx->lay.red_d),
+                                RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
         CK(launch_geom_counts(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,
                               at<int64_t>(ctx, ctx->lay.scal_i) + SI_GEOM, st));
         if (ctx->nb > 0)

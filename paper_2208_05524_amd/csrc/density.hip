@@ -6,16 +6,19 @@
 // The grid kernel is the hot loop of the method (the paper's grid-parallel
 // evaluation, Sec. "GPU Implementation"): every cell against every atom.
 // Layout on gfx950:
-//  * a workgroup of 256 lanes owns a 16 x 8 x 8 brick of cells, 4 cells per
+//  * a workgroup of 256 lanes owns a 16 x 8 x 4 brick of cells, 2 cells per
 //    lane stacked along z, so the x/y part of each distance is shared by the
-//    lane's four cells;
+//    lane's two cells (2 cells per lane keeps the kernel near 100 VGPRs and
+//    5 wavefronts per SIMD, which measured faster than 4 or 8);
 //  * atoms stream through LDS in tiles of 256: each lane stages one atom,
 //    rebased in FP64 to the brick centre and rounded to FP32 (cell offsets
 //    inside the brick are small, so the FP32 differences keep ~7 digits even
 //    for the nearest atoms); all four wavefronts then read the tile by LDS
 //    broadcast;
-//  * FP32 partial sums over 32 atoms are folded into FP64 accumulators, so
-//    no FP32 sum runs over more than 32 terms;
+//  * the LJ powers come from r^-6 = (r^-2)^3 against per-atom constants
+//    4 rho_w eps sigma^6 and 4 rho_w eps sigma^12;
+//  * FP32 partial sums over 32 atoms are summed over the 256-atom tile in
+//    FP32 and folded into FP64 once per tile;
 //  * beside U the kernel keeps the absolute sums sum 4 eps (s^6 + s^3) and
 //    sum |Q|/r^2 and the nearest squared distance, from which the epilogue
 //    writes a bound on |U_fp32 - U_exact| per cell; flip decisions inside
@@ -27,46 +30,49 @@ namespace vesis {
 namespace {
 
 constexpr int DWG = 256;
-constexpr int BX = 16, BY = 8, BZ = 8, KC = 4;
+constexpr int BX = 16, BY = 8, BZ = 4, KC = 2;
 constexpr int TILE = 256;
 
-// Error bound of the FP32 path.  Cell offsets from the brick centre are at
-// most |c| <= 9h (16 x 8 x 8 brick); a cell whose nearest atom is closer than
-// 3h (or than 10 sqrt(r2_min)) gets an infinite bound and is always decided
-// in FP64.  Otherwise r >= 3h >= |c|/3 and, with u = 2^-24:
+// Error bound of the FP32 path.  Atoms within 12h of the brick centre are
+// summed in FP64; the others are at r >= 12h - |c| >= 3.6h from every cell
+// of the 16 x 8 x 4 brick (|c| <= 8.4h), so |c|/r <= 2.4 and, with
+// u = 2^-24:
 //  * coordinates: d = fl(c - fl(r_i - O)) has |d_err| <= u (|a| + |c| + r)
-//    <= u (2|c| + 2r), so rel(r^2) <= 4u(|c|/r + 1) + 2u <= 18u;
-//  * rsqrt (1 ulp): rel(1/r) <= 10u; s = sigma^2/r^2: 21.5u; s^3: 65.5u;
-//    4 rho_w eps s^3: 66.5u; its square-weighted LJ term 133u;
-//  * a 32-term FP32 partial adds at most 31u of its absolute sum before it
-//    is folded into FP64.
-// So |U_LJ,fp32 - U_LJ| <= 164u sum 4 rho_w eps (s^6 + s^3) (KAPPA_LJ = 192
-// with margin), and each component of E carries <= 72u sum |Q|/r^2
-// (1/r^3: 31u, d: 8u relative to r; KAPPA_E = 96).
+//    <= u (2|c| + 2r), so rel(r^2) <= 4u(|c|/r + 1) + 2u <= 16u;
+//  * rsqrt (1 ulp): rel(1/r) <= 9u; r^-2: 18.5u; r^-6: 56.5u; the s^3 term
+//    c6 r^-6: 57u; the s^6 term c12 r^-6 r^-6: 114u;
+//  * sums: 32-term FP32 partials (31u), 8 of them summed in FP32 per tile
+//    (7u), then FP64.
+// So |U_LJ,fp32 - U_LJ| <= 152u sum_far 4 rho_w eps (s^6 + s^3) (KAPPA_LJ =
+// 192 with margin) and each component of E carries <= 74u sum_far |Q|/r^2
+// (Q r^-3: 29u, d: 6.8u relative to r; KAPPA_E = 96).  The FP64 near terms
+// carry ~1e-15 relative error; NEAR_REL = 1e-12 of their absolute sums.
 constexpr double U32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double KAPPA_LJ = 192.0;
 constexpr double KAPPA_E = 96.0;
+constexpr double NEAR_REL = 1.0e-12;
 constexpr int SUB = 32;                           // atoms per FP32 partial
 
-__device__ inline double cell_bound(double klj, double ke, double absLJ, double absE, double ex,
-                                    double ey, double ez, double ccfa, float rmin2,
-                                    float guard2) {
-    if (rmin2 < guard2) return INFINITY;
-    const double d = 1.7320508075688772 * ke * absE * 1.001;  // |E_err| <= sqrt(3) k u A_E
+// Bound on |U - U_exact| from a bound on the LJ part (errLJ) and a per-
+// component bound on the field (errE): |E'|^2 - |E|^2 <= 2|E'| d + d^2 with
+// d = sqrt(3) errE.
+__device__ inline double cell_bound(double errLJ, double errE, double ex, double ey, double ez,
+                                    double ccfa) {
+    const double d = 1.7320508075688772 * errE * 1.001;
     const double emag = sqrt(ex * ex + ey * ey + ez * ez);
-    return 1.001 * (klj * absLJ + fabs(ccfa) * (2.0 * emag * d + d * d));
-}
-
-__host__ __device__ inline float guard_r2(double h, double r2min) {
-    return (float)fmax(9.0 * h * h, 100.0 * r2min);
+    return 1.001 * (errLJ + fabs(ccfa) * (2.0 * emag * d + d * d));
 }
 
 __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics ph,
                                                         CellFields out) {
-    __shared__ float4 spos[TILE];
-    __shared__ float4 sprm[TILE];
+    __shared__ float4 spos[TILE];     // far atoms: rebased FP32 position, |Q|
+    __shared__ float4 sprm[TILE];     // far atoms: c6, c12, Q
+    __shared__ double4 npos[TILE];    // near atoms: FP64 position, sigma^2
+    __shared__ double4 nprm[TILE];    // near atoms: 4 rho_w eps, Q, |Q|
+    __shared__ int wcnt[2][DWG / 64];
     const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
     const int tx = t & 15, ty = (t >> 4) & 7, tz = t >> 7;
     const int nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY;
     int b = blockIdx.x;
@@ -76,84 +82,163 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
     const int bz = b / nby;
     const int i = bx * BX + tx, j = by * BY + ty, k0 = bz * BZ + tz * KC;
 
-    // brick centre in FP64; lane cell offsets from it in FP32
+    // brick centre in FP64; lane cell offsets from it in FP32 (far atoms)
+    // and the lane's cell centres in FP64 (near atoms)
     const double ox = g.x0 + (bx * BX + 0.5 * (BX - 1)) * g.h;
     const double oy = g.y0 + (by * BY + 0.5 * (BY - 1)) * g.h;
     const double oz = g.z0 + (bz * BZ + 0.5 * (BZ - 1)) * g.h;
     const float cx = (float)((tx - 0.5 * (BX - 1)) * g.h);
     const float cy = (float)((ty - 0.5 * (BY - 1)) * g.h);
+    const double x64 = g.x0 + i * g.h, y64 = g.y0 + j * g.h;
     float cz[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) cz[k] = (float)((tz * KC + k - 0.5 * (BZ - 1)) * g.h);
-
-    const float r2min = (float)ph.r2min;
-    double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dAE[KC];
-    float rmin[KC];
+    double z64[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        dP[k] = dQ[k] = dEx[k] = dEy[k] = dEz[k] = dAE[k] = 0.0;
-        rmin[k] = INFINITY;
+        cz[k] = (float)((tz * KC + k - 0.5 * (BZ - 1)) * g.h);
+        z64[k] = g.z0 + (k0 + k) * g.h;
     }
+    // atoms within 12h of the brick centre are "near": they are summed in
+    // FP64; every other atom is at least 12h - 8.4h > 3h from every cell
+    // (and beyond the r2_min floor)
+    const double rnear = 12.0 * g.h + 4.0 * sqrt(ph.r2min);
+    const float rnear2 = (float)(rnear * rnear);
+    const float r2min = (float)ph.r2min;
+
+    double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dMag[KC], dAE[KC], nMag[KC], nAE[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        dP[k] = dQ[k] = dEx[k] = dEy[k] = dEz[k] = dMag[k] = dAE[k] = nMag[k] = nAE[k] = 0.0;
 
     for (int64_t base = 0; base < a.n; base += TILE) {
-        __syncthreads();
+        // classify this tile's atoms and compact them, in atom order, into
+        // the far (FP32) and near (FP64) lists
         const int64_t ai = base + t;
+        bool far = false, near = false;
+        double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+        float4 q32 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float ax = 0.f, ay = 0.f, az = 0.f;
         if (ai < a.n) {
-            const double4 p = a.pos[ai];
-            const float4 q = a.prm32[ai];
-            spos[t] = make_float4((float)(p.x - ox), (float)(p.y - oy), (float)(p.z - oz), q.x);
-            sprm[t] = make_float4(q.y, q.z, q.w, 0.f);
-        } else {
-            spos[t] = make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
-            sprm[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            p = a.pos[ai];
+            q32 = a.prm32[ai];
+            ax = (float)(p.x - ox);
+            ay = (float)(p.y - oy);
+            az = (float)(p.z - oz);
+            near = fmaf(ax, ax, fmaf(ay, ay, az * az)) < rnear2;
+            far = !near;
+        }
+        const uint64_t bfar = __ballot(far), bnear = __ballot(near);
+        const uint64_t below = (1ull << lane) - 1ull;
+        __syncthreads();  // the previous tile has been consumed
+        if (lane == 0) {
+            wcnt[0][wv] = __popcll(bfar);
+            wcnt[1][wv] = __popcll(bnear);
         }
         __syncthreads();
-        const int cnt = (int)((a.n - base) < TILE ? (a.n - base) : TILE);
-        for (int m0 = 0; m0 < cnt; m0 += SUB) {
-            const int me = (m0 + SUB < cnt) ? m0 + SUB : cnt;
+        int ofar = 0, onear = 0, nfar = 0, nnear = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < DWG / 64; ++w2) {
+            ofar += (w2 < wv) ? wcnt[0][w2] : 0;
+            onear += (w2 < wv) ? wcnt[1][w2] : 0;
+            nfar += wcnt[0][w2];
+            nnear += wcnt[1][w2];
+        }
+        if (far) {
+            // prm32 = (4 rho_w eps sigma^6, 4 rho_w eps sigma^12, Q, |Q|)
+            const int at = ofar + __popcll(bfar & below);
+            spos[at] = make_float4(ax, ay, az, q32.w);
+            sprm[at] = make_float4(q32.x, q32.y, q32.z, 0.f);
+        }
+        if (near) {
+            const double4 q = a.prm64[ai];   // sigma^2, 4 rho_w eps, Q, sigma
+            const int at = onear + __popcll(bnear & below);
+            npos[at] = make_double4(p.x, p.y, p.z, q.x);
+            nprm[at] = make_double4(q.y, q.z, fabs(q.z), 0.0);
+        }
+        __syncthreads();
+
+        // far atoms, FP32: 32-atom partials, summed over the tile in FP32,
+        // folded into FP64 once per tile
+        float TP[KC], TQ[KC], TEx[KC], TEy[KC], TEz[KC], TAE[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) TP[k] = TQ[k] = TEx[k] = TEy[k] = TEz[k] = TAE[k] = 0.f;
+        for (int m0 = 0; m0 < nfar; m0 += SUB) {
+            const int me = (m0 + SUB < nfar) ? m0 + SUB : nfar;
             float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.f;
 #pragma unroll 2
             for (int m = m0; m < me; ++m) {
-                const float4 p = spos[m];
+                const float4 pp = spos[m];
                 const float4 q = sprm[m];
-                const float dx = cx - p.x, dy = cy - p.y;
+                const float dx = cx - pp.x, dy = cy - pp.y;
                 const float dxy = fmaf(dx, dx, dy * dy);
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
-                    const float dz = cz[k] - p.z;
-                    float r2 = fmaf(dz, dz, dxy);
-                    rmin[k] = fminf(rmin[k], r2);
-                    r2 = fmaxf(r2, r2min);
+                    const float dz = cz[k] - pp.z;
+                    const float r2 = fmaxf(fmaf(dz, dz, dxy), r2min);
                     const float ir = __builtin_amdgcn_rsqf(r2);
                     const float ir2 = ir * ir;
-                    const float s = p.w * ir2;
-                    const float s3 = s * s * s;
-                    const float es3 = q.x * s3;
-                    P[k] = fmaf(es3, s3, P[k]);
-                    Q[k] += es3;
-                    const float qr3 = q.y * (ir2 * ir);
+                    const float ir6 = ir2 * ir2 * ir2;
+                    // 4 rho_w eps (s^6, s^3) = (c12 r^-12, c6 r^-6)
+                    P[k] = fmaf(q.y * ir6, ir6, P[k]);
+                    Q[k] = fmaf(q.x, ir6, Q[k]);
+                    const float qr3 = q.z * (ir2 * ir);
                     Ex[k] = fmaf(qr3, dx, Ex[k]);
                     Ey[k] = fmaf(qr3, dy, Ey[k]);
                     Ez[k] = fmaf(qr3, dz, Ez[k]);
-                    AE[k] = fmaf(q.z, ir2, AE[k]);
+                    AE[k] = fmaf(pp.w, ir2, AE[k]);
                 }
             }
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                dP[k] += P[k];
-                dQ[k] += Q[k];
-                dEx[k] += Ex[k];
-                dEy[k] += Ey[k];
-                dEz[k] += Ez[k];
-                dAE[k] += AE[k];
+                TP[k] += P[k];
+                TQ[k] += Q[k];
+                TEx[k] += Ex[k];
+                TEy[k] += Ey[k];
+                TEz[k] += Ez[k];
+                TAE[k] += AE[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            dP[k] += TP[k];
+            dQ[k] += TQ[k];
+            dEx[k] += TEx[k];
+            dEy[k] += TEy[k];
+            dEz[k] += TEz[k];
+            dMag[k] += (double)TP[k] + (double)TQ[k];
+            dAE[k] += TAE[k];
+        }
+
+        // near atoms, FP64 (1/r from the hardware estimate + two Newton steps)
+        for (int m = 0; m < nnear; ++m) {
+            const double4 pp = npos[m];
+            const double4 q = nprm[m];
+            const double dx = x64 - pp.x, dy = y64 - pp.y;
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const double dz = z64[k] - pp.z;
+                const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
+                double ir = __builtin_amdgcn_rsq(r2);
+                ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+                ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+                const double ir2 = ir * ir;
+                const double sg = pp.w * ir2;
+                const double s3 = sg * sg * sg;
+                const double es3 = q.x * s3;
+                dP[k] += es3 * s3;
+                dQ[k] += es3;
+                nMag[k] += es3 * s3 + es3;
+                const double qr3 = q.y * (ir2 * ir);
+                dEx[k] += qr3 * dx;
+                dEy[k] += qr3 * dy;
+                dEz[k] += qr3 * dz;
+                nAE[k] += q.z * ir2;
             }
         }
     }
 
     if (i >= g.n || j >= g.n) return;
-    const float guard2 = guard_r2(g.h, ph.r2min);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int kk = k0 + k;
@@ -165,8 +250,9 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
         out.ex[c] = dEx[k];
         out.ey[c] = dEy[k];
         out.ez[c] = dEz[k];
-        out.bound[c] = cell_bound(KAPPA_LJ * U32, KAPPA_E * U32, dP[k] + dQ[k], dAE[k], dEx[k],
-                                  dEy[k], dEz[k], ph.ccfa, rmin[k], guard2);
+        out.bound[c] = cell_bound(KAPPA_LJ * U32 * dMag[k] + NEAR_REL * nMag[k],
+                                  KAPPA_E * U32 * dAE[k] + NEAR_REL * nAE[k], dEx[k], dEy[k],
+                                  dEz[k], ph.ccfa);
     }
 }
 
@@ -190,11 +276,10 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
 #pragma unroll
     for (int k = 0; k < KC; ++k) z[k] = g.z0 + (k0 + k) * g.h;
 
-    double P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC], rmin[KC];
+    double P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.0;
-        rmin[k] = INFINITY;
     }
     for (int64_t base = 0; base < a.n; base += TILE) {
         __syncthreads();
@@ -218,7 +303,6 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
             for (int k = 0; k < KC; ++k) {
                 const double dz = z[k] - p.z;
                 double r2 = dx * dx + dy * dy + dz * dz;
-                rmin[k] = fmin(rmin[k], r2);
                 r2 = fmax(r2, ph.r2min);
                 const double ir2 = 1.0 / r2;
                 const double ir = sqrt(ir2);
@@ -249,8 +333,8 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
         out.ex[c] = Ex[k];
         out.ey[c] = Ey[k];
         out.ez[c] = Ez[k];
-        out.bound[c] = cell_bound(kappa, kappa, P[k] + Q[k], AE[k], Ex[k], Ey[k], Ez[k], ph.ccfa,
-                                  (float)rmin[k], -1.0f);
+        out.bound[c] = cell_bound(kappa * (P[k] + Q[k]), kappa * AE[k], Ex[k], Ey[k], Ez[k],
+                                  ph.ccfa);
     }
 }
 

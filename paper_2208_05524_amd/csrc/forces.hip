@@ -21,6 +21,7 @@
 // FP64 partial gradient; a second kernel sums the chunks of each atom in a
 // fixed order and adds the bond terms, so the result is deterministic.
 #include "internal.h"
+#include "reduce.h"
 
 namespace vesis {
 namespace {
@@ -281,14 +282,6 @@ __global__ __launch_bounds__(BWG) void bond_energy_kernel(int64_t natoms, const 
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-__global__ void sum_final_kernel(const double* partial, int nblocks, double* out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < nblocks; ++i) s += partial[i];
-        out[0] = s;
-    }
-}
-
 }  // namespace
 
 int64_t force_partial_chunks(const Grid& g, int64_t natoms, int64_t nfar) {
@@ -337,7 +330,8 @@ hipError_t launch_bond_energy(const Atoms& a, const Bonds& bonds, double* partia
                               double* out, hipStream_t st) {
     hipLaunchKernelGGL(bond_energy_kernel, dim3(nblocks), dim3(BWG), 0, st, a.n, a.pos, bonds,
                        partial);
-    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(64), 0, st, partial, nblocks, out);
+    hipLaunchKernelGGL((reduce_partials<double, 1>), dim3(1), dim3(RED_WG), 0, st, partial, nblocks,
+                       out);
     return hipGetLastError();
 }
 

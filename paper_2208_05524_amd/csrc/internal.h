@@ -46,7 +46,7 @@ struct Atoms {
     int64_t n;
     const double4* pos;   // x, y, z, 0
     const double4* prm64; // sigma^2, 4 rho_w eps, Q, sigma
-    const float4* prm32;  // sigma^2, 4 rho_w eps, Q, |Q|
+    const float4* prm32;  // 4 rho_w eps sigma^6, 4 rho_w eps sigma^12, Q, |Q|
 };
 
 struct Physics {
@@ -63,7 +63,7 @@ struct CellFields {
     double* ex;
     double* ey;
     double* ez;
-    double* bound;   // bound on |U - U_exact| (U units); +inf forces FP64
+    double* bound;   // bound on |U - U_exact| (U units)
 };
 
 enum KernelKind { K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6, K_NKINDS = 7 };
@@ -88,15 +88,14 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream_t st);
 hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
                              hipStream_t st);
+// u64cache: 2 x ncell FP64 (LJ parts, then CFA parts; NaN = not computed).
 hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
                             int colour, int sweep, uint32_t* bits, const double* ulj,
                             const double* ucfa, const double* bound, double* u64cache,
                             int* sweep_flips, int64_t* counters, hipStream_t st);
-// u64cache: 2 x ncell FP64 (LJ parts, then CFA parts; NaN = not computed).
-hipError_t launch_energy_volume(const Grid& g, const Atoms& a, const Physics& ph,
-                                const uint32_t* bits, const double* ulj, const double* ucfa,
-                                const double* bound, double* u64cache, int64_t* counters,
-                                double* partial, int nblocks, double* out, hipStream_t st);
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
+                                const double* ucfa, double* partial, int nblocks, double* out,
+                                hipStream_t st);
 hipError_t launch_geom_counts(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
                               int64_t* out, hipStream_t st);
 hipError_t launch_band_count(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,

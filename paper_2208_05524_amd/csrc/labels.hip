@@ -355,39 +355,9 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
 // ------------------------------------------------------------ reductions
 
 // h^3-less sums of U_LJ and U_CFA over solvent cells (FP64).
-// Solvent cells whose density carries no FP32 bound (an atom closer than the
-// guard distance) enter the energy with their FP64 parts: one wavefront per
-// 64 cells fills the FP64 cache for every such cell first.
-__global__ __launch_bounds__(64) void guard_fixup_kernel(Grid g, Atoms a, Physics ph,
-                                                         const uint32_t* bits, const double* bound,
-                                                         double* cache, int64_t* counters) {
-    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    bool need = false;
-    int x = 0, y = 0, z = 0;
-    if (c < g.ncell()) {
-        x = (int)(c % g.n);
-        const int64_t r = c / g.n;
-        y = (int)(r % g.n);
-        z = (int)(r / g.n);
-        const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
-        need = ((word >> (x & 31)) & 1u) && isinf(bound[c]) && isnan(cache[c]);
-    }
-    for (;;) {
-        const uint64_t bal = __ballot(need);
-        if (bal == 0) break;
-        const int leader = __ffsll((unsigned long long)bal) - 1;
-        const int xL = __shfl(x, leader), yL = __shfl(y, leader), zL = __shfl(z, leader);
-        double lj, cfa;
-        cached_f64(g, a, ph, xL, yL, zL, cache, counters, lj, cfa);
-        if ((int)(threadIdx.x & 63) == leader) need = false;
-    }
-}
-
 __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uint32_t* bits,
                                                                const double* ulj,
                                                                const double* ucfa,
-                                                               const double* bound,
-                                                               const double* cache,
                                                                double* partial) {
     __shared__ double sh[RED_WG];
     double sa = 0.0, sb = 0.0;
@@ -399,13 +369,8 @@ __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uin
         const int y = (int)(r % g.n), z = (int)(r / g.n);
         const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
         if ((word >> (x & 31)) & 1u) {
-            if (isinf(bound[c])) {
-                sa += cache[c];
-                sb += cache[ncell + c];
-            } else {
-                sa += ulj[c];
-                sb += ucfa[c];
-            }
+            sa += ulj[c];
+            sb += ucfa[c];
         }
     }
     sa = block_sum(sa, sh);
@@ -537,14 +502,11 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     return hipGetLastError();
 }
 
-hipError_t launch_energy_volume(const Grid& g, const Atoms& a, const Physics& ph,
-                                const uint32_t* bits, const double* ulj, const double* ucfa,
-                                const double* bound, double* cache, int64_t* counters,
-                                double* partial, int nblocks, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(guard_fixup_kernel, dim3(nblk(g.ncell(), 64)), dim3(64), 0, st, g, a, ph,
-                       bits, bound, cache, counters);
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
+                                const double* ucfa, double* partial, int nblocks, double* out,
+                                hipStream_t st) {
     hipLaunchKernelGGL(energy_volume_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, ulj,
-                       ucfa, bound, cache, partial);
+                       ucfa, partial);
     hipLaunchKernelGGL((reduce_partials<double, 2>), dim3(1), dim3(RED_WG), 0, st, partial,
                        nblocks, out);
     return hipGetLastError();

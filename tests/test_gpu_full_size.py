@@ -69,10 +69,17 @@ def test_full_size_labels_and_energy(full):
     gst, ost = full["gst"], full["o_st"]
     log("gpu", gst, "oracle", ost)
     assert full["rc"] == 0 and gst["converged"] == 1 and ost["converged"] == 1
+    same = np.array_equal(full["g_lab"], full["o_lab"])
+    log("labels identical:", same, "oracle decisions inside 1e-9 |G|:", len(full["o_ties"]))
     if len(full["o_ties"]) == 0:
-        assert np.array_equal(full["g_lab"], full["o_lab"])
+        assert same
+    if same:
         assert (gst["sweeps"], gst["flips"], gst["band"]) == \
             (ost["sweeps"], ost["flips"], ost["band"])
+    else:
+        # only decisions inside the 1e-9 |G| window may differ: both results
+        # must still be local minima of (almost) the same energy
+        assert len(full["o_ties"]) > 0
     bad = energies_close(full["g_e"], full["o_e"], 1e-6, keys=("geom", "vdw_in", "vdw_far",
                                                              "elec_in", "elec_far", "bond",
                                                              "total"))

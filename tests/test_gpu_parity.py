@@ -110,15 +110,17 @@ def _compare_minimisation(w, mode, param, precision):
     s, ophi, ost, ties, oe, _ = _oracle_state(w, mode=mode, param=param)
     log(w.name, mode, "gpu", gst, "oracle", ost, "ties", len(ties))
     assert rc == 0 and gst["converged"] == 1
+    same = np.array_equal(glab, ophi)
+    log("labels identical:", same, "oracle decisions inside 1e-9 |G|:", len(ties))
     if len(ties) == 0:
-        assert np.array_equal(glab, ophi)
-        assert gst["sweeps"] == ost["sweeps"]
-        assert gst["flips"] == ost["flips"]
-        assert gst["band"] == ost["band"]
+        assert same
+    if same:
+        assert (gst["sweeps"], gst["flips"], gst["band"]) == \
+            (ost["sweeps"], ost["flips"], ost["band"])
     else:
         # decisions inside 1e-9 |G| may differ; what remains must still be a
         # local minimum of the same energy
-        log("oracle near-tie decisions:", len(ties))
+        assert len(ties) > 0
     bad = energies_close(ge, oe, 1e-6)
     assert not bad, bad
     return ctx, glab, ge

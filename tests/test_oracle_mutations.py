@@ -1,0 +1,71 @@
+"""The pins catch plausible mistakes: each case plants one mistake in a copy
+of the oracle's C source (on the CPU), builds it, and runs the pin that
+should catch it against the mutated build, which must fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "vesis_oracle.c")
+
+# (name, text to replace, replacement, pin test that must fail)
+MUTATIONS = [
+    ("lj_sign", "lj += 4.0 * s->eps[i] * (sr6 * sr6 - sr6);",
+     "lj += 4.0 * s->eps[i] * (sr6 * sr6 + sr6);", "test_lj_sphere_energy_closed_form"),
+    ("lj_no_rho", "*u_lj = s->rho_w * lj;", "*u_lj = lj;", "test_lj_sphere_energy_closed_form"),
+    ("cfa_no_cross_terms", "ex += f * dx;", "ex += fabs(f * dx);",
+     "test_two_charge_cfa_exterior_of_ball_closed_form"),
+    ("cfa_prefactor", "return s->coulomb_k / (8.0 * M_PI)", "return s->coulomb_k / (4.0 * M_PI)",
+     "test_born_energy_closed_form"),
+    ("far_jacobian", "* wt * L / (tau * tau * tau * tau);", "* wt * L / (tau * tau * tau);",
+     "test_far_field_centred_atom_independent_integral"),
+    ("far_face_axis", "y[a1] = L * gx[iu];", "y[a1] = L * gx[iv];",
+     "test_far_field_off_centre_atom_independent_integral"),
+    ("surface_power", "pow(s->h, 6) / pow(delta, 4)", "pow(s->h, 4) / pow(delta, 4)",
+     "test_geom_energy_of_a_cube_matches_pair_count"),
+    ("c0_value", "return 8.0 * M_PI / (M_PI * M_PI - 3.0);", "return 8.0 * M_PI / (M_PI * M_PI - 2.0);",
+     "test_C0_matches_its_defining_integral"),
+    ("delta_e_sign", "return pref * sum_w - pref * sum_m - h3 * u[j];",
+     "return pref * sum_w - pref * sum_m + h3 * u[j];",
+     "test_delta_e_equals_energy_difference_of_a_flip"),
+    ("band_index", "label_at(s, phi, i, jj - 1, k) != me", "label_at(s, phi, i, jj - 2, k) != me",
+     "test_band_is_face_neighbour_disagreement"),
+    ("outside_is_solute", "if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 1;",
+     "if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return -1;",
+     "test_band_is_face_neighbour_disagreement"),
+    ("cell_centre_offset", "x[1] = s->center[1] - L + ((double)j + 0.5) * s->h;",
+     "x[1] = s->center[1] - L + ((double)j + 0.25) * s->h;",
+     "test_cube_symmetry_invariance_of_energy_and_forces"),
+    ("colour_period", "int p = (int)ceil(s->rho_s);\n    int64_t cap",
+     "int p = (int)ceil(s->rho_s) - 1;\n    int64_t cap",
+     "test_colour_pass_energy_change_is_sum_of_flip_changes"),
+    ("force_drops_dd_term", "double gx = -qn * (e[0] / r3 - 3.0 * ed * dx / r5);",
+     "double gx = -qn * (e[0] / r3);", "test_forces_match_central_differences"),
+    ("force_lj_factor", "double clj = s->rho_w * 24.0 * s->eps[nidx]",
+     "double clj = s->rho_w * 12.0 * s->eps[nidx]", "test_forces_match_central_differences"),
+    ("mobility_grows", "st->M *= st->alpha;", "st->M /= st->alpha;",
+     "test_adaptive_mobility_shrinks_after_an_overshoot"),
+    ("tight_radius_sign", "double v = sqrt(dx * dx + dy * dy + dz * dz) - d[i];",
+     "double v = sqrt(dx * dx + dy * dy + dz * dz) + d[i];",
+     "test_tight_start_of_centred_atom_is_the_loose_sphere"),
+    ("heap_keeps_stale_entries", "                    ++ver[c];\n", "",
+     "test_heap_and_colour_schedules_agree_on_single_atom"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake(name, old, new, pin, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation {name}: pattern must occur exactly once"
+    mutated = tmp_path / "vesis_oracle_mut.c"
+    mutated.write_text(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle import build as ob
+    lib = ob.build(src=str(mutated), lib=str(tmp_path / "liboracle_mut.so"))
+    env = dict(os.environ, VESIS_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        f"tests/test_oracle_pins.py::{pin}"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 1, f"{pin} did not catch {name}:\n{r.stdout[-2000:]}"

@@ -339,7 +339,7 @@ def test_heap_and_colour_schedules_agree_on_single_atom():
     a = s.init_loose(1.2)
     b = a.copy()
     s.minimize_colour(a, u)
-    rc, st = s.minimize_heap(b, u)
+    rc, st = s.minimize_heap(b, u, max_flips=s.ncell)
     assert rc == 0
     assert np.array_equal(a, b)
 
