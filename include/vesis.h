@@ -203,6 +203,36 @@ vesis_status vesis_forces(vesis_ctx* ctx, double* f_out);
  * ran out (positions unchanged) or the gradient is zero. */
 vesis_status vesis_atom_step(vesis_ctx* ctx, vesis_mobility* state, vesis_step_info* out);
 
+/* Options of the full alternation (Steps 1-5 of the algorithm): max_iters
+ * (k_max, 3000 in the paper), persist (consecutive iterations with a small
+ * energy change needed to stop, 100), max_sweeps (colour sweeps allowed per
+ * interface relaxation), tol_grad (Tol1: stop once every gradient component
+ * of the movable atoms is below it, 1e-4), tol_energy (Tol2: an iteration is
+ * "small" when the relative or the absolute change of G is below it, 1e-5). */
+typedef struct {
+    int32_t max_iters, persist, max_sweeps, reserved;
+    double tol_grad, tol_energy;
+} vesis_relax_opts;
+
+/* stop_reason: 1 gradient below tol_grad, 2 energy change small for
+ * `persist` iterations, 3 max_iters reached, 4 no acceptable step (mobility
+ * below M_min or retries exhausted). */
+typedef struct {
+    int32_t iters, stop_reason, sweeps, retries;
+    double G_final, max_grad, dG_abs, dG_rel;
+} vesis_relax_report;
+
+/* The paper's alternating minimisation (Sec. "Numerical Algorithm", Steps
+ * 2-5): each iteration relaxes the interface at fixed atoms
+ * (vesis_minimize_interface), tests the gradient (Step 3.2), takes one
+ * adaptive-mobility step at the fixed interface (vesis_atom_step, Steps
+ * 3.3-3.4) and tests the change of G against the previous iteration (Steps
+ * 4-5).  Labels and positions are updated in place; `state` carries the
+ * mobility across iterations (and across calls).  Returns VESIS_OK when a
+ * stopping rule fired, VESIS_NOT_CONVERGED when max_iters ran out. */
+vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* opts, vesis_mobility* state,
+                         vesis_relax_report* out);
+
 /* Copy the labels (n^3 int8, -1/+1) to host memory. */
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);
 

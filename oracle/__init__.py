@@ -44,6 +44,16 @@ class StepInfo(C.Structure):
                 ("max_grad", _D), ("omega", _D)]
 
 
+class RelaxOpts(C.Structure):
+    _fields_ = [("max_iters", _I32), ("persist", _I32), ("max_sweeps", _I32), ("pad", _I32),
+                ("tol_grad", _D), ("tol_energy", _D)]
+
+
+class RelaxReport(C.Structure):
+    _fields_ = [("iters", _I32), ("stop_reason", _I32), ("sweeps", _I32), ("retries", _I32),
+                ("G_final", _D), ("max_grad", _D), ("dG_abs", _D), ("dG_rel", _D)]
+
+
 def default_mobility(dt: float = 0.1) -> Mobility:
     return Mobility(M=1.0, alpha=2.0 ** -0.5, dt=dt, dG_frac=0.05, M_min=1e-12, G_old=0.0,
                     N_cnt=0, N_cnt_max=5, k=0, max_retries=200)
@@ -104,6 +114,9 @@ def lib():
         L.orc_atom_step.argtypes = [sp, _P, _P, _P, _I64, _P, _P, _P, C.POINTER(Mobility),
                                     C.POINTER(StepInfo)]
         L.orc_atom_step.restype = C.c_int
+        L.orc_relax.argtypes = [sp, _P, _P, _P, _I64, _P, _P, _P, C.POINTER(RelaxOpts),
+                                C.POINTER(Mobility), C.POINTER(RelaxReport)]
+        L.orc_relax.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -327,3 +340,12 @@ class System:
                                  _ptr(self.bonds), _ptr(self.bond_r0), _ptr(self.bond_k),
                                  C.byref(mobility), C.byref(info))
         return rc, xyz, info
+
+    def relax(self, xyz, phi, opts: RelaxOpts, mobility: Mobility, movable=None):
+        """Steps 2-5 of the algorithm; xyz and phi are updated in place."""
+        mv = None if movable is None else np.ascontiguousarray(movable, dtype=np.uint8)
+        rep = RelaxReport()
+        rc = lib().orc_relax(self.sref, _ptr(xyz), _ptr(phi), None if mv is None else _ptr(mv),
+                             len(self.bonds), _ptr(self.bonds), _ptr(self.bond_r0),
+                             _ptr(self.bond_k), C.byref(opts), C.byref(mobility), C.byref(rep))
+        return rc, rep

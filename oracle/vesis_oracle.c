@@ -842,3 +842,100 @@ int orc_atom_step(const orc_sys* s0, double* xyz, const int8_t* phi, const uint8
     free(trial);
     return rc;
 }
+
+/* ------------------------------------------------------ full alternation */
+
+typedef struct {
+    int32_t max_iters;   /* k_max (3000 in the paper) */
+    int32_t persist;     /* consecutive small energy changes needed (100) */
+    int32_t max_sweeps;  /* colour sweeps allowed per interface relaxation */
+    int32_t pad;
+    double tol_grad;     /* Tol1: stop when every |dG/dr| < tol_grad (1e-4) */
+    double tol_energy;   /* Tol2: small relative or absolute change (1e-5) */
+} orc_relax_opts;
+
+typedef struct {
+    int32_t iters;       /* outer iterations run */
+    int32_t stop_reason; /* 1 gradient, 2 energy change, 3 max_iters, 4 mobility */
+    int32_t sweeps;      /* colour sweeps over all iterations */
+    int32_t retries;     /* rejected trial steps over all iterations */
+    double G_final;
+    double max_grad;
+    double dG_abs;
+    double dG_rel;
+} orc_relax_report;
+
+/* The paper's algorithm, Steps 2-5: alternate the interface relaxation at
+ * fixed atoms (colour sweeps to a local minimum) with one adaptive-mobility
+ * atom step at the fixed interface; stop when every gradient component of
+ * the moving atoms is below tol_grad (Step 3.2), when the relative or the
+ * absolute change of G between iterations stays below tol_energy for
+ * `persist` iterations in a row (Step 5), after max_iters iterations, or
+ * when the mobility cannot find an acceptable step.  xyz and phi are
+ * updated in place; st carries the mobility state across iterations. */
+int orc_relax(const orc_sys* s0, double* xyz, int8_t* phi, const uint8_t* movable, int64_t nb,
+              const int32_t* ij, const double* r0, const double* kb, const orc_relax_opts* o,
+              orc_mobility* st, orc_relax_report* rep) {
+    orc_sys s = *s0;
+    s.xyz = xyz;
+    int64_t ncell = (int64_t)s.n * s.n * s.n, na = s.na;
+    double* ulj = malloc(sizeof(double) * (size_t)ncell);
+    double* ucfa = malloc(sizeof(double) * (size_t)ncell);
+    double* u = malloc(sizeof(double) * (size_t)ncell);
+    double* f = malloc(sizeof(double) * 3 * (size_t)na);
+    int calm = 0, reason = 3;
+    double G_prev = NAN;
+    memset(rep, 0, sizeof(*rep));
+    int k;
+    for (k = 0; k < o->max_iters; ++k) {
+        rep->iters = k + 1;
+        /* Step 2: interface at fixed atoms */
+        int64_t stats[6];
+        orc_density_grid(&s, ulj, ucfa, NULL);
+        for (int64_t c = 0; c < ncell; ++c) u[c] = ulj[c] + ucfa[c];
+        orc_minimize_colour(&s, phi, u, o->max_sweeps, 0.0, stats, NULL, NULL, 0);
+        rep->sweeps += (int32_t)stats[0];
+        /* Step 3.1-3.2: gradient test */
+        orc_forces(&s, phi, nb, ij, r0, kb, f);
+        double gmax = 0.0;
+        for (int64_t a = 0; a < na; ++a) {
+            if (movable && !movable[a]) continue;
+            for (int d = 0; d < 3; ++d)
+                if (fabs(f[3 * a + d]) > gmax) gmax = fabs(f[3 * a + d]);
+        }
+        rep->max_grad = gmax;
+        if (gmax < o->tol_grad) {
+            rep->G_final = orc_total_energy(&s, phi, nb, ij, r0, kb, NULL);
+            reason = 1;
+            break;
+        }
+        /* Step 3.3-3.4: one accepted step */
+        orc_step_info info;
+        int rc = orc_atom_step(&s, xyz, phi, movable, nb, ij, r0, kb, st, &info);
+        rep->retries += info.retries;
+        if (rc != 0) {
+            rep->G_final = info.G_old;
+            reason = 4;
+            break;
+        }
+        /* Steps 4-5: change of G between iterations */
+        double G = info.G_new;
+        rep->G_final = G;
+        if (!isnan(G_prev)) {
+            rep->dG_abs = fabs(G - G_prev);
+            rep->dG_rel = rep->dG_abs / fabs(G_prev);
+            if (rep->dG_rel < o->tol_energy || rep->dG_abs < o->tol_energy)
+                ++calm;
+            else
+                calm = 0;
+            if (calm >= o->persist) {
+                reason = 2;
+                break;
+            }
+        }
+        G_prev = G;
+    }
+    rep->stop_reason = reason;
+    free(ulj); free(ucfa); free(u); free(f);
+    return reason == 3 ? 1 : 0;
+}

@@ -22,6 +22,7 @@ EXPORTS = ["vesis_create", "vesis_destroy", "vesis_last_error", "vesis_set_param
            "vesis_set_grid", "vesis_set_atoms", "vesis_set_positions", "vesis_get_positions",
            "vesis_set_bonds", "vesis_workspace_size", "vesis_set_workspace", "vesis_init_labels",
            "vesis_minimize_interface", "vesis_energy", "vesis_forces", "vesis_atom_step",
+           "vesis_relax",
            "vesis_get_labels", "vesis_get_density", "vesis_profile", "vesis_profile_read"]
 
 
@@ -53,6 +54,17 @@ class Mobility(C.Structure):
 class StepInfo(C.Structure):
     _fields_ = [("accepted", C.c_int32), ("retries", C.c_int32), ("G_old", C.c_double),
                 ("G_new", C.c_double), ("max_grad", C.c_double), ("omega", C.c_double)]
+
+
+class RelaxOpts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("persist", C.c_int32), ("max_sweeps", C.c_int32),
+                ("reserved", C.c_int32), ("tol_grad", C.c_double), ("tol_energy", C.c_double)]
+
+
+class RelaxReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("stop_reason", C.c_int32), ("sweeps", C.c_int32),
+                ("retries", C.c_int32), ("G_final", C.c_double), ("max_grad", C.c_double),
+                ("dG_abs", C.c_double), ("dG_rel", C.c_double)]
 
 
 _lib = None
@@ -94,6 +106,7 @@ def load():
     L.vesis_energy.argtypes = [P, C.POINTER(EnergyParts)]
     L.vesis_forces.argtypes = [P, P]
     L.vesis_atom_step.argtypes = [P, C.POINTER(Mobility), C.POINTER(StepInfo)]
+    L.vesis_relax.argtypes = [P, C.POINTER(RelaxOpts), C.POINTER(Mobility), C.POINTER(RelaxReport)]
     L.vesis_get_labels.argtypes = [P, P]
     L.vesis_get_density.argtypes = [P, P, P, P]
     L.vesis_profile.argtypes = [P, I32]

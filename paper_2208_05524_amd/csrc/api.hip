@@ -64,7 +64,7 @@ struct Layout {
     size_t pos, prm64, prm32, pos_stage;
     size_t boff, bother, br0, bk;
     size_t ulj, ucfa, ex, ey, ez, bound, u64cache;
-    size_t bits;
+    size_t bits, stamp;
     size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez, far_part;
     size_t red_d, red_i, scal_d, scal_i, sweep_flips;
     size_t fpart, fout;
@@ -288,6 +288,7 @@ Layout plan(const vesis_ctx* c) {
     L.bound = take(8 * ncell);
     L.u64cache = take(16 * ncell);
     L.bits = take(4 * c->g.nwords());
+    L.stamp = take(4 * c->g.nwords());
     L.far_pts = take(32 * nfar);
     L.far_ulj = take(8 * nfar);
     L.far_ucfa = take(8 * nfar);
@@ -793,6 +794,9 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
     int* flips = at<int>(ctx, ctx->lay.sweep_flips);
     int64_t* counters = at<int64_t>(ctx, ctx->lay.scal_i) + SI_CNT;
     CK(launch_fill_i64(counters, 2, 0, st));
+    int* stamp = at<int>(ctx, ctx->lay.stamp);
+    CK(launch_fill_u32(reinterpret_cast<uint32_t*>(stamp), ctx->g.nwords(),
+                       (uint32_t)(-(1 << 30)), st));
     int64_t total_flips = 0;
     int sweeps = 0;
     bool converged = false;
@@ -803,8 +807,9 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
             Timed t(ctx, K_FLIP);
             for (int sw = 0; sw < nb; ++sw)
                 for (int c = 0; c < ncol; ++c)
-                    CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw, bits,
-                                        at<double>(ctx, ctx->lay.ulj), at<double>(ctx, ctx->lay.ucfa),
+                    CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw, (sweeps + sw) * ncol + c,
+                                        bits, stamp, at<double>(ctx, ctx->lay.ulj),
+                                        at<double>(ctx, ctx->lay.ucfa),
                                         at<double>(ctx, ctx->lay.bound),
                                         at<double>(ctx, ctx->lay.u64cache), flips, counters, st));
         }
@@ -918,6 +923,72 @@ vesis_status vesis_atom_step(vesis_ctx* ctx, vesis_mobility* st, vesis_step_info
             return fail(ctx, VESIS_NOT_CONVERGED, "mobility fell below M_min or retries ran out");
         }
     }
+}
+
+vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* o, vesis_mobility* st,
+                         vesis_relax_report* rep) {
+    if (!ctx || !o || !st || !rep) return fail(ctx, VESIS_E_ARG, "null argument");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    if (o->max_iters < 1 || o->persist < 1 || o->max_sweeps < 1 || !(o->tol_grad >= 0) ||
+        !(o->tol_energy >= 0))
+        return fail(ctx, VESIS_E_ARG, "bad relax options");
+    std::memset(rep, 0, sizeof(*rep));
+    const int64_t n = ctx->na;
+    std::vector<double> f(3 * n);
+    double G_prev = NAN;
+    int calm = 0, reason = 3;
+    for (int k = 0; k < o->max_iters; ++k) {
+        rep->iters = k + 1;
+        // Step 2: interface at fixed atoms
+        vesis_min_stats ms{};
+        s = vesis_minimize_interface(ctx, o->max_sweeps, &ms);
+        if (s < 0) return s;
+        rep->sweeps += ms.sweeps;
+        // Steps 3.1-3.2: gradient test
+        s = vesis_forces(ctx, f.data());
+        if (s < 0) return s;
+        double gmax = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!ctx->movable[i]) continue;
+            for (int d = 0; d < 3; ++d) gmax = std::max(gmax, std::fabs(f[3 * i + d]));
+        }
+        rep->max_grad = gmax;
+        if (gmax < o->tol_grad) {
+            vesis_energy_parts e{};
+            s = compute_energy(ctx, &e);
+            if (s < 0) return s;
+            rep->G_final = e.total;
+            reason = 1;
+            break;
+        }
+        // Steps 3.3-3.4: one accepted step
+        vesis_step_info info{};
+        s = vesis_atom_step(ctx, st, &info);
+        if (s < 0) return s;
+        rep->retries += info.retries;
+        if (s == VESIS_NOT_CONVERGED) {
+            rep->G_final = info.G_old;
+            reason = 4;
+            break;
+        }
+        // Steps 4-5: change of G between iterations
+        const double G = info.G_new;
+        rep->G_final = G;
+        if (!std::isnan(G_prev)) {
+            rep->dG_abs = std::fabs(G - G_prev);
+            rep->dG_rel = rep->dG_abs / std::fabs(G_prev);
+            calm = (rep->dG_rel < o->tol_energy || rep->dG_abs < o->tol_energy) ? calm + 1 : 0;
+            if (calm >= o->persist) {
+                reason = 2;
+                break;
+            }
+        }
+        G_prev = G;
+    }
+    rep->stop_reason = reason;
+    ctx->err.clear();
+    return reason == 3 ? VESIS_NOT_CONVERGED : VESIS_OK;
 }
 
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out) {

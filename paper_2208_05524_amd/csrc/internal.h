@@ -89,10 +89,12 @@ hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream
 hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
                              hipStream_t st);
 // u64cache: 2 x ncell FP64 (LJ parts, then CFA parts; NaN = not computed).
+// gpass: pass index within the current minimisation call (sweep * p^3 + colour);
+// stamp: one int per label word, filled with a value < -p^3 before the call.
 hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
-                            int colour, int sweep, uint32_t* bits, const double* ulj,
-                            const double* ucfa, const double* bound, double* u64cache,
-                            int* sweep_flips, int64_t* counters, hipStream_t st);
+                            int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
+                            const double* ulj, const double* ucfa, const double* bound,
+                            double* u64cache, int* sweep_flips, int64_t* counters, hipStream_t st);
 hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
                                 const double* ucfa, double* partial, int nblocks, double* out,
                                 hipStream_t st);

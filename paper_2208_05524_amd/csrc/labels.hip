@@ -12,8 +12,8 @@
 // computed exactly as sum over squared offsets s of w_s * n_s with integer
 // counts n_s = #solvent - #solute, read from 5-bit windows of 25 neighbour
 // rows.  A candidate whose |Delta E| lies within h^3 times the density error
-// bound is a near tie: the wavefront recomputes U_j in FP64 (each lane a
-// strided share of the atoms, fixed butterfly sum), caches it, and decides.
+// bound is a near tie: the workgroup recomputes U_j in FP64 (each thread a
+// strided share of the atoms, fixed tree sum), caches it, and decides.
 // Cells of one colour lie outside each other's kernel support, so all
 // decisions of a pass read only labels that the pass does not change.
 #include "internal.h"
@@ -208,17 +208,19 @@ __device__ inline double stencil_sum(const Stencil& sc, const Rows25& R, int b) 
     return S;
 }
 
-// FP64 density parts at cell (x, y, z), summed by one wavefront: lane l takes
-// atoms l, l + 64, ...; the partial sums meet in a fixed xor butterfly, so
-// every lane ends with the same bits.
-__device__ inline void wave_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
-                                        int y, int z, double& u_lj, double& u_cfa) {
-    const int lane = threadIdx.x & 63;
+constexpr int FWG = 256;  // flip-pass workgroup: four wavefronts
+
+// FP64 density parts at cell (x, y, z), summed by the whole workgroup:
+// thread t takes atoms t, t + FWG, ...; the partial sums meet in a fixed
+// tree in LDS, so the result does not depend on timing.  All threads call.
+__device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
+                                         int y, int z, double* sh, double& u_lj, double& u_cfa) {
+    const int t = threadIdx.x;
     const double px = centre_coord(g.cx, g.L, x, g.h);
     const double py = centre_coord(g.cy, g.L, y, g.h);
     const double pz = centre_coord(g.cz, g.L, z, g.h);
     double lj = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-    for (int64_t i = lane; i < a.n; i += 64) {
+    for (int64_t i = t; i < a.n; i += FWG) {
         const double4 p = a.pos[i];
         const double4 q = a.prm64[i];
         const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
@@ -236,44 +238,46 @@ __device__ inline void wave_density_f64(const Grid& g, const Atoms& a, const Phy
         ey += f * dy;
         ez += f * dz;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lj += __shfl_xor(lj, off);
-        ex += __shfl_xor(ex, off);
-        ey += __shfl_xor(ey, off);
-        ez += __shfl_xor(ez, off);
-    }
-    u_lj = lj;
-    u_cfa = ph.ccfa * (ex * ex + ey * ey + ez * ez);
-}
-
-// FP64 parts of cell c from the cache (2 x ncell doubles: LJ, then CFA; NaN =
-// not yet computed), computing and caching them if needed.  Whole wavefront.
-__device__ inline void cached_f64(const Grid& g, const Atoms& a, const Physics& ph, int x, int y,
-                                  int z, double* cache, int64_t* counters, double& lj,
-                                  double& cfa) {
-    const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-    lj = cache[c];
-    cfa = cache[g.ncell() + c];
-    if (isnan(lj)) {
-        wave_density_f64(g, a, ph, x, y, z, lj, cfa);
-        if ((threadIdx.x & 63) == 0) {
-            cache[c] = lj;
-            cache[g.ncell() + c] = cfa;
-            atomicAdd((unsigned long long*)&counters[1], 1ull);
+    sh[t] = lj;
+    sh[FWG + t] = ex;
+    sh[2 * FWG + t] = ey;
+    sh[3 * FWG + t] = ez;
+    __syncthreads();
+    for (int st = FWG / 2; st > 0; st >>= 1) {
+        if (t < st) {
+            sh[t] += sh[t + st];
+            sh[FWG + t] += sh[FWG + t + st];
+            sh[2 * FWG + t] += sh[2 * FWG + t + st];
+            sh[3 * FWG + t] += sh[3 * FWG + t + st];
         }
+        __syncthreads();
     }
+    u_lj = sh[0];
+    ex = sh[FWG];
+    ey = sh[2 * FWG];
+    ez = sh[3 * FWG];
+    u_cfa = ph.ccfa * (ex * ex + ey * ey + ez * ez);
+    __syncthreads();
 }
 
 // --------------------------------------------------------------- flip pass
 
-constexpr int FWG = 64;  // one wavefront per workgroup
-
+// Activity stamps (one int per label word): a lane that flips cells of word
+// (w, y, z) in global pass P writes P into the words w-1..w+1 of the rows
+// y-2..y+2, z-2..z+2, which hold every cell whose flip energy or band status
+// that flip can change.  The previous evaluation of a word in this colour was
+// pass P - ncol; if its stamp is older than that, nothing in its cells'
+// neighbourhoods changed since then, every decision would repeat (no flip),
+// and the word is skipped.  The first sweep of a call evaluates every word.
 __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atoms a, Physics ph,
-                                                        int colour, int sweep, uint32_t* bits,
+                                                        int colour, int sweep, int gpass, int ncol,
+                                                        uint32_t* bits, int* stamp,
                                                         const double* ulj, const double* ucfa,
                                                         const double* bound, double* u64cache,
                                                         int* sweep_flips, int64_t* counters) {
+    __shared__ double s_red[4 * FWG];
+    __shared__ int s_leader;
+    __shared__ int s_tie[4];
     // a sweep that follows a sweep without flips has nothing to do
     if (sweep > 0 && sweep_flips[sweep - 1] == 0) return;
     const int p = sc.p;
@@ -292,7 +296,8 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
     const int x0 = 32 * w;
     uint32_t* rowc = bits + g.row(y, z);
     uint32_t C = 0, cand = 0;
-    if (active) {
+    const bool stale = gpass >= ncol && stamp[g.row(y, z) + 1 + w] < gpass - ncol;
+    if (active && !stale) {
         C = rowc[w + 1];
         const uint32_t Lw = rowc[w], Rw = rowc[w + 2];
         const uint32_t left = (C << 1) | (Lw >> 31);
@@ -323,20 +328,35 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
                 flipmask |= 1u << b;
         }
     }
-    // near ties: the whole wavefront resolves them one at a time in FP64
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        const uint64_t bal = __ballot(tiemask != 0u);
-        if (bal == 0) break;
-        const int leader = __ffsll((unsigned long long)bal) - 1;
-        const int lb = tiemask ? __ffs(tiemask) - 1 : 0;
-        const int bL = __shfl(lb, leader);
-        const int xL = __shfl(x0, leader) + bL;
-        const int yL = __shfl(y, leader);
-        const int zL = __shfl(z, leader);
-        double lj, cfa;
-        cached_f64(g, a, ph, xL, yL, zL, u64cache, counters, lj, cfa);
-        if (lane == leader) {
+    // near ties: the whole workgroup resolves them one at a time in FP64,
+    // lowest thread first; each cell's FP64 parts are computed once per atom
+    // configuration and cached (2 x ncell doubles: LJ, then CFA; NaN = none)
+    const int t = threadIdx.x;
+    while (__syncthreads_or(tiemask != 0u)) {
+        if (t == 0) s_leader = FWG;
+        __syncthreads();
+        if (tiemask) atomicMin(&s_leader, t);
+        __syncthreads();
+        const int leader = s_leader;
+        if (t == leader) {
+            s_tie[0] = __ffs(tiemask) - 1;
+            s_tie[1] = y;
+            s_tie[2] = z;
+            s_tie[3] = x0;
+        }
+        __syncthreads();
+        const int bL = s_tie[0], yL = s_tie[1], zL = s_tie[2], xL = s_tie[3] + bL;
+        const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
+        double lj = u64cache[cL], cfa = u64cache[g.ncell() + cL];
+        if (isnan(lj)) {  // same value for every thread
+            block_density_f64(g, a, ph, xL, yL, zL, s_red, lj, cfa);
+            if (t == leader) {
+                u64cache[cL] = lj;
+                u64cache[g.ncell() + cL] = cfa;
+                atomicAdd((unsigned long long*)&counters[1], 1ull);
+            }
+        }
+        if (t == leader) {
             const double S = stencil_sum(sc, R, bL);
             const double phi = ((C >> bL) & 1u) ? 1.0 : -1.0;
             const double dE = phi * (sc.c * S - ph.h3 * (lj + cfa));
@@ -345,11 +365,20 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
             atomicAdd((unsigned long long*)&counters[0], 1ull);
         }
     }
-    if (flipmask) rowc[w + 1] = C ^ flipmask;
+    if (flipmask) {
+        rowc[w + 1] = C ^ flipmask;
+        for (int dz = -2; dz <= 2; ++dz)
+            for (int dy = -2; dy <= 2; ++dy) {
+                int* sr = stamp + g.row(y + dy, z + dz) + w;
+                sr[0] = gpass;
+                sr[1] = gpass;
+                sr[2] = gpass;
+            }
+    }
     int nf = __popc(flipmask);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) nf += __shfl_xor(nf, off);
-    if (lane == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
+    if ((t & 63) == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
 }
 
 // ------------------------------------------------------------ reductions
@@ -489,16 +518,17 @@ hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32
 }
 
 hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
-                            int colour, int sweep, uint32_t* bits, const double* ulj,
-                            const double* ucfa, const double* bound, double* u64cache,
-                            int* sweep_flips, int64_t* counters, hipStream_t st) {
+                            int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
+                            const double* ulj, const double* ucfa, const double* bound,
+                            double* u64cache, int* sweep_flips, int64_t* counters, hipStream_t st) {
     const int p = sc.p;
     const int cb = (colour / p) % p, cc = colour / (p * p);
     const int64_t ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
     const int64_t total = (int64_t)g.nwin * ny * nz;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(flip_pass_kernel, dim3(nblk(total, FWG)), dim3(FWG), 0, st, g, sc, a, ph,
-                       colour, sweep, bits, ulj, ucfa, bound, u64cache, sweep_flips, counters);
+                       colour, sweep, gpass, p * p * p, bits, stamp, ulj, ucfa, bound, u64cache,
+                       sweep_flips, counters);
     return hipGetLastError();
 }
 

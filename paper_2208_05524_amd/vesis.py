@@ -11,7 +11,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import EnergyParts, MinStats, Mobility, Params, StepInfo, VesisError
+from ._lib import (EnergyParts, MinStats, Mobility, Params, RelaxOpts, RelaxReport, StepInfo,
+                   VesisError)
 
 KERNEL_KINDS = {"density": 0, "far_field": 1, "init": 2, "flip": 3, "energy": 4, "force": 5,
                 "other": 6}
@@ -165,6 +166,16 @@ class Context:
         rc = self._check(self.lib.vesis_atom_step(self.h, C.byref(mobility), C.byref(info)),
                          allow=(0, 1))
         return rc, info
+
+    def relax(self, mobility: Mobility, max_iters: int = 3000, persist: int = 100,
+              max_sweeps: int = 20000, tol_grad: float = 1e-4, tol_energy: float = 1e-5):
+        """Steps 2-5 of the paper's algorithm (interface and atoms alternately)."""
+        opts = RelaxOpts(max_iters=max_iters, persist=persist, max_sweeps=max_sweeps, reserved=0,
+                         tol_grad=tol_grad, tol_energy=tol_energy)
+        rep = RelaxReport()
+        rc = self._check(self.lib.vesis_relax(self.h, C.byref(opts), C.byref(mobility),
+                                              C.byref(rep)), allow=(0, 1))
+        return rc, rep
 
     def labels(self) -> np.ndarray:
         out = np.zeros(self.n ** 3, np.int8)

@@ -61,7 +61,12 @@ def test_full_size_density_inside_bound_everywhere(full):
     err = np.abs((full["g_ulj"] + full["g_ucfa"]) - (full["o_ulj"] + full["o_ucfa"]))
     b = full["g_bound"]
     fin = np.isfinite(b)
-    log("cells with a bound:", fin.mean(), "max err/bound", float((err[fin] / b[fin]).max()))
+    ratio = err / b
+    worst = int(np.argmax(ratio))
+    x = full["s"].cell_center(worst)
+    dmin = float(np.sqrt(((full["w"].xyz - x) ** 2).sum(1)).min())
+    log("cells with a bound:", fin.mean(), "max err/bound", float(ratio[worst]),
+        "at cell", worst, "nearest atom", dmin, "nm")
     assert np.all(err <= b)
 
 

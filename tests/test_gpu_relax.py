@@ -1,0 +1,157 @@
+"""The full alternation (Steps 2-5 of the algorithm) and the autograd
+wrapper on the GPU, against the oracle and the paper's two-atom tables."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import force_close, gpu_context, log, oracle_system
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _small_bonded(seed):
+    w = synth.random_small(24, 30, seed, h=0.07)
+    ij = np.array([[i, i + 1] for i in range(0, 29, 2)], np.int32)
+    w.bonds, w.bond_r0, w.bond_k = ij, np.full(len(ij), 0.2), np.full(len(ij), 500.0)
+    return w
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_relax_matches_oracle(precision):
+    """Eight outer iterations from a tight start: same iteration and retry
+    counts, positions within 1e-6 nm, labels identical, G within 1e-6."""
+    w = _small_bonded(seed=21)
+    s = oracle_system(w, with_bonds=True)
+    phi = s.init_tight()
+    ctx = gpu_context(w, precision=precision, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    from paper_2208_05524_amd import default_mobility
+    xo = w.xyz.copy()
+    opts = oracle.RelaxOpts(max_iters=8, persist=100, max_sweeps=10000, pad=0, tol_grad=1e-4,
+                            tol_energy=1e-5)
+    rc_o, ro = s.relax(xo, phi, opts, oracle.default_mobility(0.1))
+    mg = default_mobility(0.1)
+    rc_g, rg = ctx.relax(mg, max_iters=8, persist=100, max_sweeps=10000)
+    log("oracle", ro.iters, ro.stop_reason, ro.sweeps, ro.retries, ro.G_final,
+        "gpu", rg.iters, rg.stop_reason, rg.sweeps, rg.retries, rg.G_final)
+    assert rc_o == rc_g
+    assert (ro.iters, ro.stop_reason, ro.retries) == (rg.iters, rg.stop_reason, rg.retries)
+    assert rg.G_final == pytest.approx(ro.G_final, rel=1e-6)
+    np.testing.assert_allclose(ctx.positions(), xo, rtol=0, atol=1e-6)
+    assert np.array_equal(ctx.labels(), phi)
+    assert ro.sweeps == rg.sweeps
+
+
+def test_relax_two_atoms_reaches_paper_state():
+    """Experiment with r0 = 8 A (paper units): bond 8.00 A, atoms at +-4.00
+    A, G within 3 % of the printed 33.93 k_B T, and within 1e-6 of the
+    oracle's alternation from the same start."""
+    with open(os.path.join(HERE, "golden", "two_atom_tables.json")) as f:
+        g = json.load(f)
+    m = g["model"]
+    w = synth.Workload(name="two_atoms_r0_8", n=48, h=16.0 / 48, center=np.zeros(3),
+                       xyz=np.array([[7.0, 0.0, 0.0], [-7.0, 0.0, 0.0]]), q=np.zeros(2),
+                       sigma=np.full(2, m["sigma"]), eps=np.full(2, m["eps"]),
+                       params=synth.paper_units_params(), init_mode="tight", init_param=1.0,
+                       precision=64, bonds=np.array([[0, 1]], np.int32),
+                       bond_r0=np.array([8.0]), bond_k=np.array([m["bond_A"]]))
+    ctx = gpu_context(w, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    from paper_2208_05524_amd import default_mobility
+    rc, rep = ctx.relax(default_mobility(1.0), max_iters=3000, persist=100, max_sweeps=10000)
+    x = ctx.positions()
+    log("gpu relax", rc, rep.iters, rep.stop_reason, rep.G_final, x[:, 0])
+    assert rc == 0 and rep.stop_reason in (1, 2)
+    assert np.linalg.norm(x[0] - x[1]) == pytest.approx(8.0, abs=0.02)
+    np.testing.assert_allclose(x, g["r0_8"]["final_positions"], atol=0.05)
+    assert rep.G_final == pytest.approx(g["r0_8"]["free_energy"], rel=0.03)
+    s = oracle_system(w, with_bonds=True)
+    xo = w.xyz.copy()
+    phi = s.init_tight()
+    opts = oracle.RelaxOpts(max_iters=3000, persist=100, max_sweeps=10000, pad=0,
+                            tol_grad=1e-4, tol_energy=1e-5)
+    _, ro = s.relax(xo, phi, opts, oracle.default_mobility(1.0))
+    log("oracle relax", ro.iters, ro.stop_reason, ro.G_final, xo[:, 0])
+    assert rep.iters == ro.iters
+    assert rep.G_final == pytest.approx(ro.G_final, rel=1e-6)
+    np.testing.assert_allclose(x, xo, rtol=0, atol=1e-6)
+
+
+def test_autograd_gradient_matches_oracle_forces():
+    """free_energy(...).backward() gives dG/dX = -F of the oracle."""
+    import torch
+
+    from paper_2208_05524_amd.autograd import free_energy
+    w = _small_bonded(seed=22)
+    s = oracle_system(w, with_bonds=True)
+    phi = s.init_tight()
+    ctx = gpu_context(w, with_bonds=True)
+    ctx.init_labels("user", user=phi)
+    x = torch.tensor(w.xyz, dtype=torch.float64, device="cuda", requires_grad=True)
+    G = free_energy(ctx, x)
+    G.backward()
+    ref = s.total_energy(phi)["total"]
+    assert float(G) == pytest.approx(ref, rel=1e-6)
+    fo = s.forces(phi)
+    ok, rel = force_close(-x.grad.cpu().numpy(), fo, 1e-4)
+    log("autograd grad max rel err", float(rel.max()))
+    assert ok.all()
+
+
+def test_autograd_gradient_matches_central_differences():
+    """FP64 densities, fixed labels: the backward pass agrees with central
+    differences of the forward pass (step 1e-4 nm) on four atoms."""
+    import torch
+
+    from paper_2208_05524_amd.autograd import free_energy
+    w = _small_bonded(seed=23)
+    ctx = gpu_context(w, precision=64, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    x = torch.tensor(w.xyz, dtype=torch.float64, device="cuda", requires_grad=True)
+    G = free_energy(ctx, x)
+    G.backward()
+    grad = x.grad.cpu().numpy()
+    hfd = 1e-4
+    scale = np.abs(grad).max()
+    for a in (0, 7, 15, 29):
+        for d in range(3):
+            xp = w.xyz.copy()
+            xp[a, d] += hfd
+            xm = w.xyz.copy()
+            xm[a, d] -= hfd
+            gp = float(free_energy(ctx, torch.tensor(xp, device="cuda")))
+            gm = float(free_energy(ctx, torch.tensor(xm, device="cuda")))
+            fd = (gp - gm) / (2 * hfd)
+            assert fd == pytest.approx(grad[a, d], rel=1e-4, abs=1e-6 * scale), (a, d)
+
+
+def test_autograd_descent_lowers_the_energy():
+    """Plain gradient descent with torch.optim.SGD on G, the interface
+    relaxed at every evaluation (Step 2 inside each step), lowers G; the
+    learning rate makes the first step move no atom more than 2e-3 nm."""
+    import torch
+
+    from paper_2208_05524_amd.autograd import free_energy
+    w = _small_bonded(seed=24)
+    ctx = gpu_context(w, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    x = torch.tensor(w.xyz, dtype=torch.float64, device="cuda", requires_grad=True)
+    G = free_energy(ctx, x, relax_interface=True)
+    G.backward()
+    lr = 2e-3 / float(x.grad.abs().max())
+    opt = torch.optim.SGD([x], lr=lr)
+    hist = [float(G)]
+    for _ in range(6):
+        opt.step()
+        opt.zero_grad()
+        G = free_energy(ctx, x, relax_interface=True)
+        G.backward()
+        hist.append(float(G))
+    log("descent", hist)
+    assert hist[-1] < hist[0]

@@ -52,6 +52,9 @@ MUTATIONS = [
      "test_tight_start_of_centred_atom_is_the_loose_sphere"),
     ("heap_keeps_stale_entries", "                    ++ver[c];\n", "",
      "test_heap_and_colour_schedules_agree_on_single_atom"),
+    ("relax_skips_interface",
+     "        orc_minimize_colour(&s, phi, u, o->max_sweeps, 0.0, stats, NULL, NULL, 0);\n", "",
+     "test_paper_two_atom_relaxation_reaches_printed_state"),
 ]
 
 

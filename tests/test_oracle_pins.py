@@ -528,3 +528,31 @@ def test_adaptive_mobility_shrinks_after_an_overshoot():
     assert mob.M == pytest.approx(8.0 * (2 ** -0.5) ** info.retries)
     assert mob.N_cnt == 1
     assert info.G_new <= info.G_old + 0.05 * abs(info.G_old)
+
+
+# ------------------------------------------------------- full alternation
+
+@pytest.mark.parametrize("case", ["r0_8", "r0_3"])
+def test_paper_two_atom_relaxation_reaches_printed_state(case):
+    """Steps 2-5 of the algorithm on the paper's two-atom molecule (Tables
+    for experiments 1.1 and 1.2): starting 14 A apart, the alternation of
+    interface sweeps and adaptive-mobility atom steps ends with the bond at
+    the printed length, the atoms placed symmetrically about the box centre
+    as printed, and G within 3 % of the printed free energy (the paper's
+    grid is not stated; here 48^3 cells over (-8, 8)^3 A)."""
+    g = _golden()
+    m = g["model"]
+    r0 = g[case]["bond_length"]
+    xyz = np.array([[7.0, 0.0, 0.0], [-7.0, 0.0, 0.0]])
+    s = oracle.System(48, 16.0 / 48, np.zeros(3), xyz, [0, 0], [m["sigma"]] * 2, [m["eps"]] * 2,
+                      synth.paper_units_params(), np.array([[0, 1]], np.int32),
+                      np.array([r0]), np.array([m["bond_A"]]))
+    phi = s.init_tight()
+    x = xyz.copy()
+    opts = oracle.RelaxOpts(max_iters=3000, persist=100, max_sweeps=10000, pad=0,
+                            tol_grad=1e-4, tol_energy=1e-5)
+    rc, rep = s.relax(x, phi, opts, oracle.default_mobility(dt=1.0))
+    assert rc == 0 and rep.stop_reason in (1, 2)
+    assert np.linalg.norm(x[0] - x[1]) == pytest.approx(r0, abs=0.02)
+    np.testing.assert_allclose(x, g[case]["final_positions"], atol=0.05)
+    assert rep.G_final == pytest.approx(g[case]["free_energy"], rel=0.03)
