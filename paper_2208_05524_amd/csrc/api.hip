@@ -67,9 +67,9 @@ struct Layout {
     size_t bits, stamp;
     size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez, far_part;
     size_t red_d, red_i, scal_d, scal_i, sweep_flips;
-    size_t fpart, fout;
+    size_t fpart, fstage, fcount, fout;
     size_t total;
-    int64_t fchunks;
+    ForceSizes fsz;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -301,8 +301,10 @@ Layout plan(const vesis_ctx* c) {
     L.scal_d = take(8 * 16);
     L.scal_i = take(8 * 16);
     L.sweep_flips = take(4 * SWEEP_BATCH);
-    L.fchunks = force_partial_chunks(c->g, na, nfar);
-    L.fpart = take(8 * 3 * (size_t)L.fchunks * na);
+    L.fsz = force_sizes(c->g, na, nfar);
+    L.fpart = take(8 * (size_t)L.fsz.partial_doubles);
+    L.fstage = take(L.fsz.staged_bytes);
+    L.fcount = take(4 * (size_t)L.fsz.counts);
     L.fout = take(8 * 3 * na);
     L.total = o;
     return L;
@@ -449,6 +451,12 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     return VESIS_OK;
 }
 
+ForceScratch force_scratch(vesis_ctx* ctx) {
+    const Layout& L = ctx->lay;
+    return ForceScratch{at<double>(ctx, L.fpart), L.fsz.partial_doubles, ctx->ws + L.fstage,
+                        L.fsz.staged_bytes, at<int>(ctx, L.fcount), L.fsz.counts};
+}
+
 vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
     vesis_status s = ensure_density(ctx);
     if (s != VESIS_OK) return s;
@@ -461,8 +469,8 @@ vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
                          at<double>(ctx, ctx->lay.ey), at<double>(ctx, ctx->lay.ez),
                          at<double4>(ctx, ctx->lay.far_pts), at<double>(ctx, ctx->lay.far_ex),
                          at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
-                         ctx->nfar, dev_bonds(ctx), at<double>(ctx, ctx->lay.fpart),
-                         ctx->lay.fchunks, at<double>(ctx, ctx->lay.fout), st));
+                         ctx->nfar, dev_bonds(ctx), force_scratch(ctx),
+                         at<double>(ctx, ctx->lay.fout), st));
         ctx->forces_valid = true;
     }
     CK(hipMemcpyAsync(f_host, ctx->ws + ctx->lay.fout, 24 * ctx->na, hipMemcpyDeviceToHost, st));

@@ -10,35 +10,53 @@
 // of the discrete energy; E_j comes from the density kernel).  Within the
 // r2_min floor the LJ part is constant and E_n = Q_n d / r_min^3.
 //
-// Layout: a workgroup owns 256 atoms (one per lane) and one chunk of cells
-// (a cubic brick of the grid, or a run of far-field nodes).  Cells stream
-// through LDS 256 at a time; the solvent cells of a tile (w != 0) are
-// compacted in cell order (wave ballots, so the summation order is fixed)
-// and staged once as (position relative to the chunk centre, w, w E) in FP32,
-// read by broadcast; every lane keeps FP32 partials per tile folded into
-// FP64.  Per pair the LJ term and the (E.d) d part of the CFA term share one
-// coefficient along d, the E/r^3 part is summed separately.  Each (chunk, atom) pair writes one
-// FP64 partial gradient; a second kernel sums the chunks of each atom in a
-// fixed order and adds the bond terms, so the result is deterministic.
+// Layout.  A staging kernel first compacts, per chunk of cells (a cubic
+// 16^3 brick of the grid, or a run of 4096 far-field nodes), the cells with
+// nonzero weight in cell order, as (position relative to the chunk centre,
+// w) and w E in the working precision; it writes the count per chunk.  The
+// force kernel gives a workgroup 256 atoms (one per lane) and a group of
+// consecutive chunks; the staged cells of each chunk stream through a
+// double-buffered LDS tile of 256 (the next tile is fetched into registers
+// while the current one is summed, one barrier per tile) and are read by
+// broadcast.  Every lane keeps FP32 partials per tile, folded into FP64.  Per
+// pair the LJ term and the (E.d) d part of the CFA term share one
+// coefficient along d; the E/r^3 part is summed separately.  The r2_min
+// floor can only bind for an atom within the chunk's extent (plus a margin):
+// waves with no such atom take a loop without the floor test.  Each
+// (chunk group, atom) pair writes one FP64 partial gradient; a second kernel
+// sums the groups of each atom in a fixed order and adds the bond terms, so
+// the result is deterministic.
 #include "internal.h"
 #include "reduce.h"
 
 namespace vesis {
 namespace {
 
-constexpr int AWG = 256;   // atoms per workgroup
-constexpr int CT = 256;    // cells per LDS tile
-constexpr int FAR_TILES = 16;
+constexpr int AWG = 256;        // atoms per workgroup
+constexpr int CT = 256;         // staged cells per LDS tile
+constexpr int CB = 16;          // grid chunk edge (cells)
+constexpr int CB3 = CB * CB * CB;
+constexpr int FAR_CHUNK = 4096; // far-field nodes per chunk
+constexpr int GROUP = 4;        // chunks per force workgroup
+constexpr int RSPLIT = 8;       // group slices per atom in the reduction
+constexpr int RATOMS = 32;      // atoms per reduction workgroup
 
-int chunk_edge(int n, int64_t natoms) {
-    const int64_t ablk = (natoms + AWG - 1) / AWG;
-    int cb = 64;
-    while (cb > 8) {
-        const int64_t nc = (int64_t)((n + cb - 1) / cb) * ((n + cb - 1) / cb) * ((n + cb - 1) / cb);
-        if (nc * ablk >= 2048) break;
-        cb /= 2;
-    }
-    return cb;
+struct ChunkPlan {
+    int ncx;              // grid chunks per axis
+    int64_t ngrid;        // grid chunks
+    int64_t nfar_chunks;  // far-field chunks
+    int64_t nchunks() const { return ngrid + nfar_chunks; }
+    int64_t ngroups() const { return (nchunks() + GROUP - 1) / GROUP; }
+    // staged slots (each slot is two 4-vectors)
+    int64_t slots() const { return ngrid * CB3 + nfar_chunks * FAR_CHUNK; }
+};
+
+ChunkPlan chunk_plan(int n, int64_t nfar) {
+    ChunkPlan p;
+    p.ncx = (n + CB - 1) / CB;
+    p.ngrid = (int64_t)p.ncx * p.ncx * p.ncx;
+    p.nfar_chunks = (nfar + FAR_CHUNK - 1) / FAR_CHUNK;
+    return p;
 }
 
 struct ForceArgs {
@@ -54,10 +72,12 @@ struct ForceArgs {
     const double* far_ey;
     const double* far_ez;
     int64_t nfar;
-    int cb;          // grid chunk edge
-    int ncx;         // grid chunks per axis
-    int64_t ngrid_chunks;
-    double* partial; // [chunk][atom][3]
+    int ncx;              // grid chunks per axis
+    int64_t ngrid;        // grid chunks
+    int64_t nchunks;      // grid + far chunks
+    void* staged;         // [slot][2] 4-vectors of the working precision
+    int* count;           // staged cells per chunk
+    double* partial;      // [group][atom][3]
 };
 
 template <typename T>
@@ -79,164 +99,260 @@ __device__ inline float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <>
 __device__ inline double rsq<double>(double x) { return sqrt(1.0 / x); }
 
-template <typename T>
-__global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
-    using T4 = typename V4<T>::type;
-    __shared__ T4 scell[CT];
-    __shared__ T4 sfld[CT];
-    __shared__ int wcnt[AWG / 64];
-    const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
-    const int64_t chunk = blockIdx.y;
-    const int64_t atom = (int64_t)blockIdx.x * AWG + t;
-    const bool has_atom = atom < f.a.n;
-    const Grid& g = f.g;
+__device__ inline int64_t chunk_slot0(const ForceArgs& f, int64_t chunk) {
+    return chunk < f.ngrid ? chunk * CB3 : f.ngrid * CB3 + (chunk - f.ngrid) * FAR_CHUNK;
+}
 
-    // chunk origin and extent
-    double ox, oy, oz;
-    int64_t ncells;
+// Centre of a grid chunk's cell centres, or the first node of a far chunk.
+__device__ inline void chunk_origin(const ForceArgs& f, int64_t chunk, double& ox, double& oy,
+                                    double& oz) {
+    if (chunk < f.ngrid) {
+        const int ci = (int)(chunk % f.ncx), cj = (int)((chunk / f.ncx) % f.ncx),
+                  ck = (int)(chunk / ((int64_t)f.ncx * f.ncx));
+        ox = f.g.x0 + (ci * CB + 0.5 * (CB - 1)) * f.g.h;
+        oy = f.g.y0 + (cj * CB + 0.5 * (CB - 1)) * f.g.h;
+        oz = f.g.z0 + (ck * CB + 0.5 * (CB - 1)) * f.g.h;
+    } else {
+        const double4 o = f.far_pts[(chunk - f.ngrid) * FAR_CHUNK];
+        ox = o.x;
+        oy = o.y;
+        oz = o.z;
+    }
+}
+
+// One workgroup per chunk: compact the cells with nonzero weight in cell order.
+template <typename T>
+__global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
+    using T4 = typename V4<T>::type;
+    __shared__ int wcnt[4];
+    __shared__ int run;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t chunk = blockIdx.x;
+    const Grid& g = f.g;
+    T4* out = static_cast<T4*>(f.staged) + 2 * chunk_slot0(f, chunk);
+    const bool is_grid = chunk < f.ngrid;
     int ci = 0, cj = 0, ck = 0;
-    int64_t far0 = 0;
-    const bool is_grid = chunk < f.ngrid_chunks;
+    int64_t far0 = 0, ncells;
+    double ox, oy, oz;
+    chunk_origin(f, chunk, ox, oy, oz);
     if (is_grid) {
         ci = (int)(chunk % f.ncx);
         cj = (int)((chunk / f.ncx) % f.ncx);
         ck = (int)(chunk / ((int64_t)f.ncx * f.ncx));
-        ox = g.x0 + (ci * f.cb + 0.5 * (f.cb - 1)) * g.h;
-        oy = g.y0 + (cj * f.cb + 0.5 * (f.cb - 1)) * g.h;
-        oz = g.z0 + (ck * f.cb + 0.5 * (f.cb - 1)) * g.h;
-        ncells = (int64_t)f.cb * f.cb * f.cb;
+        ncells = CB3;
     } else {
-        far0 = (chunk - f.ngrid_chunks) * (int64_t)(CT * FAR_TILES);
-        const double4 o = f.far_pts[far0];
-        ox = o.x;
-        oy = o.y;
-        oz = o.z;
-        const int64_t rem = f.nfar - far0;
-        ncells = rem < CT * FAR_TILES ? rem : CT * FAR_TILES;
+        far0 = (chunk - f.ngrid) * FAR_CHUNK;
+        ncells = f.nfar - far0 < FAR_CHUNK ? f.nfar - far0 : FAR_CHUNK;
     }
-
-    // per-lane atom: position relative to the chunk origin and the two
-    // per-atom factors, 24 rho_w eps (LJ) and -2 Ccfa Q (CFA)
-    T ax = 0, ay = 0, az = 0, sig2 = 0, e24 = 0, k3 = 0;
-    double kq = 0.0;
-    if (has_atom) {
-        const double4 p = f.a.pos[atom];
-        const double4 q = f.a.prm64[atom];
-        ax = (T)(p.x - ox);
-        ay = (T)(p.y - oy);
-        az = (T)(p.z - oz);
-        sig2 = (T)q.x;
-        e24 = (T)(6.0 * q.y);
-        kq = -2.0 * f.ph.ccfa * q.z;
-        k3 = (T)(3.0 * kq);
-    }
-    const T r2min = (T)f.ph.r2min;
-    double gd[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
-
-    for (int64_t base = 0; base < ncells; base += CT) {
-        // stage the tile's cells with nonzero weight, in cell order
+    if (t == 0) run = 0;
+    for (int64_t base = 0; base < ncells; base += 256) {
         const int64_t li = base + t;
-        T px = 0, py = 0, pz = 0, w = 0, wx = 0, wy = 0, wz = 0;
+        T4 a = mk4((T)0, (T)0, (T)0, (T)0), b = a;
         bool keep = false;
         if (li < ncells) {
             if (is_grid) {
-                const int lx = (int)(li % f.cb), ly = (int)((li / f.cb) % f.cb),
-                          lz = (int)(li / ((int64_t)f.cb * f.cb));
-                const int x = ci * f.cb + lx, y = cj * f.cb + ly, z = ck * f.cb + lz;
+                const int lx = (int)(li % CB), ly = (int)((li / CB) % CB), lz = (int)(li / (CB * CB));
+                const int x = ci * CB + lx, y = cj * CB + ly, z = ck * CB + lz;
                 if (x < g.n && y < g.n && z < g.n) {
                     const uint32_t word = f.bits[g.row(y, z) + 1 + (x >> 5)];
                     if ((word >> (x & 31)) & 1u) {
                         const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
                         const double wd = f.ph.h3;
-                        px = (T)((lx - 0.5 * (f.cb - 1)) * g.h);
-                        py = (T)((ly - 0.5 * (f.cb - 1)) * g.h);
-                        pz = (T)((lz - 0.5 * (f.cb - 1)) * g.h);
-                        w = (T)wd;
-                        wx = (T)(wd * f.ex[c]);
-                        wy = (T)(wd * f.ey[c]);
-                        wz = (T)(wd * f.ez[c]);
+                        a = mk4((T)((lx - 0.5 * (CB - 1)) * g.h), (T)((ly - 0.5 * (CB - 1)) * g.h),
+                                (T)((lz - 0.5 * (CB - 1)) * g.h), (T)wd);
+                        b = mk4((T)(wd * f.ex[c]), (T)(wd * f.ey[c]), (T)(wd * f.ez[c]), (T)0);
                         keep = true;
                     }
                 }
             } else {
                 const int64_t pidx = far0 + li;
                 const double4 p = f.far_pts[pidx];
-                px = (T)(p.x - ox);
-                py = (T)(p.y - oy);
-                pz = (T)(p.z - oz);
-                w = (T)p.w;
-                wx = (T)(p.w * f.far_ex[pidx]);
-                wy = (T)(p.w * f.far_ey[pidx]);
-                wz = (T)(p.w * f.far_ez[pidx]);
+                a = mk4((T)(p.x - ox), (T)(p.y - oy), (T)(p.z - oz), (T)p.w);
+                b = mk4((T)(p.w * f.far_ex[pidx]), (T)(p.w * f.far_ey[pidx]),
+                        (T)(p.w * f.far_ez[pidx]), (T)0);
                 keep = true;
             }
         }
         const uint64_t bal = __ballot(keep);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        __syncthreads();  // previous tile fully consumed
         if (lane == 0) wcnt[wv] = __popcll(bal);
         __syncthreads();
-        int off = 0, cnt = 0;
+        int off = run, tot = 0;
 #pragma unroll
-        for (int k = 0; k < AWG / 64; ++k) {
+        for (int k = 0; k < 4; ++k) {
             off += (k < wv) ? wcnt[k] : 0;
-            cnt += wcnt[k];
+            tot += wcnt[k];
         }
         if (keep) {
-            scell[off + before] = mk4(px, py, pz, w);
-            sfld[off + before] = mk4(wx, wy, wz, (T)0);
+            out[2 * (off + before)] = a;
+            out[2 * (off + before) + 1] = b;
         }
+        __syncthreads();  // everyone has read run and wcnt
+        if (t == 0) run += tot;
         __syncthreads();
-        T dx_ = 0, dy_ = 0, dz_ = 0, ex_ = 0, ey_ = 0, ez_ = 0;
+    }
+    if (t == 0) f.count[chunk] = run;
+}
+
+// Pairs of one staged tile.  FLOOR: apply the r2_min floor (only needed when
+// an atom of the wave may lie within sqrt(r2_min) of a cell of the chunk).
+template <typename T, bool FLOOR>
+__device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt, T ax, T ay,
+                                           T az, T sig2, T e24, T k3, T r2min, T (&acc)[6]) {
+    using T4 = typename V4<T>::type;
+    T dx_ = 0, dy_ = 0, dz_ = 0, ex_ = 0, ey_ = 0, ez_ = 0;
 #pragma unroll 2
-        for (int m = 0; m < cnt; ++m) {
-            const T4 c = scell[m];
-            const T4 e = sfld[m];
-            const T dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const bool inside = r2 < r2min;
-            const T ir = rsq<T>(inside ? r2min : r2);
-            const T ir2 = ir * ir;
-            const T ir3 = ir2 * ir;
-            const T s = sig2 * ir2;
-            const T s3 = s * s * s;
-            const T lj = (c.w * ir2) * ((s3 + s3) * s3 - s3);
-            const T ed = e.x * dx + e.y * dy + e.z * dz;
-            T coef = e24 * lj - k3 * (ed * (ir3 * ir2));
-            coef = inside ? (T)0 : coef;
-            dx_ += coef * dx;
-            dy_ += coef * dy;
-            dz_ += coef * dz;
-            ex_ += ir3 * e.x;
-            ey_ += ir3 * e.y;
-            ez_ += ir3 * e.z;
+    for (int m = 0; m < cnt; ++m) {
+        const T4 c = sc[2 * m];
+        const T4 e = sc[2 * m + 1];
+        const T dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        bool inside = false;
+        T ir;
+        if (FLOOR) {
+            inside = r2 < r2min;
+            ir = rsq<T>(inside ? r2min : r2);
+        } else {
+            ir = rsq<T>(r2);
         }
-        gd[0] += dx_;
-        gd[1] += dy_;
-        gd[2] += dz_;
-        ge[0] += ex_;
-        ge[1] += ey_;
-        ge[2] += ez_;
+        const T ir2 = ir * ir;
+        const T ir3 = ir2 * ir;
+        const T s = sig2 * ir2;
+        const T s3 = s * s * s;
+        const T lj = (c.w * ir2) * ((s3 + s3) * s3 - s3);
+        const T ed = e.x * dx + e.y * dy + e.z * dz;
+        T coef = e24 * lj - k3 * (ed * (ir3 * ir2));
+        if (FLOOR) coef = inside ? (T)0 : coef;
+        dx_ += coef * dx;
+        dy_ += coef * dy;
+        dz_ += coef * dz;
+        ex_ += ir3 * e.x;
+        ey_ += ir3 * e.y;
+        ez_ += ir3 * e.z;
+    }
+    acc[0] = dx_;
+    acc[1] = dy_;
+    acc[2] = dz_;
+    acc[3] = ex_;
+    acc[4] = ey_;
+    acc[5] = ez_;
+}
+
+template <typename T>
+__global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
+    using T4 = typename V4<T>::type;
+    __shared__ T4 sbuf[2][2 * CT];
+    const int t = threadIdx.x;
+    const int64_t atom = (int64_t)blockIdx.x * AWG + t;
+    const bool has_atom = atom < f.a.n;
+    const Grid& g = f.g;
+    const T4* staged = static_cast<const T4*>(f.staged);
+
+    double px = 0, py = 0, pz = 0;
+    T sig2 = 0, e24 = 0, k3 = 0;
+    double kq = 0.0;
+    if (has_atom) {
+        const double4 p = f.a.pos[atom];
+        const double4 q = f.a.prm64[atom];
+        px = p.x;
+        py = p.y;
+        pz = p.z;
+        sig2 = (T)q.x;
+        e24 = (T)(6.0 * q.y);
+        kq = -2.0 * f.ph.ccfa * q.z;
+        k3 = (T)(3.0 * kq);
+    }
+    const T r2min = (T)f.ph.r2min;
+    // an atom farther than this from the chunk centre along some axis is at
+    // least 2 sqrt(r2_min) from every cell centre of the chunk
+    const double reach = 0.5 * (CB - 1) * g.h + 2.0 * sqrt(f.ph.r2min);
+    double gd[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
+
+    const int64_t c0 = (int64_t)blockIdx.y * GROUP;
+    const int64_t c1 = c0 + GROUP < f.nchunks ? c0 + GROUP : f.nchunks;
+    for (int64_t chunk = c0; chunk < c1; ++chunk) {
+        const int cnt = f.count[chunk];
+        if (cnt == 0) continue;  // uniform over the workgroup
+        double ox, oy, oz;
+        chunk_origin(f, chunk, ox, oy, oz);
+        const T ax = (T)(px - ox), ay = (T)(py - oy), az = (T)(pz - oz);
+        const bool near = has_atom && fabs(px - ox) <= reach && fabs(py - oy) <= reach &&
+                          fabs(pz - oz) <= reach;
+        const bool floor = chunk >= f.ngrid || __ballot(near) != 0;
+        const T4* src = staged + 2 * chunk_slot0(f, chunk);
+        const int ntiles = (cnt + CT - 1) / CT;
+        T4 ra = mk4((T)0, (T)0, (T)0, (T)0), rb = ra;
+        if (t < cnt) {
+            ra = src[2 * t];
+            rb = src[2 * t + 1];
+        }
+        sbuf[0][2 * t] = ra;
+        sbuf[0][2 * t + 1] = rb;
+        __syncthreads();
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int nxt = (tile + 1) * CT + t;
+            if (tile + 1 < ntiles && nxt < cnt) {
+                ra = src[2 * nxt];
+                rb = src[2 * nxt + 1];
+            }
+            const int m = cnt - tile * CT < CT ? cnt - tile * CT : CT;
+            T acc[6];
+            if (floor)
+                tile_pairs<T, true>(sbuf[tile & 1], m, ax, ay, az, sig2, e24, k3, r2min, acc);
+            else
+                tile_pairs<T, false>(sbuf[tile & 1], m, ax, ay, az, sig2, e24, k3, r2min, acc);
+            gd[0] += acc[0];
+            gd[1] += acc[1];
+            gd[2] += acc[2];
+            ge[0] += acc[3];
+            ge[1] += acc[4];
+            ge[2] += acc[5];
+            if (tile + 1 < ntiles) {
+                // the other buffer was last read in tile - 1, before the
+                // barrier that ended it
+                sbuf[(tile + 1) & 1][2 * t] = ra;
+                sbuf[(tile + 1) & 1][2 * t + 1] = rb;
+            }
+            __syncthreads();
+        }
     }
     if (!has_atom) return;
-    double* out = f.partial + (chunk * f.a.n + atom) * 3;
+    double* out = f.partial + ((int64_t)blockIdx.y * f.a.n + atom) * 3;
     out[0] = gd[0] + kq * ge[0];
     out[1] = gd[1] + kq * ge[1];
     out[2] = gd[2] + kq * ge[2];
 }
 
-// F_n = -(sum over chunks of the partial gradients + bond gradient).
-__global__ void force_reduce_kernel(int64_t natoms, int64_t nchunks, const double* partial,
-                                    const double4* pos, Bonds bonds, double* f_out) {
-    const int64_t atom = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (atom >= natoms) return;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int64_t c = 0; c < nchunks; ++c) {
-        const double* p = partial + (c * natoms + atom) * 3;
-        g0 += p[0];
-        g1 += p[1];
-        g2 += p[2];
+// F_n = -(sum over chunk groups of the partial gradients + bond gradient).
+// Each of RSPLIT lanes per atom sums a fixed slice of the groups in order;
+// the slices are then added in slice order.
+__global__ __launch_bounds__(RATOMS * RSPLIT) void force_reduce_kernel(
+    int64_t natoms, int64_t ngroups, const double* partial, const double4* pos, Bonds bonds,
+    double* f_out) {
+    __shared__ double sh[RSPLIT][RATOMS][3];
+    const int la = threadIdx.x % RATOMS, sl = threadIdx.x / RATOMS;
+    const int64_t atom = (int64_t)blockIdx.x * RATOMS + la;
+    const int64_t per = (ngroups + RSPLIT - 1) / RSPLIT;
+    const int64_t g0 = sl * per, g1 = g0 + per < ngroups ? g0 + per : ngroups;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (atom < natoms) {
+        for (int64_t c = g0; c < g1; ++c) {
+            const double* p = partial + (c * natoms + atom) * 3;
+            s0 += p[0];
+            s1 += p[1];
+            s2 += p[2];
+        }
+    }
+    sh[sl][la][0] = s0;
+    sh[sl][la][1] = s1;
+    sh[sl][la][2] = s2;
+    __syncthreads();
+    if (sl != 0 || atom >= natoms) return;
+    double g0s = 0.0, g1s = 0.0, g2s = 0.0;
+    for (int k = 0; k < RSPLIT; ++k) {
+        g0s += sh[k][la][0];
+        g1s += sh[k][la][1];
+        g2s += sh[k][la][2];
     }
     if (bonds.nb > 0) {
         const double4 pa = pos[atom];
@@ -245,14 +361,14 @@ __global__ void force_reduce_kernel(int64_t natoms, int64_t nchunks, const doubl
             const double dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
             const double r = sqrt(dx * dx + dy * dy + dz * dz);
             const double c = bonds.k[e] * (r - bonds.r0[e]) / r;
-            g0 += c * dx;
-            g1 += c * dy;
-            g2 += c * dz;
+            g0s += c * dx;
+            g1s += c * dy;
+            g2s += c * dz;
         }
     }
-    f_out[3 * atom + 0] = -g0;
-    f_out[3 * atom + 1] = -g1;
-    f_out[3 * atom + 2] = -g2;
+    f_out[3 * atom + 0] = -g0s;
+    f_out[3 * atom + 1] = -g1s;
+    f_out[3 * atom + 2] = -g2s;
 }
 
 // sum over bonds of (1/2) k (r - r0)^2, each bond counted from its lower end
@@ -284,18 +400,26 @@ __global__ __launch_bounds__(BWG) void bond_energy_kernel(int64_t natoms, const 
 
 }  // namespace
 
-int64_t force_partial_chunks(const Grid& g, int64_t natoms, int64_t nfar) {
-    const int cb = chunk_edge(g.n, natoms);
-    const int64_t ncx = (g.n + cb - 1) / cb;
-    return ncx * ncx * ncx + (nfar + CT * FAR_TILES - 1) / (CT * FAR_TILES);
+ForceSizes force_sizes(const Grid& g, int64_t natoms, int64_t nfar) {
+    const ChunkPlan p = chunk_plan(g.n, nfar);
+    ForceSizes s;
+    s.partial_doubles = 3 * p.ngroups() * natoms;
+    s.staged_bytes = 2 * sizeof(double4) * p.slots();
+    s.counts = p.nchunks();
+    return s;
 }
 
 hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int precision,
                          const uint32_t* bits, const double* ex, const double* ey,
                          const double* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
-                         const Bonds& bonds, double* partial, int64_t nchunk_cap,
-                         double* f_out, hipStream_t st) {
+                         const Bonds& bonds, const ForceScratch& scr, double* f_out,
+                         hipStream_t st) {
+    const ChunkPlan p = chunk_plan(g.n, nfar);
+    const ForceSizes need = force_sizes(g, a.n, nfar);
+    if (need.partial_doubles > scr.partial_doubles || need.staged_bytes > scr.staged_bytes ||
+        need.counts > scr.counts)
+        return hipErrorInvalidValue;
     ForceArgs f;
     f.g = g;
     f.a = a;
@@ -309,20 +433,25 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
     f.far_ey = far_ey;
     f.far_ez = far_ez;
     f.nfar = nfar;
-    f.cb = chunk_edge(g.n, a.n);
-    f.ncx = (g.n + f.cb - 1) / f.cb;
-    f.ngrid_chunks = (int64_t)f.ncx * f.ncx * f.ncx;
-    f.partial = partial;
-    const int64_t nfar_chunks = (nfar + CT * FAR_TILES - 1) / (CT * FAR_TILES);
-    const int64_t nchunks = f.ngrid_chunks + nfar_chunks;
-    if (nchunks > nchunk_cap) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.n + AWG - 1) / AWG), (unsigned)nchunks);
-    if (precision == 64)
+    f.ncx = p.ncx;
+    f.ngrid = p.ngrid;
+    f.nchunks = p.nchunks();
+    f.staged = scr.staged;
+    f.count = scr.count;
+    f.partial = scr.partial;
+    const dim3 grid((unsigned)((a.n + AWG - 1) / AWG), (unsigned)p.ngroups());
+    if (precision == 64) {
+        hipLaunchKernelGGL(force_stage_kernel<double>, dim3((unsigned)p.nchunks()), dim3(256), 0,
+                           st, f);
         hipLaunchKernelGGL(force_adjoint_kernel<double>, grid, dim3(AWG), 0, st, f);
-    else
+    } else {
+        hipLaunchKernelGGL(force_stage_kernel<float>, dim3((unsigned)p.nchunks()), dim3(256), 0,
+                           st, f);
         hipLaunchKernelGGL(force_adjoint_kernel<float>, grid, dim3(AWG), 0, st, f);
-    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st,
-                       a.n, nchunks, partial, a.pos, bonds, f_out);
+    }
+    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((a.n + RATOMS - 1) / RATOMS)),
+                       dim3(RATOMS * RSPLIT), 0, st, a.n, p.ngroups(), scr.partial, a.pos, bonds,
+                       f_out);
     return hipGetLastError();
 }
 

@@ -111,13 +111,28 @@ struct Bonds {
     const double* k;        // constant per incidence
 };
 
+// Device scratch of the force computation: staged cells (sized for FP64),
+// per-chunk counts and per-(chunk group, atom) partial gradients.
+struct ForceSizes {
+    int64_t partial_doubles = 0;
+    size_t staged_bytes = 0;
+    int64_t counts = 0;
+};
+struct ForceScratch {
+    double* partial;
+    int64_t partial_doubles;
+    void* staged;
+    size_t staged_bytes;
+    int* count;
+    int64_t counts;
+};
+ForceSizes force_sizes(const Grid& g, int64_t natoms, int64_t nfar);
 hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int precision,
                          const uint32_t* bits, const double* ex, const double* ey,
                          const double* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
-                         const Bonds& bonds, double* partial, int64_t nchunk_cap,
-                         double* grad_out, hipStream_t st);
-int64_t force_partial_chunks(const Grid& g, int64_t natoms, int64_t nfar);
+                         const Bonds& bonds, const ForceScratch& scr, double* f_out,
+                         hipStream_t st);
 
 hipError_t launch_bond_energy(const Atoms& a, const Bonds& bonds, double* partial, int nblocks,
                               double* out, hipStream_t st);
