@@ -107,7 +107,6 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
     // (and beyond the r2_min floor)
     const double rnear = 12.0 * g.h + 4.0 * sqrt(ph.r2min);
     const float rnear2 = (float)(rnear * rnear);
-    const float r2min = (float)ph.r2min;
 
     double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dMag[KC], dAE[KC], nMag[KC], nAE[KC];
 #pragma unroll
@@ -180,7 +179,8 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const float dz = cz[k] - pp.z;
-                    const float r2 = fmaxf(fmaf(dz, dz, dxy), r2min);
+                    // far atoms lie beyond 4 sqrt(r2_min): no floor needed
+                    const float r2 = fmaf(dz, dz, dxy);
                     const float ir = __builtin_amdgcn_rsqf(r2);
                     const float ir2 = ir * ir;
                     const float ir6 = ir2 * ir2 * ir2;

@@ -4,7 +4,7 @@
 //   sum_j w_j U(x_j),  w_j = h^3 [phi_j = +1] on grid cells and the
 //   quadrature weight on far-field nodes,
 // so  dG/dr_n = sum_j w_j grad_{r_n} U(x_j) with, for d = x_j - r_n,
-//   grad_{r_n} rho_w U_LJ = 24 rho_w eps_n (2 s^6 - s^3) d / r^2,  s = sigma_n^2/r^2
+//   grad_{r_n} rho_w U_LJ = 24 rho_w eps_n (2 s^6 - s^3) d / r^2,  s = sigma_n^6/r^6
 //   grad_{r_n} Ccfa |E|^2 = -2 Ccfa Q_n [E/r^3 - 3 (E.d) d / r^5]
 // (the solvent terms of the Appendix gradient, taken as the exact derivative
 // of the discrete energy; E_j comes from the density kernel).  Within the
@@ -196,9 +196,11 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
 
 // Pairs of one staged tile.  FLOOR: apply the r2_min floor (only needed when
 // an atom of the wave may lie within sqrt(r2_min) of a cell of the chunk).
+// With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the LJ part
+// of the coefficient is w r^-2 r^-6 (c1 r^-6 - c2).
 template <typename T, bool FLOOR>
 __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt, T ax, T ay,
-                                           T az, T sig2, T e24, T k3, T r2min, T (&acc)[6]) {
+                                           T az, T c1, T c2, T k3, T r2min, T (&acc)[6]) {
     using T4 = typename V4<T>::type;
     T dx_ = 0, dy_ = 0, dz_ = 0, ex_ = 0, ey_ = 0, ez_ = 0;
 #pragma unroll 2
@@ -217,11 +219,10 @@ __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int c
         }
         const T ir2 = ir * ir;
         const T ir3 = ir2 * ir;
-        const T s = sig2 * ir2;
-        const T s3 = s * s * s;
-        const T lj = (c.w * ir2) * ((s3 + s3) * s3 - s3);
+        const T ir6 = ir2 * ir2 * ir2;
+        const T lj = ((c.w * ir2) * ir6) * (c1 * ir6 - c2);
         const T ed = e.x * dx + e.y * dy + e.z * dz;
-        T coef = e24 * lj - k3 * (ed * (ir3 * ir2));
+        T coef = lj - k3 * (ed * (ir3 * ir2));
         if (FLOOR) coef = inside ? (T)0 : coef;
         dx_ += coef * dx;
         dy_ += coef * dy;
@@ -249,16 +250,17 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     const T4* staged = static_cast<const T4*>(f.staged);
 
     double px = 0, py = 0, pz = 0;
-    T sig2 = 0, e24 = 0, k3 = 0;
+    T c1 = 0, c2 = 0, k3 = 0;
     double kq = 0.0;
     if (has_atom) {
         const double4 p = f.a.pos[atom];
-        const double4 q = f.a.prm64[atom];
+        const double4 q = f.a.prm64[atom];  // sigma^2, 4 rho_w eps, Q, sigma
         px = p.x;
         py = p.y;
         pz = p.z;
-        sig2 = (T)q.x;
-        e24 = (T)(6.0 * q.y);
+        const double s6 = q.x * q.x * q.x;
+        c2 = (T)(6.0 * q.y * s6);
+        c1 = (T)(12.0 * q.y * s6 * s6);
         kq = -2.0 * f.ph.ccfa * q.z;
         k3 = (T)(3.0 * kq);
     }
@@ -268,9 +270,9 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     const double reach = 0.5 * (CB - 1) * g.h + 2.0 * sqrt(f.ph.r2min);
     double gd[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
 
-    const int64_t c0 = (int64_t)blockIdx.y * GROUP;
-    const int64_t c1 = c0 + GROUP < f.nchunks ? c0 + GROUP : f.nchunks;
-    for (int64_t chunk = c0; chunk < c1; ++chunk) {
+    const int64_t ch0 = (int64_t)blockIdx.y * GROUP;
+    const int64_t ch1 = ch0 + GROUP < f.nchunks ? ch0 + GROUP : f.nchunks;
+    for (int64_t chunk = ch0; chunk < ch1; ++chunk) {
         const int cnt = f.count[chunk];
         if (cnt == 0) continue;  // uniform over the workgroup
         double ox, oy, oz;
@@ -298,9 +300,9 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
             const int m = cnt - tile * CT < CT ? cnt - tile * CT : CT;
             T acc[6];
             if (floor)
-                tile_pairs<T, true>(sbuf[tile & 1], m, ax, ay, az, sig2, e24, k3, r2min, acc);
+                tile_pairs<T, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else
-                tile_pairs<T, false>(sbuf[tile & 1], m, ax, ay, az, sig2, e24, k3, r2min, acc);
+                tile_pairs<T, false>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             gd[0] += acc[0];
             gd[1] += acc[1];
             gd[2] += acc[2];
