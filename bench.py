@@ -38,6 +38,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str = "density_grid_f32"):
+    """HBM bytes per launch of the density kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy
+    calibration), or None when the kernel source has changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_two_globules_256.md")
+    src = os.path.join(ROOT, "paper_2208_05524_amd", "csrc", "density.hip")
+    try:
+        lines = open(path).read().splitlines()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for ln in lines:
+        f = ln.split()
+        if len(f) > 2 and f[0] == "traffic" and f[1] == kernel:
+            kv = dict(x.split("=", 1) for x in f[2:])
+            if kv.get("source_sha256") != sha:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """Oracle density (FP64, OpenMP) over whole z-planes of the same grid
     until about budget_s seconds of work; returns atom-gridpoint pairs/s."""
@@ -172,7 +195,8 @@ def main():
                    "grid": w.n, "atoms": w.natoms, "h_nm": w.h, "precision": "fp32 density, "
                    "fp64 totals and near-tie decisions"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": "density_grid_f32", "avg_ms": avg_dens_s * 1000.0,
                      "launches": dens_n, "flop_per_pair": FLOP_PER_PAIR},
         "density_atom_gridpt_per_s": pairs / avg_dens_s,
