@@ -19,15 +19,21 @@
 //    4 rho_w eps sigma^6 and 4 rho_w eps sigma^12;
 //  * FP32 partial sums over 32 atoms are summed over the 256-atom tile in
 //    FP32 and folded into FP64 once per tile;
-//  * beside U the kernel keeps the absolute sums sum 4 eps (s^6 + s^3) and
-//    sum |Q|/r^2 and the nearest squared distance, from which the epilogue
-//    writes a bound on |U_fp32 - U_exact| per cell; flip decisions inside
-//    that bound are redone in FP64.
+//  * beside U the kernel keeps the absolute sum sum 4 eps (s^6 + s^3) per
+//    cell and, per atom tile, a brick-wide bound on sum |Q|/r^2, from which
+//    the epilogue writes a bound on |U_fp32 - U_exact| per cell; flip
+//    decisions inside that bound are redone in FP64.
 #include "internal.h"
 #include "reduce.h"
 
 namespace vesis {
 namespace {
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
 constexpr int DWG = 256;
 constexpr int BX = 16, BY = 8, BZ = 4, KC = 2;
@@ -69,13 +75,17 @@ __device__ inline double cell_bound(double errLJ, double errE, double ex, double
     return 1.001 * (errLJ + fabs(ccfa) * (2.0 * emag * d + d * d));
 }
 
-__global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics ph,
-                                                        CellFields out) {
+// Four wavefronts per SIMD: at up to 128 VGPRs the loop keeps its two atoms
+// x two cells in flight; the compiler's default allocation lands above 128
+// and drops to three.
+__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void density_grid_f32(
+    Grid g, Atoms a, Physics ph, CellFields out) {
     __shared__ float4 spos[TILE];     // far atoms: rebased FP32 position, |Q|
     __shared__ float4 sprm[TILE];     // far atoms: c6, c12, Q
     __shared__ double4 npos[TILE];    // near atoms: FP64 position, sigma^2
     __shared__ double4 nprm[TILE];    // near atoms: 4 rho_w eps, Q, |Q|
     __shared__ int wcnt[2][DWG / 64];
+    __shared__ float sae[DWG / 64];  // per wavefront: bound on sum_far |Q|/r^2
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int tx = t & 15, ty = (t >> 4) & 7, tz = t >> 7;
@@ -107,6 +117,8 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
     // (and beyond the r2_min floor)
     const double rnear = 12.0 * g.h + 4.0 * sqrt(ph.r2min);
     const float rnear2 = (float)(rnear * rnear);
+    // half extents of the box spanned by the brick's cell centres
+    const double hxe = 0.5 * (BX - 1) * g.h, hye = 0.5 * (BY - 1) * g.h, hze = 0.5 * (BZ - 1) * g.h;
 
     double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dMag[KC], dAE[KC], nMag[KC], nAE[KC];
 #pragma unroll
@@ -146,6 +158,19 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
             nfar += wcnt[0][w2];
             nnear += wcnt[1][w2];
         }
+        // sum over the tile's far atoms of |Q| / d^2, d the distance from the
+        // atom to the box of the brick's cell centres: a bound on the tile's
+        // sum |Q|/r^2 for every cell of the brick (FP32 terms and wavefront
+        // sums; the 1.0001 below covers their rounding)
+        float ae = 0.f;
+        if (far) {
+            const double ex_ = fmax(fabs(p.x - ox) - hxe, 0.0);
+            const double ey_ = fmax(fabs(p.y - oy) - hye, 0.0);
+            const double ez_ = fmax(fabs(p.z - oz) - hze, 0.0);
+            ae = q32.w * __builtin_amdgcn_rcpf((float)(ex_ * ex_ + ey_ * ey_ + ez_ * ez_));
+        }
+        ae = wave_sum(ae);
+        if (lane == 0) sae[wv] = ae;
         if (far) {
             // prm32 = (4 rho_w eps sigma^6, 4 rho_w eps sigma^12, Q, |Q|)
             const int at = ofar + __popcll(bfar & below);
@@ -162,14 +187,14 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
 
         // far atoms, FP32: 32-atom partials, summed over the tile in FP32,
         // folded into FP64 once per tile
-        float TP[KC], TQ[KC], TEx[KC], TEy[KC], TEz[KC], TAE[KC];
+        float TP[KC], TQ[KC], TEx[KC], TEy[KC], TEz[KC];
 #pragma unroll
-        for (int k = 0; k < KC; ++k) TP[k] = TQ[k] = TEx[k] = TEy[k] = TEz[k] = TAE[k] = 0.f;
+        for (int k = 0; k < KC; ++k) TP[k] = TQ[k] = TEx[k] = TEy[k] = TEz[k] = 0.f;
         for (int m0 = 0; m0 < nfar; m0 += SUB) {
             const int me = (m0 + SUB < nfar) ? m0 + SUB : nfar;
-            float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC], AE[KC];
+            float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC];
 #pragma unroll
-            for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = AE[k] = 0.f;
+            for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = 0.f;
 #pragma unroll 2
             for (int m = m0; m < me; ++m) {
                 const float4 pp = spos[m];
@@ -191,7 +216,6 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
                     Ex[k] = fmaf(qr3, dx, Ex[k]);
                     Ey[k] = fmaf(qr3, dy, Ey[k]);
                     Ez[k] = fmaf(qr3, dz, Ez[k]);
-                    AE[k] = fmaf(pp.w, ir2, AE[k]);
                 }
             }
 #pragma unroll
@@ -201,7 +225,6 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
                 TEx[k] += Ex[k];
                 TEy[k] += Ey[k];
                 TEz[k] += Ez[k];
-                TAE[k] += AE[k];
             }
         }
 #pragma unroll
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(DWG) void density_grid_f32(Grid g, Atoms a, Physics
             dEy[k] += TEy[k];
             dEz[k] += TEz[k];
             dMag[k] += (double)TP[k] + (double)TQ[k];
-            dAE[k] += TAE[k];
+            dAE[k] += 1.0001 * ((double)sae[0] + (double)sae[1] + (double)sae[2] + (double)sae[3]);
         }
 
         // near atoms, FP64 (1/r from the hardware estimate + two Newton steps)
