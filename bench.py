@@ -8,7 +8,8 @@ equilibrium, energy, forces, one adaptive-mobility atom step (which itself
 re-evaluates the density of each trial; the mobility state carries over
 between steps as between iterations of the algorithm).  After the timed
 steps, the full alternation runs for --relax-iters outer iterations and is
-reported under "relax".  All inputs are
+reported under "relax", and 64 molecules are brought to equilibrium one at a
+time and batched, reported under "batch".  All inputs are
 resident in device memory before the timed region.
 
 Prints one JSON line.  `value` is atom-gridpoint pairs of one configuration
@@ -61,6 +62,72 @@ def measured_traffic(kernel: str = "density_grid_f32"):
     return None
 
 
+def batch_comparison(rounds: int = 2):
+    """Time to equilibrium of 64 molecules (atom counts log-uniform in [200,
+    3000], grids 64^3 to 160^3 at 0.05 nm): each molecule on its own (tight
+    labels, density, far field, colour sweeps, one call per molecule) against
+    the batched call (one density launch and one launch per colour pass for
+    all molecules).  Both start from the same positions and labels; the
+    labels they reach and their energies are compared."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_05524_amd import Batch, Context
+
+    ws = synth.batch_conformations()
+    ctxs = []
+    for w in ws:
+        c = Context(0)
+        c.setup(w, precision=32)
+        ctxs.append(c)
+    b = Batch(ctxs)
+
+    def reset():
+        for w, c in zip(ws, ctxs):
+            c.set_positions(w.xyz)  # marks the density stale
+        torch.cuda.synchronize()
+
+    best, tune_ms = b.tune()
+    plain_ms, batch_ms = [], []
+    for r in range(rounds + 1):
+        reset()
+        t0 = time.perf_counter()
+        for c in ctxs:
+            c.init_labels("tight", 1.0)
+            c.minimize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if r == rounds:
+            lab_plain = [c.labels() for c in ctxs]
+            e_plain = [c.energy()["total"] for c in ctxs]
+        reset()
+        t2 = time.perf_counter()
+        for c in ctxs:
+            c.init_labels("tight", 1.0)
+        rc, st = b.minimize(variant=best)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if r > 0:  # round 0 warms up
+            plain_ms.append(1e3 * (t1 - t0))
+            batch_ms.append(1e3 * (t3 - t2))
+    same = all(np.array_equal(a, c.labels()) for a, c in zip(lab_plain, ctxs))
+    e_batch = [c.energy()["total"] for c in ctxs]
+    rel = max(abs(a - e) / abs(a) for a, e in zip(e_plain, e_batch))
+    pairs = float(sum(w.natoms * w.n ** 3 for w in ws))
+    out = {"molecules": len(ws), "atoms": int(sum(w.natoms for w in ws)),
+           "cells": int(sum(w.n ** 3 for w in ws)), "pairs": pairs,
+           "plain_ms": min(plain_ms), "batched_ms": min(batch_ms),
+           "speedup": min(plain_ms) / min(batch_ms),
+           "batched_atom_gridpt_per_s": pairs / (min(batch_ms) / 1e3),
+           "density_variant": best, "tune_ms": tune_ms,
+           "sweeps_max": max(x["sweeps"] for x in st), "converged": rc == 0,
+           "labels_identical": bool(same), "max_rel_dG": rel}
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """Oracle density (FP64, OpenMP) over whole z-planes of the same grid
     until about budget_s seconds of work; returns atom-gridpoint pairs/s."""
@@ -95,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-molecule batched-vs-one-at-a-time comparison")
     ap.add_argument("--relax-iters", type=int, default=200,
                     help="after the timed steps, run this many outer iterations of the full "
                          "alternation (Steps 2-5) from the same start and report them (0: skip)")
@@ -210,6 +279,10 @@ def main():
         "atom_step": {"accepted": last["accepted"], "retries": last["retries"]},
         "G_total": last["e"]["total"],
     }
+    if not args.no_batch:
+        log("batch comparison ...")
+        out["batch"] = batch_comparison()
+        log(f"batch: {out['batch']}")
     if args.relax_iters > 0:
         ctx.set_positions(xyz0)
         ctx.init_labels("tight", 1.0)

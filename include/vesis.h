@@ -233,6 +233,34 @@ typedef struct {
 vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* opts, vesis_mobility* state,
                          vesis_relax_report* out);
 
+/* ---- Batches of molecules -------------------------------------------------
+ * Many contexts (one molecule each, own grid and atoms, set up as above, all
+ * with FP32 densities, one device, one stream and one colour period) are
+ * relaxed together: one density launch covers every molecule's cells and each
+ * colour pass is one launch over every unconverged molecule's label words.
+ * Per molecule the result is the one vesis_minimize_interface gives: the
+ * same passes in the same order (the paper's Step 2, batched).  The calls
+ * need a device buffer for the batch's own tables (descriptors, block maps):
+ * vesis_batch_workspace_size gives its size; it must be 256-byte aligned.
+ * Contexts must not be used concurrently with a batch call. */
+vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_t* bytes);
+
+/* Time each density tiling variant (0: two cells per lane on 16x8x4
+ * bricks; 1: one cell per lane on 16x8x2 bricks) on the batch, return the
+ * fastest in *best and the times in ms[variant] (ms may be NULL).  Needs no
+ * labels; leaves the densities marked stale. */
+vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* batch_ws, size_t bytes,
+                              int32_t* best, double* ms);
+
+/* Relax the interfaces of m molecules (Step 2 for each), recomputing the
+ * density of those whose atoms changed with density variant `variant`.
+ * out (m entries, may be NULL) receives each molecule's statistics.
+ * Returns VESIS_OK when every molecule converged within max_sweeps,
+ * VESIS_NOT_CONVERGED otherwise (the others keep their state and a new call
+ * resumes them). */
+vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* batch_ws, size_t bytes,
+                                  int32_t max_sweeps, int32_t variant, vesis_min_stats* out);
+
 /* Copy the labels (n^3 int8, -1/+1) to host memory. */
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);
 

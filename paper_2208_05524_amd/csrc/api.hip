@@ -376,6 +376,19 @@ vesis_status upload_inputs(vesis_ctx* ctx) {
     return VESIS_OK;
 }
 
+vesis_status density_tail(vesis_ctx* ctx);
+
+CellFields cell_fields(vesis_ctx* ctx) {
+    CellFields cf;
+    cf.ulj = at<double>(ctx, ctx->lay.ulj);
+    cf.ucfa = at<double>(ctx, ctx->lay.ucfa);
+    cf.ex = at<double>(ctx, ctx->lay.ex);
+    cf.ey = at<double>(ctx, ctx->lay.ey);
+    cf.ez = at<double>(ctx, ctx->lay.ez);
+    cf.bound = at<double>(ctx, ctx->lay.bound);
+    return cf;
+}
+
 // U, E and the error bound on every cell, the far field at every node, and
 // the far-field sums; resets the FP64 near-tie cache.
 vesis_status ensure_density(vesis_ctx* ctx) {
@@ -385,17 +398,20 @@ vesis_status ensure_density(vesis_ctx* ctx) {
     hipStream_t st = ctx->stream;
     const Atoms a = dev_atoms(ctx);
     const Physics ph = dev_physics(ctx);
-    CellFields cf;
-    cf.ulj = at<double>(ctx, ctx->lay.ulj);
-    cf.ucfa = at<double>(ctx, ctx->lay.ucfa);
-    cf.ex = at<double>(ctx, ctx->lay.ex);
-    cf.ey = at<double>(ctx, ctx->lay.ey);
-    cf.ez = at<double>(ctx, ctx->lay.ez);
-    cf.bound = at<double>(ctx, ctx->lay.bound);
+    const CellFields cf = cell_fields(ctx);
     {
         Timed t(ctx, K_DENSITY);
         CK(launch_density_grid(ctx->g, a, ph, ctx->prm.precision, cf, st));
     }
+    return density_tail(ctx);
+}
+
+// After the grid density: reset the FP64 near-tie cache, evaluate the far
+// field and its sums.
+vesis_status density_tail(vesis_ctx* ctx) {
+    hipStream_t st = ctx->stream;
+    const Atoms a = dev_atoms(ctx);
+    const Physics ph = dev_physics(ctx);
     {
         Timed t(ctx, K_OTHER);
         CK(launch_fill_f64(at<double>(ctx, ctx->lay.u64cache), 2 * ctx->g.ncell(), NAN, st));
@@ -997,6 +1013,296 @@ vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* o, vesis_mobili
     rep->stop_reason = reason;
     ctx->err.clear();
     return reason == 3 ? VESIS_NOT_CONVERGED : VESIS_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+constexpr int BATCH_MAX = 4096;
+
+struct BatchLayout {
+    size_t desc, dmap, fmap, flips, total;
+};
+
+BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
+    BatchLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o += align256(bytes ? bytes : 1);
+        return r;
+    };
+    L.desc = take(sizeof(MolDesc) * (size_t)m);
+    L.dmap = take(4 * (size_t)dens_blocks);
+    L.fmap = take(4 * (size_t)flip_blocks);
+    L.flips = take(4 * (size_t)m * SWEEP_BATCH);
+    L.total = o;
+    return L;
+}
+
+// The largest block counts any density variant or the flip passes need.
+void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip) {
+    dens = 0;
+    flip = 0;
+    for (int v = 0; v < DENSITY_VARIANTS; ++v) {
+        int64_t s = 0;
+        for (int i = 0; i < m; ++i) s += density_bricks(c[i]->g, v);
+        dens = std::max(dens, s);
+    }
+    for (int i = 0; i < m; ++i) flip += flip_slots(c[i]->g, c[i]->sc.p) / FLIP_WG;
+}
+
+MolDesc mol_desc(vesis_ctx* c) {
+    MolDesc d{};
+    d.g = c->g;
+    d.sc = c->sc;
+    d.a = dev_atoms(c);
+    d.ph = dev_physics(c);
+    d.f = cell_fields(c);
+    d.bits = at<uint32_t>(c, c->lay.bits);
+    d.stamp = at<int>(c, c->lay.stamp);
+    d.u64cache = at<double>(c, c->lay.u64cache);
+    d.sweep_flips = at<int>(c, c->lay.sweep_flips);
+    d.counters = at<int64_t>(c, c->lay.scal_i) + SI_CNT;
+    return d;
+}
+
+// Common checks of a batch call; on success `L` is the batch workspace layout.
+vesis_status batch_check(vesis_ctx* const* c, int32_t m, void* bws, size_t bytes, bool labels,
+                         BatchLayout& L) {
+    if (!c || m < 1 || m > BATCH_MAX)
+        return fail(m >= 1 && c ? c[0] : nullptr, VESIS_E_ARG, "need 1 to 4096 contexts");
+    vesis_ctx* c0 = c[0];
+    if (!c0) return VESIS_E_ARG;
+    for (int i = 0; i < m; ++i) {
+        if (!c[i]) return fail(c0, VESIS_E_ARG, "null context in batch");
+        for (int j = 0; j < i; ++j)
+            if (c[j] == c[i]) return fail(c0, VESIS_E_ARG, "context repeated in batch");
+        vesis_status s = need(c[i], labels);
+        if (s != VESIS_OK) {
+            c0->err = "batch member " + std::to_string(i) + ": " + c[i]->err;
+            return s;
+        }
+        if (c[i]->device != c0->device || c[i]->stream != c0->stream)
+            return fail(c0, VESIS_E_ARG, "batch members must share device and stream");
+        if (c[i]->prm.precision != 32)
+            return fail(c0, VESIS_E_ARG, "batched minimisation needs FP32 densities");
+        if (c[i]->sc.p != c0->sc.p)
+            return fail(c0, VESIS_E_ARG, "batch members must share the colour period");
+    }
+    int64_t db, fb;
+    batch_blocks(c, m, db, fb);
+    L = batch_layout(m, db, fb);
+    if (!bws || (reinterpret_cast<uintptr_t>(bws) & 255))
+        return fail(c0, VESIS_E_ARG, "batch workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.total)
+        return fail(c0, VESIS_E_WORKSPACE, "batch workspace too small: need " +
+                                               std::to_string(L.total) + " bytes");
+    for (int i = 0; i < m; ++i) {
+        vesis_status s = upload_inputs(c[i]);
+        if (s != VESIS_OK) {
+            c0->err = "batch member " + std::to_string(i) + ": " + c[i]->err;
+            return s;
+        }
+    }
+    return VESIS_OK;
+}
+
+// One batched density launch over the listed molecules, heaviest first (the
+// blocks of the costliest molecules are dispatched first, the light ones
+// fill the tail).
+vesis_status batch_density(vesis_ctx* c0, vesis_ctx* const* c, const std::vector<int>& which,
+                           char* bws, const BatchLayout& L, int variant) {
+    vesis_ctx* ctx = c0;
+    hipStream_t st = c0->stream;
+    if (which.empty()) return VESIS_OK;
+    std::vector<int> order(which);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (double)c[x]->na * (double)c[x]->g.ncell() > (double)c[y]->na * (double)c[y]->g.ncell();
+    });
+    std::vector<MolDesc> desc(order.size());
+    std::vector<int> map;
+    for (size_t k = 0; k < order.size(); ++k) {
+        desc[k] = mol_desc(c[order[k]]);
+        desc[k].brick0 = (int64_t)map.size();
+        map.insert(map.end(), (size_t)density_bricks(c[order[k]]->g, variant), (int)k);
+    }
+    CK(hipMemcpyAsync(bws + L.desc, desc.data(), sizeof(MolDesc) * desc.size(),
+                      hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(bws + L.dmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
+    {
+        Timed t(c0, K_DENSITY);
+        CK(launch_density_batch(reinterpret_cast<const MolDesc*>(bws + L.desc),
+                                reinterpret_cast<const int*>(bws + L.dmap), (int64_t)map.size(),
+                                variant, st));
+    }
+    // the host vectors must outlive the copies
+    CK(hipStreamSynchronize(st));
+    return VESIS_OK;
+}
+
+}  // namespace
+
+vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_t* bytes) {
+    if (!ctxs || !bytes || m < 1 || m > BATCH_MAX) return VESIS_E_ARG;
+    for (int i = 0; i < m; ++i)
+        if (!ctxs[i] || !ctxs[i]->has_grid || !ctxs[i]->has_params)
+            return fail(ctxs[0], VESIS_E_STATE, "batch members need parameters and a grid");
+    int64_t db, fb;
+    batch_blocks(ctxs, m, db, fb);
+    *bytes = batch_layout(m, db, fb).total;
+    return VESIS_OK;
+}
+
+vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
+                              int32_t* best, double* ms) {
+    BatchLayout L;
+    vesis_status s = batch_check(ctxs, m, bws, bytes, false, L);
+    if (s != VESIS_OK) return s;
+    if (!best) return fail(ctxs[0], VESIS_E_ARG, "null argument");
+    vesis_ctx* ctx = ctxs[0];
+    hipStream_t st = ctx->stream;
+    std::vector<int> all(m);
+    for (int i = 0; i < m; ++i) all[i] = i;
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    double tbest = 0.0;
+    for (int v = 0; v < DENSITY_VARIANTS; ++v) {
+        double tv = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run also warms the caches
+            CK(hipEventRecord(e0, st));
+            s = batch_density(ctx, ctxs, all, static_cast<char*>(bws), L, v);
+            if (s != VESIS_OK) break;
+            CK(hipEventRecord(e1, st));
+            CK(hipEventSynchronize(e1));
+            float t = 0.f;
+            CK(hipEventElapsedTime(&t, e0, e1));
+            tv = std::min(tv, (double)t);
+        }
+        if (s != VESIS_OK) break;
+        if (ms) ms[v] = tv;
+        if (v == 0 || tv < tbest) {
+            tbest = tv;
+            *best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the densities now come from the last variant tried: recompute on use
+    for (int i = 0; i < m; ++i) {
+        ctxs[i]->dens_valid = false;
+        ctxs[i]->forces_valid = false;
+    }
+    return s;
+}
+
+vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
+                                  int32_t max_sweeps, int32_t variant, vesis_min_stats* out) {
+    BatchLayout L;
+    vesis_status s = batch_check(ctxs, m, bws, bytes, true, L);
+    if (s != VESIS_OK) return s;
+    vesis_ctx* ctx = ctxs[0];
+    if (max_sweeps < 1) return fail(ctx, VESIS_E_ARG, "max_sweeps must be >= 1");
+    if (variant < 0 || variant >= DENSITY_VARIANTS)
+        return fail(ctx, VESIS_E_ARG, "density variant out of range");
+    hipStream_t st = ctx->stream;
+    char* b = static_cast<char*>(bws);
+    // a1 + a2: one density launch over every molecule whose atoms changed
+    std::vector<int> stale;
+    for (int i = 0; i < m; ++i)
+        if (!ctxs[i]->dens_valid) stale.push_back(i);
+    s = batch_density(ctx, ctxs, stale, b, L, variant);
+    if (s != VESIS_OK) return s;
+    for (int i : stale) {
+        s = density_tail(ctxs[i]);
+        if (s != VESIS_OK) return s;
+    }
+    // a3 + a4: one launch per colour pass over every unconverged molecule
+    const int p = ctx->sc.p, ncol = p * p * p;
+    std::vector<MolDesc> desc(m);
+    for (int i = 0; i < m; ++i) {
+        vesis_ctx* c = ctxs[i];
+        desc[i] = mol_desc(c);
+        CK(launch_fill_i64(desc[i].counters, 2, 0, st));
+        CK(launch_fill_u32(reinterpret_cast<uint32_t*>(desc[i].stamp), c->g.nwords(),
+                           (uint32_t)(-(1 << 30)), st));
+    }
+    std::vector<char> done(m, 0);
+    std::vector<int> msweeps(m, 0);
+    std::vector<int64_t> mflips(m, 0);
+    std::vector<int> map, hf((size_t)m * SWEEP_BATCH);
+    const MolDesc* ddesc = reinterpret_cast<const MolDesc*>(b + L.desc);
+    int sweeps = 0, active = m;
+    bool rebuild = true;
+    while (sweeps < max_sweeps && active > 0) {
+        if (rebuild) {
+            map.clear();
+            for (int i = 0; i < m; ++i) {
+                if (done[i]) continue;
+                desc[i].slot0 = (int64_t)map.size() * FLIP_WG;
+                map.insert(map.end(), (size_t)(flip_slots(ctxs[i]->g, p) / FLIP_WG), i);
+            }
+            CK(hipMemcpyAsync(b + L.desc, desc.data(), sizeof(MolDesc) * m, hipMemcpyHostToDevice,
+                              st));
+            CK(hipMemcpyAsync(b + L.fmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
+            rebuild = false;
+        }
+        const int nb = std::min(SWEEP_BATCH, max_sweeps - sweeps);
+        CK(launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, st));
+        {
+            Timed t(ctx, K_FLIP);
+            for (int sw = 0; sw < nb; ++sw)
+                for (int c = 0; c < ncol; ++c)
+                    CK(launch_flip_pass_batch(ddesc, reinterpret_cast<const int*>(b + L.fmap),
+                                              (int64_t)map.size(), p, c, sw,
+                                              (sweeps + sw) * ncol + c, st));
+        }
+        CK(launch_batch_gather_flips(ddesc, m, SWEEP_BATCH, reinterpret_cast<int*>(b + L.flips),
+                                     st));
+        CK(hipMemcpyAsync(hf.data(), b + L.flips, 4 * hf.size(), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int i = 0; i < m; ++i) {
+            if (done[i]) continue;
+            for (int sw = 0; sw < nb; ++sw) {
+                const int f = hf[(size_t)i * SWEEP_BATCH + sw];
+                mflips[i] += f;
+                ++msweeps[i];
+                if (f == 0) {
+                    done[i] = 1;
+                    --active;
+                    rebuild = true;
+                    break;
+                }
+            }
+        }
+        sweeps += nb;
+    }
+    for (int i = 0; i < m; ++i) {
+        vesis_ctx* c = ctxs[i];
+        if (mflips[i] > 0) c->forces_valid = false;
+        if (!out) continue;
+        int64_t cnt[2] = {0, 0}, band = 0;
+        vesis_ctx* ctx_i = c;
+        {
+            vesis_ctx* ctx = ctx_i;  // error reporting goes to the member
+            CK(launch_band_count(c->g, at<uint32_t>(c, c->lay.bits), at<int64_t>(c, c->lay.red_i),
+                                 RED_BLOCKS, at<int64_t>(c, c->lay.scal_i) + SI_BAND, st));
+            CK(hipMemcpyAsync(cnt, desc[i].counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+            CK(hipMemcpyAsync(&band, c->ws + c->lay.scal_i + 8 * SI_BAND, sizeof(band),
+                              hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+        }
+        out[i].sweeps = msweeps[i];
+        out[i].converged = done[i] ? 1 : 0;
+        out[i].flips = mflips[i];
+        out[i].band_cells = band;
+        out[i].near_ties = cnt[0];
+        out[i].fp64_recomputes = cnt[1];
+    }
+    ctx->err.clear();
+    return active == 0 ? VESIS_OK : VESIS_NOT_CONVERGED;
 }
 
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out) {

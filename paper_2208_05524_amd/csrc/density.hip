@@ -75,11 +75,12 @@ __device__ inline double cell_bound(double errLJ, double errE, double ex, double
     return 1.001 * (errLJ + fabs(ccfa) * (2.0 * emag * d + d * d));
 }
 
-// Four wavefronts per SIMD: at up to 128 VGPRs the loop keeps its two atoms
-// x two cells in flight; the compiler's default allocation lands above 128
-// and drops to three.
-__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void density_grid_f32(
-    Grid g, Atoms a, Physics ph, CellFields out) {
+// The FP32 grid kernel's work for one brick of 16 x 8 x BZV cells (KCV cells
+// per lane stacked along z), shared by the single-molecule and the batched
+// launches.
+template <int KCV, int BZV>
+__device__ __forceinline__ void density_brick_f32(const Grid& g, const Atoms& a, const Physics& ph,
+                                                  const CellFields& out, int64_t brick) {
     __shared__ float4 spos[TILE];     // far atoms: rebased FP32 position, |Q|
     __shared__ float4 sprm[TILE];     // far atoms: c6, c12, Q
     __shared__ double4 npos[TILE];    // near atoms: FP64 position, sigma^2
@@ -90,26 +91,26 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int lane = t & 63, wv = t >> 6;
     const int tx = t & 15, ty = (t >> 4) & 7, tz = t >> 7;
     const int nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY;
-    int b = blockIdx.x;
+    int b = (int)brick;
     const int bx = b % nbx;
     b /= nbx;
     const int by = b % nby;
     const int bz = b / nby;
-    const int i = bx * BX + tx, j = by * BY + ty, k0 = bz * BZ + tz * KC;
+    const int i = bx * BX + tx, j = by * BY + ty, k0 = bz * BZV + tz * KCV;
 
     // brick centre in FP64; lane cell offsets from it in FP32 (far atoms)
     // and the lane's cell centres in FP64 (near atoms)
     const double ox = g.x0 + (bx * BX + 0.5 * (BX - 1)) * g.h;
     const double oy = g.y0 + (by * BY + 0.5 * (BY - 1)) * g.h;
-    const double oz = g.z0 + (bz * BZ + 0.5 * (BZ - 1)) * g.h;
+    const double oz = g.z0 + (bz * BZV + 0.5 * (BZV - 1)) * g.h;
     const float cx = (float)((tx - 0.5 * (BX - 1)) * g.h);
     const float cy = (float)((ty - 0.5 * (BY - 1)) * g.h);
     const double x64 = g.x0 + i * g.h, y64 = g.y0 + j * g.h;
-    float cz[KC];
-    double z64[KC];
+    float cz[KCV];
+    double z64[KCV];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        cz[k] = (float)((tz * KC + k - 0.5 * (BZ - 1)) * g.h);
+    for (int k = 0; k < KCV; ++k) {
+        cz[k] = (float)((tz * KCV + k - 0.5 * (BZV - 1)) * g.h);
         z64[k] = g.z0 + (k0 + k) * g.h;
     }
     // atoms within 12h of the brick centre are "near": they are summed in
@@ -118,11 +119,11 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const double rnear = 12.0 * g.h + 4.0 * sqrt(ph.r2min);
     const float rnear2 = (float)(rnear * rnear);
     // half extents of the box spanned by the brick's cell centres
-    const double hxe = 0.5 * (BX - 1) * g.h, hye = 0.5 * (BY - 1) * g.h, hze = 0.5 * (BZ - 1) * g.h;
+    const double hxe = 0.5 * (BX - 1) * g.h, hye = 0.5 * (BY - 1) * g.h, hze = 0.5 * (BZV - 1) * g.h;
 
-    double dP[KC], dQ[KC], dEx[KC], dEy[KC], dEz[KC], dMag[KC], dAE[KC], nMag[KC], nAE[KC];
+    double dP[KCV], dQ[KCV], dEx[KCV], dEy[KCV], dEz[KCV], dMag[KCV], dAE[KCV], nMag[KCV], nAE[KCV];
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
+    for (int k = 0; k < KCV; ++k)
         dP[k] = dQ[k] = dEx[k] = dEy[k] = dEz[k] = dMag[k] = dAE[k] = nMag[k] = nAE[k] = 0.0;
 
     for (int64_t base = 0; base < a.n; base += TILE) {
@@ -187,14 +188,14 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
         // far atoms, FP32: 32-atom partials, summed over the tile in FP32,
         // folded into FP64 once per tile
-        float TP[KC], TQ[KC], TEx[KC], TEy[KC], TEz[KC];
+        float TP[KCV], TQ[KCV], TEx[KCV], TEy[KCV], TEz[KCV];
 #pragma unroll
-        for (int k = 0; k < KC; ++k) TP[k] = TQ[k] = TEx[k] = TEy[k] = TEz[k] = 0.f;
+        for (int k = 0; k < KCV; ++k) TP[k] = TQ[k] = TEx[k] = TEy[k] = TEz[k] = 0.f;
         for (int m0 = 0; m0 < nfar; m0 += SUB) {
             const int me = (m0 + SUB < nfar) ? m0 + SUB : nfar;
-            float P[KC], Q[KC], Ex[KC], Ey[KC], Ez[KC];
+            float P[KCV], Q[KCV], Ex[KCV], Ey[KCV], Ez[KCV];
 #pragma unroll
-            for (int k = 0; k < KC; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = 0.f;
+            for (int k = 0; k < KCV; ++k) P[k] = Q[k] = Ex[k] = Ey[k] = Ez[k] = 0.f;
 #pragma unroll 2
             for (int m = m0; m < me; ++m) {
                 const float4 pp = spos[m];
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 const float dx = cx - pp.x, dy = cy - pp.y;
                 const float dxy = fmaf(dx, dx, dy * dy);
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
+                for (int k = 0; k < KCV; ++k) {
                     const float dz = cz[k] - pp.z;
                     // far atoms lie beyond 4 sqrt(r2_min): no floor needed
                     const float r2 = fmaf(dz, dz, dxy);
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 }
             }
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
+            for (int k = 0; k < KCV; ++k) {
                 TP[k] += P[k];
                 TQ[k] += Q[k];
                 TEx[k] += Ex[k];
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
         }
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
+        for (int k = 0; k < KCV; ++k) {
             dP[k] += TP[k];
             dQ[k] += TQ[k];
             dEx[k] += TEx[k];
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             const double4 q = nprm[m];
             const double dx = x64 - pp.x, dy = y64 - pp.y;
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
+            for (int k = 0; k < KCV; ++k) {
                 const double dz = z64[k] - pp.z;
                 const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
                 double ir = __builtin_amdgcn_rsq(r2);
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
     if (i >= g.n || j >= g.n) return;
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
+    for (int k = 0; k < KCV; ++k) {
         const int kk = k0 + k;
         if (kk >= g.n) continue;
         const int64_t c = (int64_t)i + (int64_t)g.n * (j + (int64_t)g.n * kk);
@@ -282,6 +283,22 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                   KAPPA_E * U32 * dAE[k] + NEAR_REL * nAE[k], dEx[k], dEy[k],
                                   dEz[k], ph.ccfa);
     }
+}
+
+// Four wavefronts per SIMD: at up to 128 VGPRs the loop keeps its two atoms
+// x two cells in flight; the compiler's default allocation lands above 128
+// and drops to three.
+__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void density_grid_f32(
+    Grid g, Atoms a, Physics ph, CellFields out) {
+    density_brick_f32<KC, BZ>(g, a, ph, out, blockIdx.x);
+}
+
+// Batched: block b works on brick b - brick0 of molecule block_mol[b].
+template <int KCV, int BZV>
+__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void density_batch_f32(
+    const MolDesc* desc, const int* block_mol) {
+    const MolDesc& d = desc[block_mol[blockIdx.x]];
+    density_brick_f32<KCV, BZV>(d.g, d.a, d.ph, d.f, (int64_t)blockIdx.x - d.brick0);
 }
 
 // FP64 variant: same brick and tiling, FP64 arithmetic and accumulation
@@ -508,6 +525,24 @@ hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph,
         hipLaunchKernelGGL(density_grid_f64, dim3(nblk), dim3(DWG), 0, st, g, a, ph, out);
     else
         hipLaunchKernelGGL(density_grid_f32, dim3(nblk), dim3(DWG), 0, st, g, a, ph, out);
+    return hipGetLastError();
+}
+
+int64_t density_bricks(const Grid& g, int variant) {
+    const int bz = variant == 1 ? 2 : BZ;
+    const int64_t nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY, nbz = (g.n + bz - 1) / bz;
+    return nbx * nby * nbz;
+}
+
+hipError_t launch_density_batch(const MolDesc* desc, const int* block_mol, int64_t nblocks,
+                                int variant, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    if (variant == 1)
+        hipLaunchKernelGGL((density_batch_f32<1, 2>), dim3((unsigned)nblocks), dim3(DWG), 0, st,
+                           desc, block_mol);
+    else
+        hipLaunchKernelGGL((density_batch_f32<KC, BZ>), dim3((unsigned)nblocks), dim3(DWG), 0, st,
+                           desc, block_mol);
     return hipGetLastError();
 }
 

@@ -68,6 +68,24 @@ struct CellFields {
 
 enum KernelKind { K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6, K_NKINDS = 7 };
 
+// One molecule of a batch, in device memory: what the batched density and
+// flip-pass kernels need.  brick0 / slot0: the molecule's first brick and
+// first flip-pass slot in the batch's launch order.
+struct MolDesc {
+    Grid g;
+    Stencil sc;
+    Atoms a;
+    Physics ph;
+    CellFields f;
+    uint32_t* bits;
+    int* stamp;
+    double* u64cache;
+    int* sweep_flips;
+    int64_t* counters;
+    int64_t brick0;
+    int64_t slot0;
+};
+
 // Launch wrappers (one per translation unit; all asynchronous on `st`).
 hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph, int precision,
                                CellFields out, hipStream_t st);
@@ -82,6 +100,14 @@ hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a,
 hipError_t launch_weighted_sum2(const double4* pts, const double* a, const double* b, int64_t np,
                                 double* partial, int nblocks, double* out, hipStream_t st);
 
+// Batched density (FP32): variant 0 = 2 cells per lane on 16 x 8 x 4 bricks,
+// 1 = 1 cell per lane on 16 x 8 x 2 bricks.  block_mol maps each block to its
+// molecule; a molecule's blocks are consecutive, from desc[m].brick0.
+constexpr int DENSITY_VARIANTS = 2;
+int64_t density_bricks(const Grid& g, int variant);
+hipError_t launch_density_batch(const MolDesc* desc, const int* block_mol, int64_t nblocks,
+                                int variant, hipStream_t st);
+
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
@@ -95,6 +121,15 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                             int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
                             const double* ulj, const double* ucfa, const double* bound,
                             double* u64cache, int* sweep_flips, int64_t* counters, hipStream_t st);
+// Batched colour pass: flip_slots(g, p) thread slots per molecule (a multiple
+// of the workgroup size), a molecule's blocks consecutive from slot0.
+constexpr int FLIP_WG = 256;
+int64_t flip_slots(const Grid& g, int p);
+hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, int64_t nblocks,
+                                  int p, int colour, int sweep, int gpass, hipStream_t st);
+hipError_t launch_batch_clear_flips(const MolDesc* descs, int m, int nsweeps, hipStream_t st);
+hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out,
+                                     hipStream_t st);
 hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
                                 const double* ucfa, double* partial, int nblocks, double* out,
                                 hipStream_t st);

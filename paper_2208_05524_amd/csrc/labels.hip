@@ -269,22 +269,36 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
 // pass P - ncol; if its stamp is older than that, nothing in its cells'
 // neighbourhoods changed since then, every decision would repeat (no flip),
 // and the word is skipped.  The first sweep of a call evaluates every word.
-__global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atoms a, Physics ph,
-                                                        int colour, int sweep, int gpass, int ncol,
-                                                        uint32_t* bits, int* stamp,
-                                                        const double* ulj, const double* ucfa,
-                                                        const double* bound, double* u64cache,
-                                                        int* sweep_flips, int64_t* counters) {
+// One colour pass.  BATCH = false: one molecule, described by `one`; BATCH =
+// true: block b works on molecule block_mol[b] of `descs` (a molecule's
+// blocks are consecutive from slot0 / FWG, so a block never spans two).
+template <bool BATCH>
+__global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDesc* descs,
+                                                        const int* block_mol, int colour,
+                                                        int sweep, int gpass, int ncol) {
     __shared__ double s_red[4 * FWG];
     __shared__ int s_leader;
     __shared__ int s_tie[4];
+    const MolDesc& D = BATCH ? descs[block_mol[blockIdx.x]] : one;
+    const Grid& g = D.g;
+    const Stencil& sc = D.sc;
+    const Atoms& a = D.a;
+    const Physics& ph = D.ph;
+    uint32_t* bits = D.bits;
+    int* stamp = D.stamp;
+    const double* ulj = D.f.ulj;
+    const double* ucfa = D.f.ucfa;
+    const double* bound = D.f.bound;
+    double* u64cache = D.u64cache;
+    int* sweep_flips = D.sweep_flips;
+    int64_t* counters = D.counters;
     // a sweep that follows a sweep without flips has nothing to do
     if (sweep > 0 && sweep_flips[sweep - 1] == 0) return;
     const int p = sc.p;
     const int ca = colour % p, cb = (colour / p) % p, cc = colour / (p * p);
     const int ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
     const int64_t total = (int64_t)g.nwin * ny * nz;
-    const int64_t tid = (int64_t)blockIdx.x * FWG + threadIdx.x;
+    const int64_t tid = (int64_t)blockIdx.x * FWG - (BATCH ? D.slot0 : 0) + threadIdx.x;
     const bool active = tid < total;
     int w = 0, y = 0, z = 0;
     if (active) {
@@ -379,6 +393,18 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(Grid g, Stencil sc, Atom
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) nf += __shfl_xor(nf, off);
     if ((t & 63) == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
+}
+
+// Zero the sweep flip counters of every molecule of a batch.
+__global__ void batch_clear_flips(const MolDesc* descs, int m, int nsweeps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * nsweeps) descs[i / nsweeps].sweep_flips[i % nsweeps] = 0;
+}
+
+// Gather the sweep flip counters of every molecule into one array.
+__global__ void batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * nsweeps) out[i] = descs[i / nsweeps].sweep_flips[i % nsweeps];
 }
 
 // ------------------------------------------------------------ reductions
@@ -526,9 +552,51 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     const int64_t ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
     const int64_t total = (int64_t)g.nwin * ny * nz;
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(flip_pass_kernel, dim3(nblk(total, FWG)), dim3(FWG), 0, st, g, sc, a, ph,
-                       colour, sweep, gpass, p * p * p, bits, stamp, ulj, ucfa, bound, u64cache,
-                       sweep_flips, counters);
+    MolDesc d{};
+    d.g = g;
+    d.sc = sc;
+    d.a = a;
+    d.ph = ph;
+    d.f.ulj = const_cast<double*>(ulj);
+    d.f.ucfa = const_cast<double*>(ucfa);
+    d.f.bound = const_cast<double*>(bound);
+    d.bits = bits;
+    d.stamp = stamp;
+    d.u64cache = u64cache;
+    d.sweep_flips = sweep_flips;
+    d.counters = counters;
+    hipLaunchKernelGGL(flip_pass_kernel<false>, dim3(nblk(total, FWG)), dim3(FWG), 0, st, d,
+                       nullptr, nullptr, colour, sweep, gpass, p * p * p);
+    return hipGetLastError();
+}
+
+static_assert(FWG == FLIP_WG, "flip-pass workgroup size");
+
+int64_t flip_slots(const Grid& g, int p) {
+    const int64_t ny = (g.n + p - 1) / p;
+    const int64_t slots = (int64_t)g.nwin * ny * ny;
+    return (slots + FWG - 1) / FWG * FWG;
+}
+
+hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, int64_t nblocks,
+                                  int p, int colour, int sweep, int gpass, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    MolDesc unused{};
+    hipLaunchKernelGGL(flip_pass_kernel<true>, dim3((unsigned)nblocks), dim3(FWG), 0, st, unused,
+                       descs, block_mol, colour, sweep, gpass, p * p * p);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_clear_flips(const MolDesc* descs, int m, int nsweeps, hipStream_t st) {
+    hipLaunchKernelGGL(batch_clear_flips, dim3(nblk((int64_t)m * nsweeps, 256)), dim3(256), 0, st,
+                       descs, m, nsweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(batch_gather_flips, dim3(nblk((int64_t)m * nsweeps, 256)), dim3(256), 0, st,
+                       descs, m, nsweeps, out);
     return hipGetLastError();
 }
 

@@ -199,3 +199,54 @@ class Context:
         self._check(self.lib.vesis_profile_read(self.h, KERNEL_KINDS[kind], C.byref(ms),
                                                 C.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Several contexts (one molecule each) relaxed together: one density
+    launch and one launch per colour pass for the whole batch.  The batch's
+    tables live in one more torch uint8 device tensor."""
+
+    def __init__(self, contexts):
+        if not contexts:
+            raise ValueError("empty batch")
+        self.contexts = list(contexts)
+        self.lib = self.contexts[0].lib
+        self._torch = self.contexts[0]._torch
+        m = len(self.contexts)
+        self._arr = (C.c_void_p * m)(*[c.h for c in self.contexts])
+        n = C.c_size_t()
+        rc = self.lib.vesis_batch_workspace_size(self._arr, m, C.byref(n))
+        self._check(rc)
+        t = self._torch
+        self.nbytes = int(n.value)
+        self.workspace = t.empty(self.nbytes + 256, dtype=t.uint8,
+                                 device=self.contexts[0].device)
+        self._ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.variant = 0
+
+    def _check(self, rc, allow=(0,)):
+        if rc not in allow:
+            msg = self.lib.vesis_last_error(self.contexts[0].h)
+            raise VesisError(rc, msg.decode() if msg else "")
+        return rc
+
+    def tune(self):
+        """Time the density variants on this batch and keep the fastest."""
+        best = C.c_int32()
+        ms = (C.c_double * 2)()
+        self._check(self.lib.vesis_batch_tune(self._arr, len(self.contexts),
+                                              C.c_void_p(self._ptr), self.nbytes,
+                                              C.byref(best), ms))
+        self.variant = int(best.value)
+        return self.variant, [ms[0], ms[1]]
+
+    def minimize(self, max_sweeps: int = 20000, variant=None):
+        m = len(self.contexts)
+        st = (MinStats * m)()
+        v = self.variant if variant is None else int(variant)
+        rc = self._check(self.lib.vesis_minimize_batch(self._arr, m, C.c_void_p(self._ptr),
+                                                       self.nbytes, int(max_sweeps), v, st),
+                         allow=(0, 1))
+        return rc, [dict(sweeps=s.sweeps, converged=s.converged, flips=s.flips,
+                         band=s.band_cells, near_ties=s.near_ties,
+                         fp64_recomputes=s.fp64_recomputes) for s in st]

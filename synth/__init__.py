@@ -116,9 +116,48 @@ def _unit_vectors(rng: SplitMix64, m: int) -> np.ndarray:
     return np.asarray(out[:m])
 
 
+_WALK = None
+
+
+def _walk_lib():
+    """The compiled walk (synth/walk.c), or None if it has not been built."""
+    global _WALK
+    if _WALK is None:
+        import ctypes as C
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwalk.so")
+        _WALK = False
+        if os.path.exists(path):
+            lib = C.CDLL(path)
+            lib.synth_globule.argtypes = [C.c_int64, C.c_uint64, C.c_double, C.c_double,
+                                          C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p]
+            lib.synth_globule.restype = C.c_int
+            _WALK = lib
+    return _WALK or None
+
+
 def globule(natoms: int, seed: int, bond: float = 0.15, min_sep: float = 0.30,
             min_sep2: float = 0.24, density: float = 35.0, trials: int = 200,
-            backtrack: int = 10) -> np.ndarray:
+            backtrack: int = 10, compiled: bool = True) -> np.ndarray:
+    """Seeded self-avoiding chain confined to a sphere ("protein-like globule").
+
+    Uses the compiled walk of synth/walk.c when it has been built (the same
+    draws and decisions, bit for bit; a CPU test checks this), else the
+    Python walk below.
+    """
+    lib = _walk_lib() if compiled else None
+    if lib is not None:
+        pos = np.zeros((natoms, 3))
+        rc = lib.synth_globule(natoms, seed & 0xFFFFFFFFFFFFFFFF, bond, min_sep, min_sep2,
+                               density, trials, backtrack, pos.ctypes.data)
+        if rc != 0:
+            raise RuntimeError("globule walk did not finish")
+        return pos - pos.mean(axis=0)
+    return _globule_py(natoms, seed, bond, min_sep, min_sep2, density, trials, backtrack)
+
+
+def _globule_py(natoms: int, seed: int, bond: float, min_sep: float, min_sep2: float,
+                density: float, trials: int, backtrack: int) -> np.ndarray:
     """Seeded self-avoiding chain confined to a sphere ("protein-like globule").
 
     Consecutive atoms sit ``bond`` apart; atoms two apart keep ``min_sep2``,

@@ -1,5 +1,6 @@
 """The seeded input generators: determinism and the stated geometry."""
 import numpy as np
+import pytest
 
 import synth
 
@@ -38,3 +39,13 @@ def test_two_globules_fit_the_box():
     w = synth.two_globules()
     L = w.n * w.h / 2
     assert np.abs(w.xyz).max() + 0.4 + 3 * w.h < L
+
+
+@pytest.mark.parametrize("natoms,seed", [(300, 1), (1000, 2000), (2500, 4017)])
+def test_compiled_walk_matches_python_walk(natoms, seed):
+    """The compiled globule walk reproduces the Python walk bit for bit."""
+    if synth._walk_lib() is None:
+        pytest.skip("synth/libwalk.so not built")
+    a = synth.globule(natoms, seed, compiled=False)
+    b = synth.globule(natoms, seed, compiled=True)
+    assert np.array_equal(a, b)
