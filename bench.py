@@ -67,7 +67,8 @@ def batch_comparison(rounds: int = 2):
     3000], grids 64^3 to 160^3 at 0.05 nm): each molecule on its own (tight
     labels, density, far field, colour sweeps, one call per molecule) against
     the batched call (one density launch and one launch per colour pass for
-    all molecules).  Both start from the same positions and labels; the
+    all molecules, groups of sweeps replayed from a captured graph; also
+    timed with direct launches).  Both start from the same positions and labels; the
     labels they reach and their energies are compared."""
     import numpy as np
     import torch
@@ -89,7 +90,7 @@ def batch_comparison(rounds: int = 2):
         torch.cuda.synchronize()
 
     best, tune_ms = b.tune()
-    plain_ms, batch_ms = [], []
+    plain_ms, batch_ms, eager_ms = [], [], []
     for r in range(rounds + 1):
         reset()
         t0 = time.perf_counter()
@@ -108,9 +109,21 @@ def batch_comparison(rounds: int = 2):
         rc, st = b.minimize(variant=best)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        reset()
+        t4 = time.perf_counter()
+        for c in ctxs:
+            c.init_labels("tight", 1.0)
+        b.minimize(variant=best, graph=False)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
         if r > 0:  # round 0 warms up
             plain_ms.append(1e3 * (t1 - t0))
             batch_ms.append(1e3 * (t3 - t2))
+            eager_ms.append(1e3 * (t5 - t4))
+    reset()  # leave the graph-replayed result in place for the comparison
+    for c in ctxs:
+        c.init_labels("tight", 1.0)
+    rc, st = b.minimize(variant=best)
     same = all(np.array_equal(a, c.labels()) for a, c in zip(lab_plain, ctxs))
     e_batch = [c.energy()["total"] for c in ctxs]
     rel = max(abs(a - e) / abs(a) for a, e in zip(e_plain, e_batch))
@@ -118,6 +131,7 @@ def batch_comparison(rounds: int = 2):
     out = {"molecules": len(ws), "atoms": int(sum(w.natoms for w in ws)),
            "cells": int(sum(w.n ** 3 for w in ws)), "pairs": pairs,
            "plain_ms": min(plain_ms), "batched_ms": min(batch_ms),
+           "batched_without_graph_ms": min(eager_ms),
            "speedup": min(plain_ms) / min(batch_ms),
            "batched_atom_gridpt_per_s": pairs / (min(batch_ms) / 1e3),
            "density_variant": best, "tune_ms": tune_ms,

@@ -254,12 +254,17 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* batch_ws,
 
 /* Relax the interfaces of m molecules (Step 2 for each), recomputing the
  * density of those whose atoms changed with density variant `variant`.
+ * Sweeps run in groups of 8; a full group is captured once as a HIP graph
+ * (on a private stream) and replayed on the context stream, unless flags
+ * holds VESIS_BATCH_EAGER.
  * out (m entries, may be NULL) receives each molecule's statistics.
  * Returns VESIS_OK when every molecule converged within max_sweeps,
  * VESIS_NOT_CONVERGED otherwise (the others keep their state and a new call
  * resumes them). */
+#define VESIS_BATCH_EAGER 1 /* flags: launch every pass directly instead of replaying a graph */
 vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* batch_ws, size_t bytes,
-                                  int32_t max_sweeps, int32_t variant, vesis_min_stats* out);
+                                  int32_t max_sweeps, int32_t variant, int32_t flags,
+                                  vesis_min_stats* out);
 
 /* Copy the labels (n^3 int8, -1/+1) to host memory. */
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);

@@ -112,7 +112,7 @@ def load():
     L.vesis_batch_tune.argtypes = [PP, C.c_int32, P, C.c_size_t, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double)]
     L.vesis_minimize_batch.argtypes = [PP, C.c_int32, P, C.c_size_t, C.c_int32, C.c_int32,
-                                       C.POINTER(MinStats)]
+                                       C.c_int32, C.POINTER(MinStats)]
     L.vesis_get_labels.argtypes = [P, P]
     L.vesis_get_density.argtypes = [P, P, P, P]
     L.vesis_profile.argtypes = [P, I32]

@@ -120,6 +120,8 @@ struct vesis_ctx {
     bool dens_valid = false;
     bool forces_valid = false;
 
+    hipStream_t capture = nullptr;  // private stream for graph capture (made on first use)
+
     bool prof = false;
     double prof_ms[K_NKINDS] = {0};
     int64_t prof_n[K_NKINDS] = {0};
@@ -545,6 +547,7 @@ vesis_status vesis_create(int32_t device, void* stream, vesis_ctx** out) {
 void vesis_destroy(vesis_ctx* ctx) {
     if (!ctx) return;
     if (!ctx->pending.empty()) drain_events(ctx);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
 
@@ -1022,7 +1025,7 @@ namespace {
 constexpr int BATCH_MAX = 4096;
 
 struct BatchLayout {
-    size_t desc, dmap, fmap, flips, total;
+    size_t desc, dmap, fmap, flips, done, pass, total;
 };
 
 BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
@@ -1037,6 +1040,8 @@ BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
     L.dmap = take(4 * (size_t)dens_blocks);
     L.fmap = take(4 * (size_t)flip_blocks);
     L.flips = take(4 * (size_t)m * SWEEP_BATCH);
+    L.done = take(4 * (size_t)m);
+    L.pass = take(4);
     L.total = o;
     return L;
 }
@@ -1199,7 +1204,8 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
 }
 
 vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
-                                  int32_t max_sweeps, int32_t variant, vesis_min_stats* out) {
+                                  int32_t max_sweeps, int32_t variant, int32_t flags,
+                                  vesis_min_stats* out) {
     BatchLayout L;
     vesis_status s = batch_check(ctxs, m, bws, bytes, true, L);
     if (s != VESIS_OK) return s;
@@ -1233,36 +1239,76 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     std::vector<int> msweeps(m, 0);
     std::vector<int64_t> mflips(m, 0);
     std::vector<int> map, hf((size_t)m * SWEEP_BATCH);
+    for (int i = 0; i < m; ++i) {
+        desc[i].slot0 = (int64_t)map.size() * FLIP_WG;
+        map.insert(map.end(), (size_t)(flip_slots(ctxs[i]->g, p) / FLIP_WG), i);
+    }
     const MolDesc* ddesc = reinterpret_cast<const MolDesc*>(b + L.desc);
+    const int* dmap = reinterpret_cast<const int*>(b + L.fmap);
+    int* ddone = reinterpret_cast<int*>(b + L.done);
+    int* dpass = reinterpret_cast<int*>(b + L.pass);
+    int* dflips = reinterpret_cast<int*>(b + L.flips);
+    const int64_t nblocks = (int64_t)map.size();
+    CK(hipMemcpyAsync(b + L.desc, desc.data(), sizeof(MolDesc) * m, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(b + L.fmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
+    CK(launch_fill_u32(reinterpret_cast<uint32_t*>(ddone), m, 0u, st));
+    CK(launch_fill_u32(reinterpret_cast<uint32_t*>(dpass), 1, 0u, st));
+    CK(hipStreamSynchronize(st));  // the host tables must outlive the copies
+    // one group of sweeps: every pass of every colour over the molecules not
+    // yet done, then the done flags, the pass counter and the flip counts
+    auto enqueue_group = [&](hipStream_t s2, int nb) -> hipError_t {
+        hipError_t e = launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, s2);
+        for (int sw = 0; sw < nb && e == hipSuccess; ++sw)
+            for (int c = 0; c < ncol && e == hipSuccess; ++c)
+                e = launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, sw,
+                                           sw * ncol + c, s2);
+        if (e == hipSuccess) e = launch_batch_end_group(ddesc, m, nb, ncol, ddone, dpass, s2);
+        if (e == hipSuccess) e = launch_batch_gather_flips(ddesc, m, SWEEP_BATCH, dflips, s2);
+        return e;
+    };
+    const bool use_graph = !(flags & VESIS_BATCH_EAGER);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto release = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
     int sweeps = 0, active = m;
-    bool rebuild = true;
     while (sweeps < max_sweeps && active > 0) {
-        if (rebuild) {
-            map.clear();
-            for (int i = 0; i < m; ++i) {
-                if (done[i]) continue;
-                desc[i].slot0 = (int64_t)map.size() * FLIP_WG;
-                map.insert(map.end(), (size_t)(flip_slots(ctxs[i]->g, p) / FLIP_WG), i);
-            }
-            CK(hipMemcpyAsync(b + L.desc, desc.data(), sizeof(MolDesc) * m, hipMemcpyHostToDevice,
-                              st));
-            CK(hipMemcpyAsync(b + L.fmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
-            rebuild = false;
-        }
         const int nb = std::min(SWEEP_BATCH, max_sweeps - sweeps);
-        CK(launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, st));
-        {
+        hipError_t e = hipSuccess;
+        if (use_graph && nb == SWEEP_BATCH) {
+            if (!exec) {
+                // the same group of launches every time: capture it once on a
+                // private stream, replay it on the caller's stream
+                if (!ctx->capture) {
+                    e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+                    if (e != hipSuccess) ctx->capture = nullptr;
+                }
+                if (e == hipSuccess) e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed);
+                if (e == hipSuccess) {
+                    const hipError_t e1 = enqueue_group(ctx->capture, nb);
+                    const hipError_t e2 = hipStreamEndCapture(ctx->capture, &graph);
+                    e = e1 != hipSuccess ? e1 : e2;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            }
+            if (e == hipSuccess) {
+                Timed t(ctx, K_FLIP);
+                e = hipGraphLaunch(exec, st);
+            }
+        } else {
             Timed t(ctx, K_FLIP);
-            for (int sw = 0; sw < nb; ++sw)
-                for (int c = 0; c < ncol; ++c)
-                    CK(launch_flip_pass_batch(ddesc, reinterpret_cast<const int*>(b + L.fmap),
-                                              (int64_t)map.size(), p, c, sw,
-                                              (sweeps + sw) * ncol + c, st));
+            e = enqueue_group(st, nb);
         }
-        CK(launch_batch_gather_flips(ddesc, m, SWEEP_BATCH, reinterpret_cast<int*>(b + L.flips),
-                                     st));
-        CK(hipMemcpyAsync(hf.data(), b + L.flips, 4 * hf.size(), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
+        if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), dflips, 4 * hf.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            release();
+            return fail(ctx, VESIS_E_DEVICE, std::string("batched sweeps: ") + hipGetErrorString(e));
+        }
         for (int i = 0; i < m; ++i) {
             if (done[i]) continue;
             for (int sw = 0; sw < nb; ++sw) {
@@ -1272,13 +1318,13 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
                 if (f == 0) {
                     done[i] = 1;
                     --active;
-                    rebuild = true;
                     break;
                 }
             }
         }
         sweeps += nb;
     }
+    release();
     for (int i = 0; i < m; ++i) {
         vesis_ctx* c = ctxs[i];
         if (mflips[i] > 0) c->forces_valid = false;

@@ -125,8 +125,14 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
 // of the workgroup size), a molecule's blocks consecutive from slot0.
 constexpr int FLIP_WG = 256;
 int64_t flip_slots(const Grid& g, int p);
-hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, int64_t nblocks,
-                                  int p, int colour, int sweep, int gpass, hipStream_t st);
+// done[k] != 0 skips molecule k; the pass index is *pass_base + gpass_off.
+hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
+                                  const int* pass_base, int64_t nblocks, int p, int colour,
+                                  int sweep, int gpass_off, hipStream_t st);
+// End of a group of nsweeps sweeps: flag molecules that had a sweep without
+// flips, advance *pass_base by nsweeps * ncol.
+hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,
+                                  int* pass_base, hipStream_t st);
 hipError_t launch_batch_clear_flips(const MolDesc* descs, int m, int nsweeps, hipStream_t st);
 hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out,
                                      hipStream_t st);

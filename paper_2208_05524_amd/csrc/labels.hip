@@ -272,13 +272,21 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
 // One colour pass.  BATCH = false: one molecule, described by `one`; BATCH =
 // true: block b works on molecule block_mol[b] of `descs` (a molecule's
 // blocks are consecutive from slot0 / FWG, so a block never spans two).
+// In a batch, molecules flagged in `done` are skipped and the pass index is
+// *pass_base + gpass, so that one captured sequence of passes can be
+// replayed.
 template <bool BATCH>
 __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDesc* descs,
-                                                        const int* block_mol, int colour,
+                                                        const int* block_mol, const int* done,
+                                                        const int* pass_base, int colour,
                                                         int sweep, int gpass, int ncol) {
     __shared__ double s_red[4 * FWG];
     __shared__ int s_leader;
     __shared__ int s_tie[4];
+    if (BATCH) {
+        if (done[block_mol[blockIdx.x]]) return;
+        gpass += *pass_base;
+    }
     const MolDesc& D = BATCH ? descs[block_mol[blockIdx.x]] : one;
     const Grid& g = D.g;
     const Stencil& sc = D.sc;
@@ -399,6 +407,20 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
 __global__ void batch_clear_flips(const MolDesc* descs, int m, int nsweeps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m * nsweeps) descs[i / nsweeps].sweep_flips[i % nsweeps] = 0;
+}
+
+// After a group of nsweeps sweeps: a molecule whose group holds a sweep
+// without flips is done; the pass counter advances by the group.
+__global__ void batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,
+                                int* pass_base) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *pass_base += nsweeps * ncol;
+    if (i >= m || done[i]) return;
+    for (int sw = 0; sw < nsweeps; ++sw)
+        if (descs[i].sweep_flips[sw] == 0) {
+            done[i] = 1;
+            return;
+        }
 }
 
 // Gather the sweep flip counters of every molecule into one array.
@@ -566,7 +588,7 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     d.sweep_flips = sweep_flips;
     d.counters = counters;
     hipLaunchKernelGGL(flip_pass_kernel<false>, dim3(nblk(total, FWG)), dim3(FWG), 0, st, d,
-                       nullptr, nullptr, colour, sweep, gpass, p * p * p);
+                       nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, p * p * p);
     return hipGetLastError();
 }
 
@@ -578,12 +600,20 @@ int64_t flip_slots(const Grid& g, int p) {
     return (slots + FWG - 1) / FWG * FWG;
 }
 
-hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, int64_t nblocks,
-                                  int p, int colour, int sweep, int gpass, hipStream_t st) {
+hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
+                                  const int* pass_base, int64_t nblocks, int p, int colour,
+                                  int sweep, int gpass_off, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     MolDesc unused{};
     hipLaunchKernelGGL(flip_pass_kernel<true>, dim3((unsigned)nblocks), dim3(FWG), 0, st, unused,
-                       descs, block_mol, colour, sweep, gpass, p * p * p);
+                       descs, block_mol, done, pass_base, colour, sweep, gpass_off, p * p * p);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,
+                                  int* pass_base, hipStream_t st) {
+    hipLaunchKernelGGL(batch_end_group, dim3(nblk(m, 256)), dim3(256), 0, st, descs, m, nsweeps,
+                       ncol, done, pass_base);
     return hipGetLastError();
 }
 

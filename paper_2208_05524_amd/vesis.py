@@ -240,12 +240,14 @@ class Batch:
         self.variant = int(best.value)
         return self.variant, [ms[0], ms[1]]
 
-    def minimize(self, max_sweeps: int = 20000, variant=None):
+    def minimize(self, max_sweeps: int = 20000, variant=None, graph: bool = True):
         m = len(self.contexts)
         st = (MinStats * m)()
         v = self.variant if variant is None else int(variant)
+        flags = 0 if graph else 1
         rc = self._check(self.lib.vesis_minimize_batch(self._arr, m, C.c_void_p(self._ptr),
-                                                       self.nbytes, int(max_sweeps), v, st),
+                                                       self.nbytes, int(max_sweeps), v, flags,
+                                                       st),
                          allow=(0, 1))
         return rc, [dict(sweeps=s.sweeps, converged=s.converged, flips=s.flips,
                          band=s.band_cells, near_ties=s.near_ties,

@@ -131,3 +131,31 @@ def test_full_batch_64_molecules_matches_single():
         assert (a["sweeps"], a["flips"], a["band"]) == (bb["sweeps"], bb["flips"], bb["band"])
         es, eb = cs.energy(), cb.energy()
         assert abs(es["total"] - eb["total"]) <= 1e-6 * abs(es["total"])
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured group of sweeps, replayed several times per call with the
+    host's reads and synchronisations between replays, ends where direct
+    launches end; twice in a row."""
+    from paper_2208_05524_amd import Batch
+    ws = _molecules()
+    eager = [gpu_context(w) for w in ws]
+    graph = [gpu_context(w) for w in ws]
+    be, bg = Batch(eager), Batch(graph)
+    for rep in range(2):
+        # a loose sphere filling most of the box needs many sweeps (two or
+        # more replays of the 8-sweep group); then a tight start
+        for w, c in zip(ws + ws, eager + graph):
+            if rep == 0:
+                c.init_labels("loose", 0.45 * w.n * w.h)
+            else:
+                c.init_labels("tight", 1.0)
+        rc_e, se = be.minimize(graph=False)
+        rc_g, sg = bg.minimize(graph=True)
+        log("rep", rep, "sweeps", [s["sweeps"] for s in sg])
+        assert rc_e == rc_g == 0
+        if rep == 0:
+            assert max(s["sweeps"] for s in sg) > 8  # two replays or more
+        for ce, cg, a, b in zip(eager, graph, se, sg):
+            assert np.array_equal(ce.labels(), cg.labels())
+            assert a == b
