@@ -203,6 +203,13 @@ vesis_status vesis_forces(vesis_ctx* ctx, double* f_out);
  * ran out (positions unchanged) or the gradient is zero. */
 vesis_status vesis_atom_step(vesis_ctx* ctx, vesis_mobility* state, vesis_step_info* out);
 
+/* Labels from per-cell logits on the device (n^3 FP32, x fastest, e.g. the
+ * output of the learned warm start of vesis_nn.h): solute (-1) where the
+ * logit is positive, solvent elsewhere.  A start for
+ * vesis_minimize_interface like the loose and tight spheres of Sec.
+ * "Initial surfaces"; the relaxation from it is the paper's Step 2. */
+vesis_status vesis_init_labels_logits(vesis_ctx* ctx, const float* logits);
+
 /* Options of the full alternation (Steps 1-5 of the algorithm): max_iters
  * (k_max, 3000 in the paper), persist (consecutive iterations with a small
  * energy change needed to stop, 100), max_sweeps (colour sweeps allowed per

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "VESIS_OK", 1: "VESIS_NOT_CONVERGED", -1: "VESIS_E_ARG", -2: 
 EXPORTS = ["vesis_create", "vesis_destroy", "vesis_last_error", "vesis_set_params",
            "vesis_set_grid", "vesis_set_atoms", "vesis_set_positions", "vesis_get_positions",
            "vesis_set_bonds", "vesis_workspace_size", "vesis_set_workspace", "vesis_init_labels",
+           "vesis_init_labels_logits",
            "vesis_minimize_interface", "vesis_energy", "vesis_forces", "vesis_atom_step",
            "vesis_relax", "vesis_batch_workspace_size", "vesis_batch_tune", "vesis_minimize_batch",
            "vesis_get_labels", "vesis_get_density", "vesis_profile", "vesis_profile_read"]
@@ -107,6 +108,7 @@ def load():
     L.vesis_forces.argtypes = [P, P]
     L.vesis_atom_step.argtypes = [P, C.POINTER(Mobility), C.POINTER(StepInfo)]
     L.vesis_relax.argtypes = [P, C.POINTER(RelaxOpts), C.POINTER(Mobility), C.POINTER(RelaxReport)]
+    L.vesis_init_labels_logits.argtypes = [P, P]
     PP = C.POINTER(C.c_void_p)
     L.vesis_batch_workspace_size.argtypes = [PP, C.c_int32, C.POINTER(C.c_size_t)]
     L.vesis_batch_tune.argtypes = [PP, C.c_int32, P, C.c_size_t, C.POINTER(C.c_int32),

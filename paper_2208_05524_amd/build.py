@@ -4,7 +4,7 @@
 
 Each .hip source compiles separately (in parallel) with hipcc for gfx950 and
 the objects link into one shared library exporting the C ABI of
-include/vesis.h.
+include/vesis.h and include/vesis_nn.h.
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvesis.so")
-SOURCES = ["api.hip", "density.hip", "labels.hip", "forces.hip"]
+SOURCES = ["api.hip", "density.hip", "labels.hip", "forces.hip", "nn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

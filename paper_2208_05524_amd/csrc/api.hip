@@ -806,6 +806,25 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
     return VESIS_OK;
 }
 
+vesis_status vesis_init_labels_logits(vesis_ctx* ctx, const float* logits) {
+    if (!ctx) return VESIS_E_ARG;
+    vesis_status s = need(ctx, false);
+    if (s != VESIS_OK) return s;
+    if (!logits) return fail(ctx, VESIS_E_ARG, "logits missing");
+    s = upload_inputs(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
+    {
+        Timed t(ctx, K_INIT);
+        CK(launch_fill_u32(bits, ctx->g.nwords(), 0xffffffffu, st));
+        CK(launch_labels_from_logits(ctx->g, logits, bits, st));
+    }
+    ctx->has_labels = true;
+    ctx->forces_valid = false;
+    return VESIS_OK;
+}
+
 vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out) {
     if (!ctx) return VESIS_E_ARG;
     vesis_status s = need(ctx, true);

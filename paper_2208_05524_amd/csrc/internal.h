@@ -114,6 +114,9 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream_t st);
 hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
                              hipStream_t st);
+// In-box label bits from per-cell logits (solute where logit > 0).
+hipError_t launch_labels_from_logits(const Grid& g, const float* logits, uint32_t* bits,
+                                     hipStream_t st);
 // u64cache: 2 x ncell FP64 (LJ parts, then CFA parts; NaN = not computed).
 // gpass: pass index within the current minimisation call (sweep * p^3 + colour);
 // stamp: one int per label word, filled with a value < -p^3 before the call.

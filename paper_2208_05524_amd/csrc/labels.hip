@@ -403,6 +403,24 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     if ((t & 63) == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
 }
 
+// Labels from per-cell logits (FP32, x fastest): solute (bit 0) where the
+// logit is positive; padding bits stay solvent.
+__global__ void labels_from_logits_kernel(Grid g, const float* logits, uint32_t* bits) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    if (tid >= total) return;
+    const int w = (int)(tid % g.nwin);
+    const int64_t r = tid / g.nwin;
+    const int y = (int)(r % g.n), z = (int)(r / g.n);
+    uint32_t word = 0xffffffffu;
+    for (int b = 0; b < 32; ++b) {
+        const int x = 32 * w + b;
+        if (x >= g.n) break;
+        if (logits[(int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z)] > 0.f) word &= ~(1u << b);
+    }
+    bits[g.row(y, z) + 1 + w] = word;
+}
+
 // Zero the sweep flip counters of every molecule of a batch.
 __global__ void batch_clear_flips(const MolDesc* descs, int m, int nsweeps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -593,6 +611,14 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
 }
 
 static_assert(FWG == FLIP_WG, "flip-pass workgroup size");
+
+hipError_t launch_labels_from_logits(const Grid& g, const float* logits, uint32_t* bits,
+                                     hipStream_t st) {
+    const int64_t total = (int64_t)g.nwin * g.n * g.n;
+    hipLaunchKernelGGL(labels_from_logits_kernel, dim3(nblk(total, 256)), dim3(256), 0, st, g,
+                       logits, bits);
+    return hipGetLastError();
+}
 
 int64_t flip_slots(const Grid& g, int p) {
     const int64_t ny = (g.n + p - 1) / p;

@@ -1,0 +1,558 @@
+// The learned warm start: a 3-D U-Net on the cell grid, its layers as HIP
+// kernels for gfx950.
+//
+// Activations are BF16 in channels-last order (n, z, y, x, c), so that the
+// K dimension of a convolution (27 taps x Cin channels) is contiguous per
+// tap.  A 3x3x3 convolution with zero padding is an implicit GEMM
+//   Y[p][co] = sum_{tap, ci} X[p + off(tap)][ci] W[tap][co][ci]
+// with M = positions, N = output channels, K = 27 Cin, computed with the
+// CDNA4 BF16 matrix instruction v_mfma_f32_32x32x16_bf16 (32 x 32 x 16,
+// FP32 accumulation).  Its operand layout (checked on the device): lane i
+// holds A[i % 32][8 (i / 32) + j] and B[8 (i / 32) + j][i % 32] for
+// j = 0..7, and the 16 results D[8 (r / 4) + 4 (i / 32) + r % 4][i % 32],
+// r = 0..15.  A wavefront computes 32 positions x 32 NT output channels;
+// a workgroup of four wavefronts 128 consecutive positions.
+//
+// The data gradient is the same convolution of dY with the weights flipped
+// in space and transposed in channels; the weight gradient is a GEMM over
+// positions (M = Cout, N = Cin per tap, K = positions) split over position
+// chunks whose FP32 partial tiles are summed in a fixed order.
+#include "internal.h"
+#include "reduce.h"
+
+namespace vesis {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int CWG = 256;  // convolution workgroup: four wavefronts
+
+__device__ inline void pos_coords(int64_t p, int D, int H, int W, int& n, int& z, int& y, int& x) {
+    x = (int)(p % W);
+    int64_t r = p / W;
+    y = (int)(r % H);
+    r /= H;
+    z = (int)(r % D);
+    n = (int)(r / D);
+}
+
+// 8 consecutive BF16 values (16 bytes) as an MFMA operand.
+__device__ inline bf16x8 load8(const __bf16* p) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+}
+
+// Y = [relu](conv3x3x3(X, Wt) + bias).  X: (P, Cin), Wt: (27, Cout, Cin),
+// Y: (P, Cout); Cin % 16 == 0, Cout % (32 NT) == 0.
+template <int NT, bool RELU>
+__global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict__ X,
+                                                        const __bf16* __restrict__ Wt,
+                                                        const float* __restrict__ bias,
+                                                        __bf16* __restrict__ Y, int N, int D,
+                                                        int H, int W, int Cin, int Cout) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t P = (int64_t)N * D * H * W;
+    const int64_t p0 = (int64_t)blockIdx.x * 128 + wv * 32;
+    const int co0 = blockIdx.y * 32 * NT;
+    const int row = lane & 31, half = lane >> 5;
+    // the position whose A row this lane loads
+    const int64_t pa = p0 + row;
+    int n, z, y, x;
+    pos_coords(pa < P ? pa : 0, D, H, W, n, z, y, x);
+    const bool pa_ok = pa < P;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+    for (int tap = 0; tap < 27; ++tap) {
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int zz = z + dz, yy = y + dy, xx = x + dx;
+        const bool ok = pa_ok && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int64_t q = (((int64_t)n * D + zz) * H + yy) * W + xx;
+        const __bf16* xa = X + (ok ? q : 0) * Cin + 8 * half;
+        const __bf16* wb = Wt + ((int64_t)tap * Cout + co0 + row) * Cin + 8 * half;
+        for (int c0 = 0; c0 < Cin; c0 += 16) {
+            bf16x8 a = load8(xa + c0);
+            if (!ok) a = bf16x8{};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 b = load8(wb + (int64_t)t * 32 * Cin + c0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // D[8 (r/4) + 4 half + r%4][row]: position p0 + that, channel co0 + 32 t + row
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = co0 + 32 * t + row;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t p = p0 + 8 * (r / 4) + 4 * half + (r % 4);
+            if (p >= P) continue;
+            float v = acc[t][r] + bv;
+            if (RELU) v = v > 0.f ? v : 0.f;
+            Y[p * Cout + co] = (__bf16)v;
+        }
+    }
+}
+
+// Weight gradient partials: for one tap, a 32 x 32 (co, ci) tile and one
+// chunk of positions: part[chunk][tap][co][ci] = sum_p dY[p][co] X[p+off][ci].
+// Each of the four wavefronts takes every fourth group of 16 positions; the
+// four tiles are added in LDS in wavefront order.
+constexpr int WCHUNK = 2048;  // positions per chunk
+__global__ __launch_bounds__(CWG) void conv3_wgrad_kernel(const __bf16* __restrict__ X,
+                                                          const __bf16* __restrict__ dY,
+                                                          float* __restrict__ part, int N, int D,
+                                                          int H, int W, int Cin, int Cout) {
+    __shared__ float red[4][32 * 32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 31, half = lane >> 5;
+    const int64_t P = (int64_t)N * D * H * W;
+    const int64_t chunk = blockIdx.x;
+    const int nco = Cout / 32, nci = Cin / 32;
+    int t2 = blockIdx.y;
+    const int cit = t2 % nci;
+    t2 /= nci;
+    const int cot = t2 % nco;
+    const int tap = t2 / nco;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int co = cot * 32 + row, ci = cit * 32 + row;
+    f32x16 acc = f32x16{};
+    const int64_t pbeg = chunk * WCHUNK;
+    const int64_t pend = pbeg + WCHUNK < P ? pbeg + WCHUNK : P;
+    for (int64_t g0 = pbeg + 16 * wv; g0 < pend; g0 += 64) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t p = g0 + 8 * half + j;
+            __bf16 av = (__bf16)0.f, bv = (__bf16)0.f;
+            if (p < pend) {
+                av = dY[p * Cout + co];
+                int n, z, y, x;
+                pos_coords(p, D, H, W, n, z, y, x);
+                const int zz = z + dz, yy = y + dy, xx = x + dx;
+                if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    bv = X[((((int64_t)n * D + zz) * H + yy) * W + xx) * Cin + ci];
+            }
+            a[j] = av;
+            b[j] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wv][(8 * (r / 4) + 4 * half + (r % 4)) * 32 + row] = acc[r];
+    __syncthreads();
+    float* out = part + ((chunk * 27 + tap) * (int64_t)Cout) * Cin;
+    for (int e = threadIdx.x; e < 32 * 32; e += CWG) {
+        const float v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+        const int r_ = e / 32, c_ = e % 32;
+        out[(int64_t)(cot * 32 + r_) * Cin + cit * 32 + c_] = v;
+    }
+}
+
+// dW[i] = sum over chunks, in order, of part[chunk][i].
+__global__ void wgrad_reduce_kernel(const float* part, int64_t nchunks, int64_t nw, float* dW) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    float s = 0.f;
+    for (int64_t c = 0; c < nchunks; ++c) s += part[c * nw + i];
+    dW[i] = s;
+}
+
+// db[co] = sum_p dY[p][co]: one workgroup per channel, fixed-order tree.
+__global__ __launch_bounds__(256) void bias_grad_kernel(const __bf16* dY, int64_t P, int Cout,
+                                                        float* db) {
+    __shared__ double sh[256];
+    const int co = blockIdx.x;
+    double s = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += 256) s += (double)(float)dY[p * Cout + co];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) db[co] = (float)s;
+}
+
+// BF16 forward weights and the spatially flipped, channel-transposed
+// weights of the data gradient, from the FP32 master copy (27, Cout, Cin).
+__global__ void prep_weights_kernel(const float* W32, int Cout, int Cin, __bf16* Wf, __bf16* Wb) {
+    const int64_t n = 27LL * Cout * Cin;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = (int)(i % Cin);
+    const int64_t r = i / Cin;
+    const int co = (int)(r % Cout);
+    const int tap = (int)(r / Cout);
+    const __bf16 v = (__bf16)W32[i];
+    Wf[i] = v;
+    Wb[((int64_t)(26 - tap) * Cin + ci) * Cout + co] = v;
+}
+
+// dPre = dY where Y > 0 (the ReLU was applied to the pre-activation).
+__global__ void relu_bwd_kernel(const __bf16* Y, const __bf16* dY, __bf16* dPre, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dPre[i] = (float)Y[i] > 0.f ? dY[i] : (__bf16)0.f;
+}
+
+// 2x2x2 average pooling and its adjoint (even sizes).
+__global__ void pool2_fwd_kernel(const __bf16* X, __bf16* Y, int N, int D, int H, int W, int C) {
+    const int d = D / 2, h = H / 2, w = W / 2;
+    const int64_t n_out = (int64_t)N * d * h * w * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    const int c = (int)(i % C);
+    int n, z, y, x;
+    pos_coords(i / C, d, h, w, n, z, y, x);
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
+        s += (float)X[((((int64_t)n * D + zz) * H + yy) * W + xx) * C + c];
+    }
+    Y[i] = (__bf16)(0.125f * s);
+}
+__global__ void pool2_bwd_kernel(const __bf16* dY, __bf16* dX, int N, int D, int H, int W, int C) {
+    const int64_t n_in = (int64_t)N * D * H * W * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
+    const int c = (int)(i % C);
+    int n, z, y, x;
+    pos_coords(i / C, D, H, W, n, z, y, x);
+    const int d = D / 2, h = H / 2, w = W / 2;
+    dX[i] = (__bf16)(0.125f * (float)dY[((((int64_t)n * d + z / 2) * h + y / 2) * w + x / 2) * C + c]);
+}
+
+// Nearest 2x upsampling (X: half size) and its adjoint.
+__global__ void up2_fwd_kernel(const __bf16* X, __bf16* Y, int N, int D, int H, int W, int C) {
+    const int64_t n_out = (int64_t)N * D * H * W * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    const int c = (int)(i % C);
+    int n, z, y, x;
+    pos_coords(i / C, D, H, W, n, z, y, x);
+    const int d = D / 2, h = H / 2, w = W / 2;
+    Y[i] = X[((((int64_t)n * d + z / 2) * h + y / 2) * w + x / 2) * C + c];
+}
+__global__ void up2_bwd_kernel(const __bf16* dY, __bf16* dX, int N, int D, int H, int W, int C) {
+    const int d = D / 2, h = H / 2, w = W / 2;
+    const int64_t n_small = (int64_t)N * d * h * w * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_small) return;
+    const int c = (int)(i % C);
+    int n, z, y, x;
+    pos_coords(i / C, d, h, w, n, z, y, x);
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
+        s += (float)dY[((((int64_t)n * D + zz) * H + yy) * W + xx) * C + c];
+    }
+    dX[i] = (__bf16)s;
+}
+
+// Channel concatenation Y = [A | B] and its adjoint (dA = dY[:, :Ca],
+// dB (+)= dY[:, Ca:]).
+__global__ void concat_kernel(const __bf16* A, int Ca, const __bf16* B, int Cb, __bf16* Y,
+                              int64_t P) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    const int64_t p = i / C;
+    const int c = (int)(i % C);
+    Y[i] = c < Ca ? A[p * Ca + c] : B[p * Cb + (c - Ca)];
+}
+__global__ void split_kernel(const __bf16* dY, int Ca, int Cb, __bf16* dA, __bf16* dB,
+                             int accumulate_b, int64_t P) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    const int64_t p = i / C;
+    const int c = (int)(i % C);
+    if (c < Ca) {
+        dA[p * Ca + c] = dY[i];
+    } else {
+        const int64_t j = p * Cb + (c - Ca);
+        dB[j] = accumulate_b ? (__bf16)((float)dB[j] + (float)dY[i]) : dY[i];
+    }
+}
+
+// Y = A + B (BF16, added in FP32).
+__global__ void add_kernel(const __bf16* A, const __bf16* B, __bf16* Y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Y[i] = (__bf16)((float)A[i] + (float)B[i]);
+}
+
+// 1x1x1 head: logits[p] = w . X[p] + b (FP32), and its adjoint.
+__global__ void head_fwd_kernel(const __bf16* X, const float* w, const float* b, float* logits,
+                                int64_t P, int C) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = b[0];
+    for (int c = 0; c < C; ++c) s += w[c] * (float)X[p * C + c];
+    logits[p] = s;
+}
+__global__ void head_bwd_x_kernel(const float* dlogit, const float* w, __bf16* dX, int64_t P,
+                                  int C) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    dX[i] = (__bf16)(dlogit[i / C] * w[i % C]);
+}
+// dw[c] = sum_p dlogit[p] X[p][c] (c < C), db = sum_p dlogit[p] (c == C).
+__global__ __launch_bounds__(256) void head_bwd_w_kernel(const float* dlogit, const __bf16* X,
+                                                         int64_t P, int C, float* dw, float* db) {
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += 256)
+        s += (double)dlogit[p] * (c < C ? (double)(float)X[p * C + c] : 1.0);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        if (c < C)
+            dw[c] = (float)s;
+        else
+            db[0] = (float)s;
+    }
+}
+
+// Weighted binary cross-entropy with logits against labels (target 1 for
+// solute, phi = -1), mean over cells: per-block FP64 partial losses and the
+// gradient dlogit = w (sigmoid(l) - t) / P.
+__global__ __launch_bounds__(256) void bce_kernel(const float* logits, const int8_t* labels,
+                                                  int64_t P, float pos_weight, float* dlogit,
+                                                  double* partial) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += stride) {
+        const float l = logits[p];
+        const float t = labels[p] < 0 ? 1.f : 0.f;
+        const float wt = t > 0.f ? pos_weight : 1.f;
+        // log(1 + exp(-|l|)) + max(l, 0) - l t
+        const float sp = log1pf(expf(-fabsf(l))) + fmaxf(l, 0.f) - l * t;
+        s += (double)(wt * sp);
+        const float sg = 1.f / (1.f + expf(-l));
+        dlogit[p] = wt * (sg - t) / (float)P;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s / (double)P;
+}
+
+// Adam on FP32 master parameters.
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Input features on the cell grid (n^3 cells of edge h, first centre x0):
+// channel 0 = sum_i exp(-|x - r_i|^2 / (2 s_i^2)), channel 1 = the same
+// weighted by q_i, with s_i = sigma_i / 2, cut at 4 s_i; channels 2..C-1 = 0.
+__global__ __launch_bounds__(256) void featurize_kernel(const double4* pos, const double* sigma,
+                                                        const double* q, int64_t na, int n,
+                                                        double h, double x0, double y0, double z0,
+                                                        int C, __bf16* X) {
+    __shared__ float4 sa[256];
+    __shared__ float2 sp[256];
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t ncell = (int64_t)n * n * n;
+    const int x = (int)(cell % n), y = (int)((cell / n) % n), z = (int)(cell / ((int64_t)n * n));
+    const float cx = (float)(x0 + x * h), cy = (float)(y0 + y * h), cz = (float)(z0 + z * h);
+    float d0 = 0.f, d1 = 0.f;
+    for (int64_t base = 0; base < na; base += 256) {
+        __syncthreads();
+        const int64_t a = base + threadIdx.x;
+        if (a < na) {
+            const double4 p = pos[a];
+            const float s = (float)(0.5 * sigma[a]);
+            sa[threadIdx.x] = make_float4((float)p.x, (float)p.y, (float)p.z, 1.f / (2.f * s * s));
+            sp[threadIdx.x] = make_float2((float)q[a], 16.f * s * s);
+        }
+        __syncthreads();
+        const int cnt = (int)(na - base < 256 ? na - base : 256);
+        for (int k = 0; k < cnt; ++k) {
+            const float4 p = sa[k];
+            const float dx = cx - p.x, dy = cy - p.y, dz = cz - p.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < sp[k].y) {
+                const float e = __expf(-r2 * p.w);
+                d0 += e;
+                d1 += sp[k].x * e;
+            }
+        }
+    }
+    if (cell >= ncell) return;
+    for (int c = 0; c < C; ++c) X[cell * C + c] = (__bf16)(c == 0 ? d0 : (c == 1 ? d1 : 0.f));
+}
+
+inline unsigned nblk(int64_t n, int wg) { return (unsigned)((n + wg - 1) / wg); }
+
+}  // namespace
+}  // namespace nn
+}  // namespace vesis
+
+// ------------------------------------------------------------------ C ABI
+
+#include "vesis_nn.h"
+
+using namespace vesis::nn;
+
+namespace {
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline int status(hipError_t e) { return e == hipSuccess ? 0 : VESIS_NN_E_DEVICE; }
+inline const __bf16* B(const void* p) { return static_cast<const __bf16*>(p); }
+inline __bf16* Bm(void* p) { return static_cast<__bf16*>(p); }
+bool dims_ok(int N, int D, int H, int W) { return N > 0 && D > 0 && H > 0 && W > 0; }
+}  // namespace
+
+extern "C" {
+
+int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* bias, void* y,
+                       int n, int d, int h, int wd, int cin, int cout, int relu) {
+    if (!x || !w || !y || !dims_ok(n, d, h, wd) || cin <= 0 || cin % 16 || cout <= 0 || cout % 32)
+        return VESIS_NN_E_ARG;
+    const int64_t P = (int64_t)n * d * h * wd;
+    const bool two = cout % 64 == 0;
+    const dim3 grid(nblk(P, 128), (unsigned)(cout / (two ? 64 : 32)));
+    if (two && relu)
+        hipLaunchKernelGGL((conv3_fwd_kernel<2, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    else if (two)
+        hipLaunchKernelGGL((conv3_fwd_kernel<2, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    else if (relu)
+        hipLaunchKernelGGL((conv3_fwd_kernel<1, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    else
+        hipLaunchKernelGGL((conv3_fwd_kernel<1, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_wgrad_workspace(int n, int d, int h, int wd, int cin, int cout, size_t* bytes) {
+    if (!bytes || !dims_ok(n, d, h, wd) || cin % 32 || cout % 32) return VESIS_NN_E_ARG;
+    const int64_t P = (int64_t)n * d * h * wd;
+    *bytes = sizeof(float) * (size_t)((P + WCHUNK - 1) / WCHUNK) * 27 * cout * cin;
+    return 0;
+}
+
+int vesis_nn_conv3_wgrad(void* stream, const void* x, const void* dy, float* dw, float* db,
+                         float* ws, size_t ws_bytes, int n, int d, int h, int wd, int cin,
+                         int cout) {
+    size_t need = 0;
+    if (!x || !dy || !dw || !ws || vesis_nn_wgrad_workspace(n, d, h, wd, cin, cout, &need) != 0)
+        return VESIS_NN_E_ARG;
+    if (ws_bytes < need) return VESIS_NN_E_ARG;
+    const int64_t P = (int64_t)n * d * h * wd;
+    const int64_t nch = (P + WCHUNK - 1) / WCHUNK;
+    hipLaunchKernelGGL(conv3_wgrad_kernel, dim3((unsigned)nch, (unsigned)(27 * (cout / 32) * (cin / 32))),
+                       dim3(CWG), 0, S(stream), B(x), B(dy), ws, n, d, h, wd, cin, cout);
+    const int64_t nw = 27LL * cout * cin;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nblk(nw, 256)), dim3(256), 0, S(stream), ws, nch, nw, dw);
+    if (db) hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)cout), dim3(256), 0, S(stream), B(dy), P, cout, db);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_prep_weights(void* stream, const float* w32, int cout, int cin, void* wf, void* wb) {
+    if (!w32 || !wf || !wb || cout <= 0 || cin <= 0) return VESIS_NN_E_ARG;
+    const int64_t n = 27LL * cout * cin;
+    hipLaunchKernelGGL(prep_weights_kernel, dim3(nblk(n, 256)), dim3(256), 0, S(stream), w32, cout, cin, Bm(wf), Bm(wb));
+    return status(hipGetLastError());
+}
+
+int vesis_nn_relu_bwd(void* stream, const void* y, const void* dy, void* dpre, int64_t count) {
+    if (!y || !dy || !dpre || count < 0) return VESIS_NN_E_ARG;
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(nblk(count, 256)), dim3(256), 0, S(stream), B(y), B(dy), Bm(dpre), count);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_pool2(void* stream, const void* x, void* y, int n, int d, int h, int wd, int c, int backward) {
+    if (!x || !y || !dims_ok(n, d, h, wd) || c <= 0 || d % 2 || h % 2 || wd % 2) return VESIS_NN_E_ARG;
+    if (backward) {
+        const int64_t cnt = (int64_t)n * d * h * wd * c;
+        hipLaunchKernelGGL(pool2_bwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+    } else {
+        const int64_t cnt = (int64_t)n * (d / 2) * (h / 2) * (wd / 2) * c;
+        hipLaunchKernelGGL(pool2_fwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+    }
+    return status(hipGetLastError());
+}
+
+int vesis_nn_up2(void* stream, const void* x, void* y, int n, int d, int h, int wd, int c, int backward) {
+    if (!x || !y || !dims_ok(n, d, h, wd) || c <= 0 || d % 2 || h % 2 || wd % 2) return VESIS_NN_E_ARG;
+    if (backward) {
+        const int64_t cnt = (int64_t)n * (d / 2) * (h / 2) * (wd / 2) * c;
+        hipLaunchKernelGGL(up2_bwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+    } else {
+        const int64_t cnt = (int64_t)n * d * h * wd * c;
+        hipLaunchKernelGGL(up2_fwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+    }
+    return status(hipGetLastError());
+}
+
+int vesis_nn_concat(void* stream, const void* a, int ca, const void* b, int cb, void* y, int64_t p) {
+    if (!a || !b || !y || ca <= 0 || cb <= 0 || p <= 0) return VESIS_NN_E_ARG;
+    hipLaunchKernelGGL(concat_kernel, dim3(nblk(p * (ca + cb), 256)), dim3(256), 0, S(stream), B(a), ca, B(b), cb, Bm(y), p);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_split(void* stream, const void* dy, int ca, int cb, void* da, void* db,
+                   int accumulate_b, int64_t p) {
+    if (!dy || !da || !db || ca <= 0 || cb <= 0 || p <= 0) return VESIS_NN_E_ARG;
+    hipLaunchKernelGGL(split_kernel, dim3(nblk(p * (ca + cb), 256)), dim3(256), 0, S(stream), B(dy), ca, cb, Bm(da), Bm(db), accumulate_b, p);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_add(void* stream, const void* a, const void* b, void* y, int64_t count) {
+    if (!a || !b || !y || count < 0) return VESIS_NN_E_ARG;
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(count, 256)), dim3(256), 0, S(stream), B(a), B(b), Bm(y), count);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_head_fwd(void* stream, const void* x, const float* w, const float* b, float* logits,
+                      int64_t p, int c) {
+    if (!x || !w || !b || !logits || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
+    hipLaunchKernelGGL(head_fwd_kernel, dim3(nblk(p, 256)), dim3(256), 0, S(stream), B(x), w, b, logits, p, c);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const float* w, void* dx,
+                      float* dw, float* db, int64_t p, int c) {
+    if (!dlogit || !x || !w || !dx || !dw || !db || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
+    hipLaunchKernelGGL(head_bwd_x_kernel, dim3(nblk(p * c, 256)), dim3(256), 0, S(stream), dlogit, w, Bm(dx), p, c);
+    hipLaunchKernelGGL(head_bwd_w_kernel, dim3((unsigned)(c + 1)), dim3(256), 0, S(stream), dlogit, B(x), p, c, dw, db);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_bce(void* stream, const float* logits, const int8_t* labels, int64_t p,
+                 float pos_weight, float* dlogit, double* partial, int nblocks, double* loss) {
+    if (!logits || !labels || !dlogit || !partial || !loss || p <= 0 || nblocks < 1 || nblocks > 4096)
+        return VESIS_NN_E_ARG;
+    hipLaunchKernelGGL(bce_kernel, dim3((unsigned)nblocks), dim3(256), 0, S(stream), logits, labels, p, pos_weight, dlogit, partial);
+    hipLaunchKernelGGL((vesis::reduce_partials<double, 1>), dim3(1), dim3(vesis::RED_WG), 0, S(stream), partial, nblocks, loss);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_adam(void* stream, float* w, const float* g, float* m, float* v, int64_t count,
+                  float lr, float b1, float b2, float eps, int step) {
+    if (!w || !g || !m || !v || count <= 0 || step < 1) return VESIS_NN_E_ARG;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(nblk(count, 256)), dim3(256), 0, S(stream), w, g, m, v, count, lr, b1, b2, eps, c1, c2);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_featurize(void* stream, const double* pos4, const double* sigma, const double* q,
+                       int64_t na, int n, double h, const double* center, int c, void* x) {
+    if (!pos4 || !sigma || !q || !center || !x || na < 0 || n <= 0 || c < 2) return VESIS_NN_E_ARG;
+    const double L = 0.5 * n * h;
+    const int64_t ncell = (int64_t)n * n * n;
+    hipLaunchKernelGGL(featurize_kernel, dim3(nblk(ncell, 256)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const double4*>(pos4), sigma, q, na, n, h,
+                       center[0] - L + 0.5 * h, center[1] - L + 0.5 * h, center[2] - L + 0.5 * h, c, Bm(x));
+    return status(hipGetLastError());
+}
+
+}  // extern "C"

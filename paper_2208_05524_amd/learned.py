@@ -1,0 +1,371 @@
+"""The learned warm start: a 3-D U-Net that predicts the equilibrium labels
+of the binary level-set relaxation from the atoms, trained on labels the
+relaxation itself produced.  Not part of the paper (which starts from a
+loose or tight sphere); the relaxation always finishes from the predicted
+labels, so a poor prediction costs sweeps, never correctness of the
+relaxation.
+
+Architecture: 4 levels with 32, 64, 128, 256 channels, two 3x3x3
+convolutions + ReLU per level, 2x2x2 average pooling down, nearest 2x
+upsampling + channel concatenation with the skip up, a 1x1x1 head to one
+logit per cell (solute where positive).  Input: 32 channels on the cell
+grid, of which channel 0 is the Gaussian-smeared atom density and channel 1
+the smeared charge (vesis_nn_featurize), the rest zero.
+
+Every layer runs in the library's HIP kernels (include/vesis_nn.h); torch
+tensors serve only as device memory.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import nn as N
+
+IN_C = 32
+LEVELS = (32, 64, 128, 256)
+
+
+def layer_specs():
+    """(name, cin, cout) of every 3x3x3 convolution, in forward order."""
+    c1, c2, c3, c4 = LEVELS
+    return [("e1a", IN_C, c1), ("e1b", c1, c1), ("e2a", c1, c2), ("e2b", c2, c2),
+            ("e3a", c2, c3), ("e3b", c3, c3), ("e4a", c3, c4), ("e4b", c4, c4),
+            ("d3a", c4 + c3, c3), ("d3b", c3, c3), ("d2a", c3 + c2, c2), ("d2b", c2, c2),
+            ("d1a", c2 + c1, c1), ("d1b", c1, c1)]
+
+
+def init_weights(seed: int = 0):
+    """He-uniform weights from the seeded input generators, zero biases:
+    {name: (w (27, cout, cin) float32, b (cout,) float32)}, head included."""
+    import synth
+    return synth.conv_weights(layer_specs(), LEVELS[0], seed)
+
+
+class UNet:
+    """Parameters, activations and gradients on one device; forward,
+    backward and Adam through the library's kernels."""
+
+    def __init__(self, size: int, batch: int = 1, device: int = 0, seed: int = 0,
+                 weights=None):
+        import torch
+        if size % 8:
+            raise ValueError("grid size must be a multiple of 8 (three poolings)")
+        self.t = torch
+        self.dev = torch.device("cuda", device)
+        self.L = N.lib()
+        self.n, self.b = size, batch
+        w0 = weights if weights is not None else init_weights(seed)
+        self.specs = layer_specs()
+        self.p = {}
+        f32 = dict(dtype=torch.float32, device=self.dev)
+        for name, cin, cout in self.specs:
+            w, bias = w0[name]
+            self.p[name] = dict(
+                cin=cin, cout=cout,
+                w=torch.tensor(np.asarray(w, np.float32).reshape(27, cout, cin), **f32),
+                bias=torch.tensor(np.asarray(bias, np.float32), **f32),
+                wf=torch.empty(27 * cout * cin, dtype=torch.bfloat16, device=self.dev),
+                wb=torch.empty(27 * cout * cin, dtype=torch.bfloat16, device=self.dev),
+                gw=torch.zeros(27 * cout * cin, **f32), gb=torch.zeros(cout, **f32))
+        hw, hb = w0["head"]
+        self.p["head"] = dict(w=torch.tensor(np.asarray(hw, np.float32), **f32),
+                              bias=torch.tensor(np.asarray(hb, np.float32), **f32),
+                              gw=torch.zeros(LEVELS[0], **f32), gb=torch.zeros(1, **f32))
+        self.adam = {k: (torch.zeros_like(v["w"]), torch.zeros_like(v["w"]),
+                         torch.zeros_like(v["bias"]), torch.zeros_like(v["bias"]))
+                     for k, v in self.p.items()}
+        self.step_count = 0
+        # weight-gradient scratch: the largest layer at its resolution
+        need = 0
+        for name, cin, cout in self.specs:
+            s = self._size_of(name)
+            nb = C.c_size_t()
+            N.check(self.L.vesis_nn_wgrad_workspace(batch, s, s, s, cin, cout, C.byref(nb)),
+                    "wgrad workspace")
+            need = max(need, nb.value)
+        self.ws = torch.empty(need // 4 + 1, **f32)
+        self.ws_bytes = need
+        self.partial = torch.zeros(1024, dtype=torch.float64, device=self.dev)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.prep()
+
+    # ------------------------------------------------------------ helpers
+    def _size_of(self, name):
+        lvl = int(name[1])
+        return self.n >> (lvl - 1)
+
+    def _s(self):
+        return C.c_void_p(self.t.cuda.current_stream(self.dev).cuda_stream)
+
+    def _act(self, size, c):
+        return self.t.empty((self.b, size, size, size, c), dtype=self.t.bfloat16,
+                            device=self.dev)
+
+    def prep(self):
+        """BF16 forward and data-gradient weights from the FP32 masters."""
+        for name, cin, cout in self.specs:
+            q = self.p[name]
+            N.check(self.L.vesis_nn_prep_weights(self._s(), N.ptr(q["w"]), cout, cin,
+                                                 N.ptr(q["wf"]), N.ptr(q["wb"])), "prep")
+
+    def conv(self, name, x, relu=True):
+        q = self.p[name]
+        s = x.shape[1]
+        y = self._act(s, q["cout"])
+        N.check(self.L.vesis_nn_conv3_fwd(self._s(), N.ptr(x), N.ptr(q["wf"]), N.ptr(q["bias"]),
+                                          N.ptr(y), self.b, s, s, s, q["cin"], q["cout"],
+                                          1 if relu else 0), "conv " + name)
+        return y
+
+    def pool(self, x):
+        s, c = x.shape[1], x.shape[4]
+        y = self._act(s // 2, c)
+        N.check(self.L.vesis_nn_pool2(self._s(), N.ptr(x), N.ptr(y), self.b, s, s, s, c, 0),
+                "pool")
+        return y
+
+    def up(self, x):
+        s, c = 2 * x.shape[1], x.shape[4]
+        y = self._act(s, c)
+        N.check(self.L.vesis_nn_up2(self._s(), N.ptr(x), N.ptr(y), self.b, s, s, s, c, 0), "up")
+        return y
+
+    def cat(self, a, b):
+        s = a.shape[1]
+        y = self._act(s, a.shape[4] + b.shape[4])
+        P = self.b * s ** 3
+        N.check(self.L.vesis_nn_concat(self._s(), N.ptr(a), a.shape[4], N.ptr(b), b.shape[4],
+                                       N.ptr(y), P), "concat")
+        return y
+
+    # ------------------------------------------------------------ forward
+    def featurize(self, pos4, sigma, q, h, center, out=None):
+        """Input channels for one molecule (device FP64 arrays) on this grid."""
+        x = out if out is not None else self._act(self.n, IN_C)
+        cen = (C.c_double * 3)(*[float(v) for v in center])
+        N.check(self.L.vesis_nn_featurize(self._s(), N.ptr(pos4), N.ptr(sigma), N.ptr(q),
+                                          int(sigma.numel()), self.n, float(h),
+                                          C.cast(cen, C.c_void_p), IN_C, N.ptr(x)), "featurize")
+        return x
+
+    def forward(self, x):
+        """x: (b, n, n, n, 32) BF16.  Returns logits (b n^3 FP32); keeps the
+        activations for backward."""
+        a = {"x": x}
+        a["a1"] = self.conv("e1a", x)
+        a["s1"] = self.conv("e1b", a["a1"])
+        a["p1"] = self.pool(a["s1"])
+        a["a2"] = self.conv("e2a", a["p1"])
+        a["s2"] = self.conv("e2b", a["a2"])
+        a["p2"] = self.pool(a["s2"])
+        a["a3"] = self.conv("e3a", a["p2"])
+        a["s3"] = self.conv("e3b", a["a3"])
+        a["p3"] = self.pool(a["s3"])
+        a["a4"] = self.conv("e4a", a["p3"])
+        a["b4"] = self.conv("e4b", a["a4"])
+        a["c3"] = self.cat(self.up(a["b4"]), a["s3"])
+        a["a5"] = self.conv("d3a", a["c3"])
+        a["b5"] = self.conv("d3b", a["a5"])
+        a["c2"] = self.cat(self.up(a["b5"]), a["s2"])
+        a["a6"] = self.conv("d2a", a["c2"])
+        a["b6"] = self.conv("d2b", a["a6"])
+        a["c1"] = self.cat(self.up(a["b6"]), a["s1"])
+        a["a7"] = self.conv("d1a", a["c1"])
+        a["b7"] = self.conv("d1b", a["a7"])
+        P = self.b * self.n ** 3
+        logits = self.t.empty(P, dtype=self.t.float32, device=self.dev)
+        h = self.p["head"]
+        N.check(self.L.vesis_nn_head_fwd(self._s(), N.ptr(a["b7"]), N.ptr(h["w"]), N.ptr(h["bias"]),
+                                         N.ptr(logits), P, LEVELS[0]), "head")
+        self.acts = a
+        return logits
+
+    # ------------------------------------------------------------ backward
+    def _relu_bwd(self, y, dy):
+        g = self.t.empty_like(y)
+        N.check(self.L.vesis_nn_relu_bwd(self._s(), N.ptr(y), N.ptr(dy), N.ptr(g), y.numel()),
+                "relu_bwd")
+        return g
+
+    def _conv_bwd(self, name, x, y, dy, need_dx=True):
+        """Gradient through y = relu(conv(x)): weight and bias gradients, and
+        the gradient at x (unless need_dx is False)."""
+        q = self.p[name]
+        s = x.shape[1]
+        g = self._relu_bwd(y, dy)
+        N.check(self.L.vesis_nn_conv3_wgrad(self._s(), N.ptr(x), N.ptr(g), N.ptr(q["gw"]),
+                                            N.ptr(q["gb"]), N.ptr(self.ws), self.ws_bytes, self.b,
+                                            s, s, s, q["cin"], q["cout"]), "wgrad " + name)
+        if not need_dx:
+            return None
+        dx = self._act(s, q["cin"])
+        N.check(self.L.vesis_nn_conv3_fwd(self._s(), N.ptr(g), N.ptr(q["wb"]), None, N.ptr(dx),
+                                          self.b, s, s, s, q["cout"], q["cin"], 0),
+                "dgrad " + name)
+        return dx
+
+    def _split(self, dcat, ca):
+        s = dcat.shape[1]
+        cb = dcat.shape[4] - ca
+        da, db = self._act(s, ca), self._act(s, cb)
+        N.check(self.L.vesis_nn_split(self._s(), N.ptr(dcat), ca, cb, N.ptr(da), N.ptr(db), 0,
+                                      self.b * s ** 3), "split")
+        return da, db
+
+    def _up_bwd(self, dy):
+        s, c = dy.shape[1], dy.shape[4]
+        dx = self._act(s // 2, c)
+        N.check(self.L.vesis_nn_up2(self._s(), N.ptr(dy), N.ptr(dx), self.b, s, s, s, c, 1),
+                "up_bwd")
+        return dx
+
+    def _pool_bwd_add(self, dp, dskip):
+        """dskip + the adjoint of pooling applied to dp (in place on dskip)."""
+        s, c = dskip.shape[1], dskip.shape[4]
+        t = self._act(s, c)
+        N.check(self.L.vesis_nn_pool2(self._s(), N.ptr(dp), N.ptr(t), self.b, s, s, s, c, 1),
+                "pool_bwd")
+        N.check(self.L.vesis_nn_add(self._s(), N.ptr(dskip), N.ptr(t), N.ptr(dskip),
+                                    dskip.numel()), "add")
+        return dskip
+
+    def backward(self, dlogit):
+        """Gradients of every parameter from dlogit (b n^3 FP32)."""
+        a = self.acts
+        h = self.p["head"]
+        P = self.b * self.n ** 3
+        db7 = self.t.empty_like(a["b7"])
+        N.check(self.L.vesis_nn_head_bwd(self._s(), N.ptr(dlogit), N.ptr(a["b7"]), N.ptr(h["w"]),
+                                         N.ptr(db7), N.ptr(h["gw"]), N.ptr(h["gb"]), P, LEVELS[0]),
+                "head_bwd")
+        c1, c2, c3, _ = LEVELS
+        da7 = self._conv_bwd("d1b", a["a7"], a["b7"], db7)
+        dc1 = self._conv_bwd("d1a", a["c1"], a["a7"], da7)
+        du1, ds1 = self._split(dc1, c2)
+        db6 = self._up_bwd(du1)
+        da6 = self._conv_bwd("d2b", a["a6"], a["b6"], db6)
+        dc2 = self._conv_bwd("d2a", a["c2"], a["a6"], da6)
+        du2, ds2 = self._split(dc2, c3)
+        db5 = self._up_bwd(du2)
+        da5 = self._conv_bwd("d3b", a["a5"], a["b5"], db5)
+        dc3 = self._conv_bwd("d3a", a["c3"], a["a5"], da5)
+        du3, ds3 = self._split(dc3, LEVELS[3])
+        db4 = self._up_bwd(du3)
+        da4 = self._conv_bwd("e4b", a["a4"], a["b4"], db4)
+        dp3 = self._conv_bwd("e4a", a["p3"], a["a4"], da4)
+        ds3 = self._pool_bwd_add(dp3, ds3)
+        da3 = self._conv_bwd("e3b", a["a3"], a["s3"], ds3)
+        dp2 = self._conv_bwd("e3a", a["p2"], a["a3"], da3)
+        ds2 = self._pool_bwd_add(dp2, ds2)
+        da2 = self._conv_bwd("e2b", a["a2"], a["s2"], ds2)
+        dp1 = self._conv_bwd("e2a", a["p1"], a["a2"], da2)
+        ds1 = self._pool_bwd_add(dp1, ds1)
+        da1 = self._conv_bwd("e1b", a["a1"], a["s1"], ds1)
+        self._conv_bwd("e1a", a["x"], a["a1"], da1, need_dx=False)
+
+    def loss(self, logits, labels, pos_weight: float = 1.0):
+        """Mean BCE against labels (device int8, -1 solute): (device loss, dlogit)."""
+        P = logits.numel()
+        dlogit = self.t.empty_like(logits)
+        N.check(self.L.vesis_nn_bce(self._s(), N.ptr(logits), N.ptr(labels), P, float(pos_weight),
+                                    N.ptr(dlogit), N.ptr(self.partial), 1024,
+                                    N.ptr(self.loss_dev)), "bce")
+        return self.loss_dev, dlogit
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        for k, q in self.p.items():
+            m_w, v_w, m_b, v_b = self.adam[k]
+            N.check(self.L.vesis_nn_adam(self._s(), N.ptr(q["w"]), N.ptr(q["gw"]), N.ptr(m_w),
+                                         N.ptr(v_w), q["w"].numel(), lr, b1, b2, eps,
+                                         self.step_count), "adam")
+            N.check(self.L.vesis_nn_adam(self._s(), N.ptr(q["bias"]), N.ptr(q["gb"]), N.ptr(m_b),
+                                         N.ptr(v_b), q["bias"].numel(), lr, b1, b2, eps,
+                                         self.step_count), "adam")
+        self.prep()
+
+    def weights(self):
+        """FP32 master weights as numpy, in init_weights' format."""
+        out = {}
+        for name, cin, cout in self.specs:
+            q = self.p[name]
+            out[name] = (q["w"].cpu().numpy().reshape(27, cout, cin), q["bias"].cpu().numpy())
+        out["head"] = (self.p["head"]["w"].cpu().numpy(), self.p["head"]["bias"].cpu().numpy())
+        return out
+
+    def grads(self):
+        out = {}
+        for name, cin, cout in self.specs:
+            q = self.p[name]
+            out[name] = (q["gw"].cpu().numpy().reshape(27, cout, cin), q["gb"].cpu().numpy())
+        out["head"] = (self.p["head"]["gw"].cpu().numpy(), self.p["head"]["gb"].cpu().numpy())
+        return out
+
+
+def molecule_arrays(w, device):
+    """Device FP64 arrays (pos4, sigma, q) of a synth.Workload."""
+    import torch
+    pos4 = np.zeros((w.natoms, 4))
+    pos4[:, :3] = w.xyz
+    dd = dict(dtype=torch.float64, device=device)
+    return (torch.tensor(pos4, **dd), torch.tensor(np.asarray(w.sigma, np.float64), **dd),
+            torch.tensor(np.asarray(w.q, np.float64), **dd))
+
+
+class Sample:
+    """One training molecule on the device: its atoms and the labels the
+    relaxation reached from the tight start."""
+
+    def __init__(self, w, labels_host, device):
+        import torch
+        self.w = w
+        self.pos4, self.sigma, self.q = molecule_arrays(w, device)
+        self.labels = torch.tensor(np.asarray(labels_host, np.int8), device=device)
+
+
+def relaxed_labels(workloads, batch: int = 64):
+    """Equilibrium labels of each workload from the tight start (the
+    relaxation of Step 2, batched), as host int8 arrays, with the sweeps."""
+    from .vesis import Batch, Context
+    out, sweeps = [], []
+    for k in range(0, len(workloads), batch):
+        ctxs = []
+        for w in workloads[k:k + batch]:
+            c = Context(0)
+            c.setup(w, precision=32)
+            c.init_labels("tight", 1.0)
+            ctxs.append(c)
+        rc, st = Batch(ctxs).minimize()
+        for c, s in zip(ctxs, st):
+            out.append(c.labels())
+            sweeps.append(s["sweeps"])
+            c.close()
+    return out, sweeps
+
+
+def train(model: UNet, samples, steps: int, lr: float = 1e-3, pos_weight: float = 1.0,
+          log_every: int = 0, log=print):
+    """Adam on the mean BCE, one sample per step, cycling through samples.
+    Returns the loss of every step."""
+    import torch
+    x = model._act(model.n, IN_C)
+    losses = []
+    for s in range(steps):
+        smp = samples[s % len(samples)]
+        model.featurize(smp.pos4, smp.sigma, smp.q, smp.w.h, smp.w.center, out=x)
+        logits = model.forward(x)
+        loss, dlogit = model.loss(logits, smp.labels, pos_weight)
+        losses.append(loss.clone())
+        model.backward(dlogit)
+        model.adam_step(lr)
+        if log_every and (s + 1) % log_every == 0:
+            log(f"step {s + 1}: loss {float(torch.stack(losses[-log_every:]).mean()):.4f}")
+    return [float(v) for v in torch.stack(losses).cpu().numpy().ravel()]
+
+
+def predict_logits(model: UNet, pos4, sigma, q, h, center):
+    x = model.featurize(pos4, sigma, q, h, center)
+    return model.forward(x)

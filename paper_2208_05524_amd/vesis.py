@@ -143,6 +143,12 @@ class Context:
         u = None if user is None else np.ascontiguousarray(user, dtype=np.int8)
         self._check(self.lib.vesis_init_labels(self.h, m, float(param), _ptr(u)))
 
+    def init_labels_logits(self, logits):
+        """Labels from a CUDA float32 tensor of n^3 logits (solute where > 0)."""
+        t = self._torch
+        assert logits.is_cuda and logits.dtype == t.float32 and logits.numel() == self.n ** 3
+        self._check(self.lib.vesis_init_labels_logits(self.h, C.c_void_p(logits.data_ptr())))
+
     def minimize(self, max_sweeps: int = 20000):
         st = MinStats()
         rc = self._check(self.lib.vesis_minimize_interface(self.h, int(max_sweeps), C.byref(st)),

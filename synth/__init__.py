@@ -325,3 +325,34 @@ def random_small(n: int, natoms: int, seed: int, h: float = 0.05, charged: bool 
         q = np.zeros(natoms)
     return Workload(name=f"random{natoms}_{n}_s{seed}", n=n, h=h, center=np.zeros(3),
                     xyz=xyz, q=q, sigma=sigma, eps=eps, params=Params())
+
+
+def conv_weights(specs, head_channels: int, seed: int = 0):
+    """He-uniform weights for 3x3x3 convolutions, drawn from the SplitMix64
+    stream: {name: (w (27, cout, cin) float32, zero bias)} for each
+    (name, cin, cout) in specs, plus "head": (w (head_channels,), zero bias)."""
+    rng = SplitMix64(seed)
+    out = {}
+    for name, cin, cout in specs:
+        a = math.sqrt(6.0 / (27 * cin))
+        w = rng.uniform(27 * cout * cin, -a, a).astype(np.float32).reshape(27, cout, cin)
+        out[name] = (w, np.zeros(cout, np.float32))
+    a = math.sqrt(6.0 / head_channels)
+    out["head"] = (rng.uniform(head_channels, -a, a).astype(np.float32), np.zeros(1, np.float32))
+    return out
+
+
+def warm_start_set(count: int, n: int = 128, h: float = 0.05, seed0: int = 5000):
+    """Molecules for the learned warm start: globules with atom counts
+    log-uniform in [300, 1500] on an n^3 grid of spacing h (the 1,000-atom
+    chain workload's generator and grid)."""
+    rng = SplitMix64(seed0)
+    u = rng.uniform(count)
+    out = []
+    for m in range(count):
+        na = int(round(math.exp(math.log(300.0) + u[m] * (math.log(1500.0) - math.log(300.0)))))
+        xyz = globule(na, seed=seed0 + 1 + m)
+        sigma, eps, q = atom_params(na, seed=seed0 + 1 + m)
+        out.append(Workload(name=f"warm{m}", n=n, h=h, center=np.zeros(3), xyz=xyz, q=q,
+                            sigma=sigma, eps=eps, params=Params()))
+    return out

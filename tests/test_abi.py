@@ -7,12 +7,13 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vesis.h")
+NN_HEADER = os.path.join(ROOT, "include", "vesis_nn.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vesis_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(vesis_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary_calls():
@@ -29,6 +30,15 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     assert sorted(_lib.EXPORTS) == declared_functions()
+
+
+def test_library_exports_every_network_layer():
+    from paper_2208_05524_amd import _lib, nn
+    lib = _lib.load()
+    names = declared_functions(NN_HEADER)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(nn.NN_EXPORTS) == names
 
 
 def test_library_is_built_for_gfx950():
