@@ -39,7 +39,8 @@ int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* 
                        int n, int d, int h, int wd, int cin, int cout, int relu);
 
 /* Bytes of FP32 scratch vesis_nn_conv3_wgrad needs (one partial weight
- * gradient per chunk of 2048 positions). */
+ * gradient per chunk of 8192 positions, and per-channel partial sums for
+ * the bias gradient). */
 int vesis_nn_wgrad_workspace(int n, int d, int h, int wd, int cin, int cout, size_t* bytes);
 
 /* Weight gradient dw (27,cout,cin FP32, overwritten) = sum over positions
@@ -80,11 +81,12 @@ int vesis_nn_split(void* stream, const void* dy, int ca, int cb, void* da, void*
 int vesis_nn_add(void* stream, const void* a, const void* b, void* y, int64_t count);
 
 /* 1x1x1 head: logits (p FP32) = x (p,c) . w (c FP32) + b (1 FP32); and its
- * adjoint: dx (BF16) = dlogit w, dw = sum_p dlogit x, db = sum_p dlogit. */
+ * adjoint: dx (BF16) = dlogit w, dw = sum_p dlogit x, db = sum_p dlogit,
+ * with FP32 scratch ws of at least 4 c ceil(p / 1024) bytes. */
 int vesis_nn_head_fwd(void* stream, const void* x, const float* w, const float* b, float* logits,
                       int64_t p, int c);
 int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const float* w, void* dx,
-                      float* dw, float* db, int64_t p, int c);
+                      float* dw, float* db, float* ws, size_t ws_bytes, int64_t p, int c);
 
 /* Mean binary cross-entropy of logits against labels (int8 per cell, -1 =
  * solute = target 1, +1 = solvent = target 0), solute cells weighted by

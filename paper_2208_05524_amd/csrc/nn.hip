@@ -67,22 +67,41 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
-    for (int tap = 0; tap < 27; ++tap) {
+    // K = 27 taps x Cin/16 steps, flattened; the operands of step k + 1 are
+    // loaded before the matrix instructions of step k issue
+    const int ncb = Cin / 16, K = 27 * ncb;
+    auto a_ptr = [&](int tap, bool& ok) {
         const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
         const int zz = z + dz, yy = y + dy, xx = x + dx;
-        const bool ok = pa_ok && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        ok = pa_ok && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
         const int64_t q = (((int64_t)n * D + zz) * H + yy) * W + xx;
-        const __bf16* xa = X + (ok ? q : 0) * Cin + 8 * half;
-        const __bf16* wb = Wt + ((int64_t)tap * Cout + co0 + row) * Cin + 8 * half;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            bf16x8 a = load8(xa + c0);
-            if (!ok) a = bf16x8{};
+        return X + (ok ? q : 0) * Cin + 8 * half;
+    };
+    const __bf16* wrow = Wt + ((int64_t)co0 + row) * Cin + 8 * half;
+    bool ok;
+    const __bf16* xa = a_ptr(0, ok);
+    bf16x8 a = load8(xa);
+    if (!ok) a = bf16x8{};
+    bf16x8 bb[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const bf16x8 b = load8(wb + (int64_t)t * 32 * Cin + c0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
-            }
-        }
+    for (int t = 0; t < NT; ++t) bb[t] = load8(wrow + (int64_t)t * 32 * Cin);
+    for (int k = 0; k < K; ++k) {
+        bf16x8 an = bf16x8{}, bn[NT];
+        const int k1 = k + 1 < K ? k + 1 : k;
+        const int tap1 = k1 / ncb, c1 = (k1 - tap1 * ncb) * 16;
+        bool ok1;
+        const __bf16* xa1 = a_ptr(tap1, ok1);
+        an = load8(xa1 + c1);
+        if (!ok1) an = bf16x8{};
+        const __bf16* wb1 = wrow + (int64_t)tap1 * Cout * Cin + c1;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bn[t] = load8(wb1 + (int64_t)t * 32 * Cin);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb[t], acc[t], 0, 0, 0);
+        a = an;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bb[t] = bn[t];
     }
     // D[8 (r/4) + 4 half + r%4][row]: position p0 + that, channel co0 + 32 t + row
 #pragma unroll
@@ -102,14 +121,20 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict
 
 // Weight gradient partials: for one tap, a 32 x 32 (co, ci) tile and one
 // chunk of positions: part[chunk][tap][co][ci] = sum_p dY[p][co] X[p+off][ci].
-// Each of the four wavefronts takes every fourth group of 16 positions; the
-// four tiles are added in LDS in wavefront order.
-constexpr int WCHUNK = 2048;  // positions per chunk
+// Per step a wavefront takes 16 consecutive positions: each lane loads 8
+// channels of one position of dY and of the shifted X (16-byte loads),
+// stores them transposed (channel-major) in the wavefront's own LDS tiles,
+// and the matrix operands (8 consecutive positions per lane) come back as
+// 16-byte LDS reads.  The four wavefronts take interleaved steps; their
+// tiles are added in LDS in wavefront order.
+constexpr int WCHUNK = 8192;  // positions per chunk
 __global__ __launch_bounds__(CWG) void conv3_wgrad_kernel(const __bf16* __restrict__ X,
                                                           const __bf16* __restrict__ dY,
                                                           float* __restrict__ part, int N, int D,
                                                           int H, int W, int Cin, int Cout) {
     __shared__ float red[4][32 * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 sA[4][32][16];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[4][32][16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 31, half = lane >> 5;
     const int64_t P = (int64_t)N * D * H * W;
@@ -121,28 +146,50 @@ __global__ __launch_bounds__(CWG) void conv3_wgrad_kernel(const __bf16* __restri
     const int cot = t2 % nco;
     const int tap = t2 / nco;
     const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int co = cot * 32 + row, ci = cit * 32 + row;
+    // loader role of this lane: position j of the 16, channels 8 o .. 8 o + 7
+    const int j = lane >> 2, o = lane & 3;
     f32x16 acc = f32x16{};
     const int64_t pbeg = chunk * WCHUNK;
     const int64_t pend = pbeg + WCHUNK < P ? pbeg + WCHUNK : P;
+    // coordinates of this lane's position, advanced by 64 positions per step
+    int n, z, y, x;
+    pos_coords(pbeg + 16 * wv + j, D, H, W, n, z, y, x);
     for (int64_t g0 = pbeg + 16 * wv; g0 < pend; g0 += 64) {
-        bf16x8 a, b;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t p = g0 + 8 * half + j;
-            __bf16 av = (__bf16)0.f, bv = (__bf16)0.f;
-            if (p < pend) {
-                av = dY[p * Cout + co];
-                int n, z, y, x;
-                pos_coords(p, D, H, W, n, z, y, x);
-                const int zz = z + dz, yy = y + dy, xx = x + dx;
-                if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    bv = X[((((int64_t)n * D + zz) * H + yy) * W + xx) * Cin + ci];
-            }
-            a[j] = av;
-            b[j] = bv;
+        const int64_t p = g0 + j;
+        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+        if (p < pend) {
+            va = *reinterpret_cast<const uint4*>(dY + p * Cout + cot * 32 + 8 * o);
+            const int zz = z + dz, yy = y + dy, xx = x + dx;
+            if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                vb = *reinterpret_cast<const uint4*>(
+                    X + ((((int64_t)n * D + zz) * H + yy) * W + xx) * Cin + cit * 32 + 8 * o);
         }
+        __bf16 ea[8], eb[8];
+        __builtin_memcpy(ea, &va, 16);
+        __builtin_memcpy(eb, &vb, 16);
+        __builtin_amdgcn_wave_barrier();  // the previous step's LDS reads are done
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            sA[wv][8 * o + e][j] = ea[e];
+            sB[wv][8 * o + e][j] = eb[e];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bf16x8 a = load8(&sA[wv][row][8 * half]);
+        const bf16x8 b = load8(&sB[wv][row][8 * half]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        x += 64;
+        while (x >= W) {
+            x -= W;
+            if (++y == H) {
+                y = 0;
+                if (++z == D) {
+                    z = 0;
+                    ++n;
+                }
+            }
+        }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) red[wv][(8 * (r / 4) + 4 * half + (r % 4)) * 32 + row] = acc[r];
@@ -164,15 +211,52 @@ __global__ void wgrad_reduce_kernel(const float* part, int64_t nchunks, int64_t 
     dW[i] = s;
 }
 
-// db[co] = sum_p dY[p][co]: one workgroup per channel, fixed-order tree.
-__global__ __launch_bounds__(256) void bias_grad_kernel(const __bf16* dY, int64_t P, int Cout,
-                                                        float* db) {
-    __shared__ double sh[256];
-    const int co = blockIdx.x;
+// Per-channel sums over positions, in chunks of RCH positions:
+// partial[chunk][c] = sum_p (A ? A[p][c] : 1) (scale ? scale[p] : 1);
+// 64 channels x 4 position lanes per workgroup (loads coalesced along c).
+constexpr int RCH = 1024;
+__global__ __launch_bounds__(256) void channel_partial_kernel(const __bf16* A, const float* scale,
+                                                              int64_t P, int C, float* partial) {
+    __shared__ float sh[4][64];
+    const int cl = threadIdx.x & 63, pl = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + cl;
+    const int64_t p0 = (int64_t)blockIdx.x * RCH;
+    float s = 0.f;
+    if (c < C) {
+        for (int k = pl; k < RCH; k += 4) {
+            const int64_t p = p0 + k;
+            if (p >= P) break;
+            const float v = A ? (float)A[p * C + c] : 1.f;
+            s += scale ? v * scale[p] : v;
+        }
+    }
+    sh[pl][cl] = s;
+    __syncthreads();
+    if (pl == 0 && c < C)
+        partial[blockIdx.x * (int64_t)C + c] = ((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl];
+}
+
+// out[c] = sum over chunks, in order, of partial[chunk][c] (FP64 sum).
+__global__ void channel_reduce_kernel(const float* partial, int64_t nch, int C, float* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
     double s = 0.0;
-    for (int64_t p = threadIdx.x; p < P; p += 256) s += (double)(float)dY[p * Cout + co];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) db[co] = (float)s;
+    for (int64_t k = 0; k < nch; ++k) s += partial[k * C + c];
+    out[c] = (float)s;
+}
+
+hipError_t channel_sums(const __bf16* A, const float* scale, int64_t P, int C, float* partial,
+                        float* out, hipStream_t st) {
+    const int64_t nch = (P + RCH - 1) / RCH;
+    hipLaunchKernelGGL(channel_partial_kernel, dim3((unsigned)nch, (unsigned)((C + 63) / 64)),
+                       dim3(256), 0, st, A, scale, P, C, partial);
+    hipLaunchKernelGGL(channel_reduce_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st,
+                       partial, nch, C, out);
+    return hipGetLastError();
+}
+
+size_t channel_sums_bytes(int64_t P, int C) {
+    return sizeof(float) * (size_t)((P + RCH - 1) / RCH) * (size_t)C;
 }
 
 // BF16 forward weights and the spatially flipped, channel-transposed
@@ -297,23 +381,6 @@ __global__ void head_bwd_x_kernel(const float* dlogit, const float* w, __bf16* d
     if (i >= P * C) return;
     dX[i] = (__bf16)(dlogit[i / C] * w[i % C]);
 }
-// dw[c] = sum_p dlogit[p] X[p][c] (c < C), db = sum_p dlogit[p] (c == C).
-__global__ __launch_bounds__(256) void head_bwd_w_kernel(const float* dlogit, const __bf16* X,
-                                                         int64_t P, int C, float* dw, float* db) {
-    __shared__ double sh[256];
-    const int c = blockIdx.x;
-    double s = 0.0;
-    for (int64_t p = threadIdx.x; p < P; p += 256)
-        s += (double)dlogit[p] * (c < C ? (double)(float)X[p * C + c] : 1.0);
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        if (c < C)
-            dw[c] = (float)s;
-        else
-            db[0] = (float)s;
-    }
-}
-
 // Weighted binary cross-entropy with logits against labels (target 1 for
 // solute, phi = -1), mean over cells: per-block FP64 partial losses and the
 // gradient dlogit = w (sigmoid(l) - t) / P.
@@ -433,7 +500,9 @@ int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* 
 int vesis_nn_wgrad_workspace(int n, int d, int h, int wd, int cin, int cout, size_t* bytes) {
     if (!bytes || !dims_ok(n, d, h, wd) || cin % 32 || cout % 32) return VESIS_NN_E_ARG;
     const int64_t P = (int64_t)n * d * h * wd;
-    *bytes = sizeof(float) * (size_t)((P + WCHUNK - 1) / WCHUNK) * 27 * cout * cin;
+    const size_t wpart = sizeof(float) * (size_t)((P + WCHUNK - 1) / WCHUNK) * 27 * cout * cin;
+    const size_t bpart = channel_sums_bytes(P, cout);
+    *bytes = wpart + bpart + 256;
     return 0;
 }
 
@@ -450,7 +519,11 @@ int vesis_nn_conv3_wgrad(void* stream, const void* x, const void* dy, float* dw,
                        dim3(CWG), 0, S(stream), B(x), B(dy), ws, n, d, h, wd, cin, cout);
     const int64_t nw = 27LL * cout * cin;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nblk(nw, 256)), dim3(256), 0, S(stream), ws, nch, nw, dw);
-    if (db) hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)cout), dim3(256), 0, S(stream), B(dy), P, cout, db);
+    if (db) {
+        // bias partials after the weight partials (256-byte aligned)
+        const size_t off = (sizeof(float) * (size_t)nch * nw + 255) / 256 * 256 / sizeof(float);
+        channel_sums(B(dy), nullptr, P, cout, ws + off, db, S(stream));
+    }
     return status(hipGetLastError());
 }
 
@@ -520,10 +593,12 @@ int vesis_nn_head_fwd(void* stream, const void* x, const float* w, const float* 
 }
 
 int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const float* w, void* dx,
-                      float* dw, float* db, int64_t p, int c) {
-    if (!dlogit || !x || !w || !dx || !dw || !db || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
+                      float* dw, float* db, float* ws, size_t ws_bytes, int64_t p, int c) {
+    if (!dlogit || !x || !w || !dx || !dw || !db || !ws || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
+    if (ws_bytes < channel_sums_bytes(p, c)) return VESIS_NN_E_ARG;
     hipLaunchKernelGGL(head_bwd_x_kernel, dim3(nblk(p * c, 256)), dim3(256), 0, S(stream), dlogit, w, Bm(dx), p, c);
-    hipLaunchKernelGGL(head_bwd_w_kernel, dim3((unsigned)(c + 1)), dim3(256), 0, S(stream), dlogit, B(x), p, c, dw, db);
+    channel_sums(B(x), dlogit, p, c, ws, dw, S(stream));
+    channel_sums(nullptr, dlogit, p, 1, ws, db, S(stream));
     return status(hipGetLastError());
 }
 

@@ -86,6 +86,7 @@ class UNet:
             N.check(self.L.vesis_nn_wgrad_workspace(batch, s, s, s, cin, cout, C.byref(nb)),
                     "wgrad workspace")
             need = max(need, nb.value)
+        need = max(need, 4 * LEVELS[0] * (batch * size ** 3 // 1024 + 1))  # head sums
         self.ws = torch.empty(need // 4 + 1, **f32)
         self.ws_bytes = need
         self.partial = torch.zeros(1024, dtype=torch.float64, device=self.dev)
@@ -239,7 +240,8 @@ class UNet:
         P = self.b * self.n ** 3
         db7 = self.t.empty_like(a["b7"])
         N.check(self.L.vesis_nn_head_bwd(self._s(), N.ptr(dlogit), N.ptr(a["b7"]), N.ptr(h["w"]),
-                                         N.ptr(db7), N.ptr(h["gw"]), N.ptr(h["gb"]), P, LEVELS[0]),
+                                         N.ptr(db7), N.ptr(h["gw"]), N.ptr(h["gb"]),
+                                         N.ptr(self.ws), self.ws_bytes, P, LEVELS[0]),
                 "head_bwd")
         c1, c2, c3, _ = LEVELS
         da7 = self._conv_bwd("d1b", a["a7"], a["b7"], db7)
@@ -369,3 +371,133 @@ def train(model: UNet, samples, steps: int, lr: float = 1e-3, pos_weight: float 
 def predict_logits(model: UNet, pos4, sigma, q, h, center):
     x = model.featurize(pos4, sigma, q, h, center)
     return model.forward(x)
+
+
+def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1,
+                          lr: float = 1e-3, seed: int = 0, log=print):
+    """Train the network on relaxed labels of n_train molecules (128^3 grid,
+    0.05 nm) and compare, on n_test held-out molecules, the relaxation from
+    the tight start with the relaxation from the network's labels: sweeps,
+    wall time (density, far field and sweeps included; for the learned start
+    also featurisation and the network), and the free energy reached.
+    Molecule by molecule and batched."""
+    import time
+
+    import torch
+
+    import synth
+    from .vesis import Batch, Context
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    train_set = synth.warm_start_set(n_train, seed0=5000)
+    test_set = synth.warm_start_set(n_test, seed0=9000)
+    labels, train_sweeps = relaxed_labels(train_set)
+    samples = [Sample(w, lab, dev) for w, lab in zip(train_set, labels)]
+    del labels
+    t1 = time.perf_counter()
+    log(f"training set: {n_train} molecules relaxed in {t1 - t0:.1f} s")
+    model = UNet(128, seed=seed)
+    losses = train(model, samples, steps=epochs * n_train, lr=lr,
+                   log_every=max(1, n_train // 4), log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"trained {epochs * n_train} steps in {t2 - t1:.1f} s")
+    del samples
+
+    ctxs, arrays = [], []
+    for w in test_set:
+        c = Context(0)
+        c.setup(w, precision=32)
+        ctxs.append(c)
+        arrays.append(molecule_arrays(w, dev))
+
+    def plain(c, w):
+        c.set_positions(w.xyz)
+        c.init_labels("tight", 1.0)
+        return c.minimize()[1]
+
+    def learned(c, w, a):
+        c.set_positions(w.xyz)
+        logits = predict_logits(model, a[0], a[1], a[2], w.h, w.center)
+        c.init_labels_logits(logits)
+        return c.minimize()[1]
+
+    rows = []
+    for k, (c, w, a) in enumerate(zip(ctxs, test_set, arrays)):
+        for rep in range(2):  # the first pass warms up
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sp = plain(c, w)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            gp = c.energy()["total"]
+            lab_p = c.labels()
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            sl = learned(c, w, a)
+            torch.cuda.synchronize()
+            td = time.perf_counter()
+        gl = c.energy()["total"]
+        agree = float((c.labels() == lab_p).mean())
+        rows.append(dict(atoms=w.natoms, plain_sweeps=sp["sweeps"], learned_sweeps=sl["sweeps"],
+                         plain_flips=sp["flips"], learned_flips=sl["flips"],
+                         plain_ms=1e3 * (tb - ta), learned_ms=1e3 * (td - tc),
+                         G_plain=gp, G_learned=gl, label_agreement=agree))
+    # batched: every test molecule at once
+    b = Batch(ctxs)
+    times = {}
+    for rep in range(2):
+        for c, w in zip(ctxs, test_set):
+            c.set_positions(w.xyz)
+            c.init_labels("tight", 1.0)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rc, stp = b.minimize()
+        torch.cuda.synchronize()
+        times["plain_batched_ms"] = 1e3 * (time.perf_counter() - ta)
+        for c, w in zip(ctxs, test_set):
+            c.set_positions(w.xyz)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for c, w, a in zip(ctxs, test_set, arrays):
+            c.init_labels_logits(predict_logits(model, a[0], a[1], a[2], w.h, w.center))
+        rc, stl = b.minimize()
+        torch.cuda.synchronize()
+        times["learned_batched_ms"] = 1e3 * (time.perf_counter() - ta)
+    for c in ctxs:
+        c.close()
+    dG = [abs(r["G_learned"] - r["G_plain"]) / abs(r["G_plain"]) for r in rows]
+    return {
+        "train_molecules": n_train, "test_molecules": n_test, "epochs": epochs, "grid": 128,
+        "train_relax_s": t1 - t0, "train_s": t2 - t1,
+        "train_loss_first": float(np.mean(losses[:50])), "train_loss_last": float(np.mean(losses[-50:])),
+        "plain_sweeps_mean": float(np.mean([r["plain_sweeps"] for r in rows])),
+        "learned_sweeps_mean": float(np.mean([r["learned_sweeps"] for r in rows])),
+        "plain_ms_mean": float(np.mean([r["plain_ms"] for r in rows])),
+        "learned_ms_mean": float(np.mean([r["learned_ms"] for r in rows])),
+        "max_rel_dG": float(max(dG)), "median_rel_dG": float(np.median(dG)),
+        "learned_G_lower_or_equal": int(sum(r["G_learned"] <= r["G_plain"] for r in rows)),
+        "label_agreement_mean": float(np.mean([r["label_agreement"] for r in rows])),
+        "plain_batched_sweeps_max": max(s["sweeps"] for s in stp),
+        "learned_batched_sweeps_max": max(s["sweeps"] for s in stl),
+        **times, "rows": rows}
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    res = warm_start_experiment(args.train, args.test, args.epochs, args.lr,
+                                log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    text = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)

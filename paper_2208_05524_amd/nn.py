@@ -38,7 +38,7 @@ def lib():
         L.vesis_nn_split.argtypes = [P, P, I, I, P, P, I, I64]
         L.vesis_nn_add.argtypes = [P, P, P, P, I64]
         L.vesis_nn_head_fwd.argtypes = [P, P, P, P, P, I64, I]
-        L.vesis_nn_head_bwd.argtypes = [P, P, P, P, P, P, P, I64, I]
+        L.vesis_nn_head_bwd.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, I64, I]
         L.vesis_nn_bce.argtypes = [P, P, P, I64, F, P, P, I, P]
         L.vesis_nn_adam.argtypes = [P, P, P, P, P, I64, F, F, F, F, I]
         L.vesis_nn_featurize.argtypes = [P, P, P, P, I64, I, D, P, I, P]
