@@ -9,7 +9,9 @@ re-evaluates the density of each trial; the mobility state carries over
 between steps as between iterations of the algorithm).  After the timed
 steps, the full alternation runs for --relax-iters outer iterations and is
 reported under "relax", and 64 molecules are brought to equilibrium one at a
-time and batched, reported under "batch".  All inputs are
+time and batched, reported under "batch"; the warm-start network is trained
+on relaxed molecules and compared with the tight start on held-out ones,
+reported under "learned".  All inputs are
 resident in device memory before the timed region.
 
 Prints one JSON line.  `value` is atom-gridpoint pairs of one configuration
@@ -178,6 +180,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-molecule batched-vs-one-at-a-time comparison")
+    ap.add_argument("--learned-train", type=int, default=2000,
+                    help="molecules the warm-start network trains on (0: skip the comparison)")
+    ap.add_argument("--learned-test", type=int, default=16)
     ap.add_argument("--relax-iters", type=int, default=200,
                     help="after the timed steps, run this many outer iterations of the full "
                          "alternation (Steps 2-5) from the same start and report them (0: skip)")
@@ -297,6 +302,13 @@ def main():
         log("batch comparison ...")
         out["batch"] = batch_comparison()
         log(f"batch: {out['batch']}")
+    if args.learned_train > 0:
+        log("learned warm start ...")
+        from paper_2208_05524_amd.learned import warm_start_experiment
+        res = warm_start_experiment(args.learned_train, args.learned_test, epochs=1, log=log)
+        res.pop("rows")
+        out["learned"] = res
+        log(f"learned: {res}")
     if args.relax_iters > 0:
         ctx.set_positions(xyz0)
         ctx.init_labels("tight", 1.0)

@@ -119,6 +119,92 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict
     }
 }
 
+// The same convolution with the input staged in LDS.  A workgroup owns a
+// tile of 4 MT x-rows of 32 positions (TY = 4 rows in y, TZ = MT in z) and
+// 32 NT output channels; per chunk of 16 input channels it stages the tile
+// with its one-cell halo (TZ+2) x 6 x 34 positions in LDS (16 channels =
+// 32 bytes per position, so the 32 rows of an operand are one contiguous
+// kilobyte: conflict-free 16-byte reads), then runs the 27 taps:
+// wavefront w takes y-row w of each of the MT z-layers of the tile (MT
+// operands of 32 positions) against NT output-channel tiles, the weights
+// read from global memory (shared by every workgroup, they stay in cache).
+constexpr int TX = 32, TY = 4, HX = TX + 2, HY = TY + 2;
+template <int MT, int NT, bool RELU>
+__global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const __bf16* __restrict__ X,
+                                                            const __bf16* __restrict__ Wt,
+                                                            const float* __restrict__ bias,
+                                                            __bf16* __restrict__ Y, int N, int D,
+                                                            int H, int W, int Cin, int Cout) {
+    constexpr int TZ = MT, HZ = TZ + 2, HPOS = HZ * HY * HX;
+    __shared__ __attribute__((aligned(16))) __bf16 tile[HPOS * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 31, half = lane >> 5;
+    const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
+    const int x0 = (blockIdx.x % ntx) * TX;
+    const int y0 = ((int)(blockIdx.x / ntx) % nty) * TY;
+    const int co0 = blockIdx.y * 32 * NT;
+    const int z0 = ((int)blockIdx.z % ntz) * TZ;
+    const int nb = (int)blockIdx.z / ntz;
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
+    const __bf16* wrow = Wt + ((int64_t)co0 + row) * Cin + 8 * half;
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+        __syncthreads();  // the previous chunk's reads are done
+        // stage the halo tile: two lanes per position, 8 channels each
+        for (int e = threadIdx.x; e < 2 * HPOS; e += CWG) {
+            const int hp = e >> 1, hh = e & 1;
+            const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
+            const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D)
+                v = *reinterpret_cast<const uint4*>(
+                    X + ((((int64_t)nb * D + zz) * H + yy) * W + xx) * Cin + c0 + 8 * hh);
+            *reinterpret_cast<uint4*>(&tile[hp * 16 + 8 * hh]) = v;
+        }
+        __syncthreads();
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // halo offsets 0..2
+            bf16x8 b[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                b[t] = load8(wrow + ((int64_t)tap * Cout + 32 * t) * Cin + c0);
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                // x-row: z layer i, y row wv of the tile
+                const int hp = ((i + dz) * HY + (wv + dy)) * HX + (row + dx);
+                const bf16x8 a = load8(&tile[hp * 16 + 8 * half]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], acc[i][t], 0, 0, 0);
+            }
+        }
+    }
+    // D[8 (r/4) + 4 half + r%4][row]: x = x0 + that, channel co0 + 32 t + row
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int z = z0 + i, y = y0 + wv;
+        if (z >= D || y >= H) continue;
+        const int64_t rowbase = (((int64_t)nb * D + z) * H + y) * W;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = co0 + 32 * t + row;
+            const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int x = x0 + 8 * (r / 4) + 4 * half + (r % 4);
+                if (x >= W) continue;
+                float v = acc[i][t][r] + bv;
+                if (RELU) v = v > 0.f ? v : 0.f;
+                Y[(rowbase + x) * Cout + co] = (__bf16)v;
+            }
+        }
+    }
+}
+
 // Weight gradient partials: for one tap, a 32 x 32 (co, ci) tile and one
 // chunk of positions: part[chunk][tap][co][ci] = sum_p dY[p][co] X[p+off][ci].
 // Per step a wavefront takes 16 consecutive positions: each lane loads 8
@@ -485,6 +571,26 @@ int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* 
         return VESIS_NN_E_ARG;
     const int64_t P = (int64_t)n * d * h * wd;
     const bool two = cout % 64 == 0;
+    if (wd >= TX / 2) {
+        // LDS-staged tiles: 4 x-rows (y) x MT z-layers x 32 positions
+        const unsigned nt_xy = (unsigned)(((wd + TX - 1) / TX) * ((h + TY - 1) / TY));
+        if (two) {
+            constexpr int MT = 2;
+            const dim3 grid(nt_xy, (unsigned)(cout / 64), (unsigned)(n * ((d + MT - 1) / MT)));
+            if (relu)
+                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            else
+                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+        } else {
+            constexpr int MT = 4;
+            const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + MT - 1) / MT)));
+            if (relu)
+                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            else
+                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+        }
+        return status(hipGetLastError());
+    }
     const dim3 grid(nblk(P, 128), (unsigned)(cout / (two ? 64 : 32)));
     if (two && relu)
         hipLaunchKernelGGL((conv3_fwd_kernel<2, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);

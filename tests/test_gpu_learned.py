@@ -32,11 +32,15 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-@pytest.mark.parametrize("n,cin,cout,relu", [(8, 32, 64, 1), (6, 16, 32, 0), (5, 96, 32, 1)])
+@pytest.mark.parametrize("n,cin,cout,relu", [(8, 32, 64, 1), (6, 16, 32, 0), (5, 96, 32, 1),
+                                             (16, 32, 64, 1), (20, 32, 32, 1), (18, 16, 64, 0),
+                                             (24, 96, 32, 1)])
 def test_conv_forward_matches_reference(n, cin, cout, relu):
-    """Ragged position counts (6^3, 5^3 against 128-position tiles), both
-    output-channel tilings, with and without ReLU: every output within BF16
-    rounding of the FP64 convolution of the same BF16 inputs."""
+    """Both kernels (grids narrower than 16 cells take the direct one, wider
+    ones the LDS-tiled one), ragged sizes against their tiles (128 positions;
+    32 x 4 x MT), both output-channel tilings, with and without ReLU: every
+    output within BF16 rounding of the FP64 convolution of the same BF16
+    inputs."""
     import torch
 
     from oracle import unet
@@ -70,7 +74,7 @@ def test_conv_gradients_match_reference():
     from oracle import unet
     from paper_2208_05524_amd import nn
     r = np.random.default_rng(11)
-    n, cin, cout = 12, 64, 32
+    n, cin, cout = 20, 64, 32
     x = _bf(r.standard_normal((1, n, n, n, cin)))
     w = 0.1 * r.standard_normal((27, cout, cin)).astype(np.float32)
     dy = _bf(r.standard_normal((1, n, n, n, cout)))
