@@ -13,7 +13,9 @@
 // Layout.  A staging kernel first compacts, per chunk of cells (a cubic
 // 16^3 brick of the grid, or a run of 4096 far-field nodes), the cells with
 // nonzero weight in cell order, as (position relative to the chunk centre,
-// w) and w E in the working precision; it writes the count per chunk.  The
+// w) and w E in the working precision (for grid cells w = 1: their common
+// weight h^3 multiplies the sums of each tile instead, which saves a
+// multiply per pair); it writes the count per chunk.  The
 // force kernel gives a workgroup 256 atoms (one per lane) and a group of
 // consecutive chunks; the staged cells of each chunk stream through a
 // double-buffered LDS tile of 256 (the next tile is fetched into registers
@@ -156,11 +158,11 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
                 if (x < g.n && y < g.n && z < g.n) {
                     const uint32_t word = f.bits[g.row(y, z) + 1 + (x >> 5)];
                     if ((word >> (x & 31)) & 1u) {
+                        // weight h^3 left out: applied to the sums of the tile
                         const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-                        const double wd = f.ph.h3;
                         a = mk4((T)((lx - 0.5 * (CB - 1)) * g.h), (T)((ly - 0.5 * (CB - 1)) * g.h),
-                                (T)((lz - 0.5 * (CB - 1)) * g.h), (T)wd);
-                        b = mk4((T)(wd * f.ex[c]), (T)(wd * f.ey[c]), (T)(wd * f.ez[c]), (T)0);
+                                (T)((lz - 0.5 * (CB - 1)) * g.h), (T)1);
+                        b = mk4((T)f.ex[c], (T)f.ey[c], (T)f.ez[c], (T)0);
                         keep = true;
                     }
                 }
@@ -198,7 +200,9 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
 // an atom of the wave may lie within sqrt(r2_min) of a cell of the chunk).
 // With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the LJ part
 // of the coefficient is w r^-2 r^-6 (c1 r^-6 - c2).
-template <typename T, bool FLOOR>
+// UNIT_W: the staged weights are all 1 (grid cells, whose common weight h^3
+// is applied to the tile's sums instead).
+template <typename T, bool FLOOR, bool UNIT_W>
 __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt, T ax, T ay,
                                            T az, T c1, T c2, T k3, T r2min, T (&acc)[6]) {
     using T4 = typename V4<T>::type;
@@ -220,7 +224,7 @@ __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int c
         const T ir2 = ir * ir;
         const T ir3 = ir2 * ir;
         const T ir6 = ir2 * ir2 * ir2;
-        const T lj = ((c.w * ir2) * ir6) * (c1 * ir6 - c2);
+        const T lj = (UNIT_W ? ir2 * ir6 : (c.w * ir2) * ir6) * (c1 * ir6 - c2);
         const T ed = e.x * dx + e.y * dy + e.z * dz;
         T coef = lj - k3 * (ed * (ir3 * ir2));
         if (FLOOR) coef = inside ? (T)0 : coef;
@@ -280,7 +284,9 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         const T ax = (T)(px - ox), ay = (T)(py - oy), az = (T)(pz - oz);
         const bool near = has_atom && fabs(px - ox) <= reach && fabs(py - oy) <= reach &&
                           fabs(pz - oz) <= reach;
-        const bool floor = chunk >= f.ngrid || __ballot(near) != 0;
+        const bool is_grid = chunk < f.ngrid;
+        const bool floor = !is_grid || __ballot(near) != 0;
+        const double wscale = is_grid ? f.ph.h3 : 1.0;
         const T4* src = staged + 2 * chunk_slot0(f, chunk);
         const int ntiles = (cnt + CT - 1) / CT;
         T4 ra = mk4((T)0, (T)0, (T)0, (T)0), rb = ra;
@@ -299,16 +305,18 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
             }
             const int m = cnt - tile * CT < CT ? cnt - tile * CT : CT;
             T acc[6];
-            if (floor)
-                tile_pairs<T, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+            if (!is_grid)
+                tile_pairs<T, true, false>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+            else if (floor)
+                tile_pairs<T, true, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else
-                tile_pairs<T, false>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
-            gd[0] += acc[0];
-            gd[1] += acc[1];
-            gd[2] += acc[2];
-            ge[0] += acc[3];
-            ge[1] += acc[4];
-            ge[2] += acc[5];
+                tile_pairs<T, false, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+            gd[0] += wscale * acc[0];
+            gd[1] += wscale * acc[1];
+            gd[2] += wscale * acc[2];
+            ge[0] += wscale * acc[3];
+            ge[1] += wscale * acc[4];
+            ge[2] += wscale * acc[5];
             if (tile + 1 < ntiles) {
                 // the other buffer was last read in tile - 1, before the
                 // barrier that ended it
