@@ -165,10 +165,19 @@ def cpu_baseline(w, budget_s: float = 12.0):
     dt = time.perf_counter() - t0
     pairs = planes * n * n * w.natoms
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": pairs / dt, "unit": "atom·gridpt/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle density over {planes} z-planes ({planes * n * n} cells) of "
-                      f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s; the GPU value is a whole "
-                      f"hot-path step, whose density work alone is >= 2 such evaluations"}
+                      f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s on {cores} threads of "
+                      f"{model}; the GPU value is a whole hot-path step, whose density work "
+                      f"alone is >= 2 such evaluations"}
 
 
 def main():
