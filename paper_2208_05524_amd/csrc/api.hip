@@ -798,8 +798,11 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
         CK(launch_fill_u32(bits, g.nwords(), 0xffffffffu, st));
         if (mode == 0)
             CK(launch_init_loose(g, param, bits, st));
-        else
-            CK(launch_init_tight(g, dev_atoms(ctx), param, bits, st));
+        else {
+            double smax = 0.0;
+            for (double sg : ctx->sigma) smax = std::max(smax, sg);
+            CK(launch_init_tight(g, dev_atoms(ctx), param, param * smax, bits, st));
+        }
     }
     ctx->has_labels = true;
     ctx->forces_valid = false;

@@ -112,8 +112,9 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream_t st);
-hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
-                             hipStream_t st);
+// bits must hold all-solvent labels; dmax >= scale * max_i sigma_i.
+hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, double dmax,
+                             uint32_t* bits, hipStream_t st);
 // In-box label bits from per-cell logits (solute where logit > 0).
 hipError_t launch_labels_from_logits(const Grid& g, const float* logits, uint32_t* bits,
                                      hipStream_t st);

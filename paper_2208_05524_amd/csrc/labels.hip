@@ -16,6 +16,8 @@
 // strided share of the atoms, fixed tree sum), caches it, and decides.
 // Cells of one colour lie outside each other's kernel support, so all
 // decisions of a pass read only labels that the pass does not change.
+#include <cmath>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -78,71 +80,45 @@ __global__ void init_loose_kernel(Grid g, double R0, uint32_t* bits) {
     bits[g.row(y, z) + 1 + w] = word;
 }
 
-// Tight surface: solute iff min_i (|x - r_i| - d_i) <= 0, d_i = scale sigma_i.
-// A workgroup owns one 32-cell word column (fixed w) of a 16 x 16 patch of
-// rows (y, z).  Atoms stream through in tiles of 256; each lane tests one
-// atom of the tile against the patch's bounding box and the survivors are
-// compacted into LDS, so every lane then visits only atoms that can reach
-// its row; those are tested cell by cell in FP64 exactly as defined.
-constexpr int IWG = 256;
-__global__ __launch_bounds__(IWG) void init_tight_kernel(Grid g, Atoms a, double scale,
+// Tight surface: solute iff min_i (|x - r_i| - d_i) <= 0, d_i = scale sigma_i,
+// i.e. the union over atoms of the cells within d_i of the atom.  Scattered
+// from the atoms (after the labels are filled with solvent): one lane per
+// (atom, row) of the atom's box of (2R+1)^2 rows around its cell, R covering
+// the largest d_i; the cells of the row within the box are tested exactly as
+// defined, in FP64, and the solute ones cleared with one atomic AND per word.
+// The union does not depend on the order of the atoms.
+__global__ __launch_bounds__(256) void init_tight_kernel(Grid g, Atoms a, double scale, int R,
                                                          uint32_t* bits) {
 #pragma clang fp contract(off)
-    __shared__ double4 sat[IWG];
-    __shared__ int nsurv;
-    const int t = threadIdx.x;
-    const int npy = (g.n + 15) / 16;
-    int b = blockIdx.x;
-    const int w = b % g.nwin;
-    b /= g.nwin;
-    const int yb = b % npy, zb = b / npy;
-    const int y = yb * 16 + (t & 15), z = zb * 16 + (t >> 4);
-    const bool active = y < g.n && z < g.n;
-    const int x0 = 32 * w;
-    const int xl = min(32, g.n - x0);
-    const int ylo = yb * 16, yhi = min(yb * 16 + 15, g.n - 1);
-    const int zlo = zb * 16, zhi = min(zb * 16 + 15, g.n - 1);
-    // cell-centre bounding box of the patch
-    const double bx0 = centre_coord(g.cx, g.L, x0, g.h), bx1 = centre_coord(g.cx, g.L, x0 + xl - 1, g.h);
-    const double by0 = centre_coord(g.cy, g.L, ylo, g.h), by1 = centre_coord(g.cy, g.L, yhi, g.h);
-    const double bz0 = centre_coord(g.cz, g.L, zlo, g.h), bz1 = centre_coord(g.cz, g.L, zhi, g.h);
-    const double py = centre_coord(g.cy, g.L, active ? y : ylo, g.h);
-    const double pz = centre_coord(g.cz, g.L, active ? z : zlo, g.h);
-    uint32_t solute = 0;
-    for (int64_t base = 0; base < a.n; base += IWG) {
-        if (t == 0) nsurv = 0;
-        __syncthreads();
-        const int64_t ai = base + t;
-        if (ai < a.n) {
-            const double4 p = a.pos[ai];
-            const double d = scale * a.prm64[ai].w;
-            const double ex = p.x < bx0 ? bx0 - p.x : (p.x > bx1 ? p.x - bx1 : 0.0);
-            const double ey = p.y < by0 ? by0 - p.y : (p.y > by1 ? p.y - by1 : 0.0);
-            const double ez = p.z < bz0 ? bz0 - p.z : (p.z > bz1 ? p.z - bz1 : 0.0);
-            const double lim = d * (1.0 + 1e-9) + 1e-12;
-            if (ex * ex + ey * ey + ez * ez <= lim * lim) {
-                const int slot = atomicAdd(&nsurv, 1);
-                sat[slot] = make_double4(p.x, p.y, p.z, d);
-            }
+    const int side = 2 * R + 1;
+    const int64_t rows = (int64_t)side * side;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= a.n * rows) return;
+    const int64_t ai = tid / rows;
+    const int r = (int)(tid - ai * rows);
+    const double4 p = a.pos[ai];
+    const double d = scale * a.prm64[ai].w;
+    // the atom's cell along each axis
+    const int ix = (int)floor((p.x - (g.cx - g.L)) / g.h);
+    const int iy = (int)floor((p.y - (g.cy - g.L)) / g.h);
+    const int iz = (int)floor((p.z - (g.cz - g.L)) / g.h);
+    const int y = iy + r % side - R, z = iz + r / side - R;
+    if (y < 0 || y >= g.n || z < 0 || z >= g.n) return;
+    const double dy = centre_coord(g.cy, g.L, y, g.h) - p.y;
+    const double dz = centre_coord(g.cz, g.L, z, g.h) - p.z;
+    const double lim = d * (1.0 + 1e-9) + 1e-12;
+    if (dy * dy + dz * dz > lim * lim) return;  // no cell of this row is within d
+    const int xlo = max(0, ix - R), xhi = min(g.n - 1, ix + R);
+    uint32_t* row = bits + g.row(y, z) + 1;
+    for (int w = xlo >> 5; w <= (xhi >> 5); ++w) {
+        uint32_t mask = 0;
+        const int xa = max(xlo, 32 * w), xb = min(xhi, 32 * w + 31);
+        for (int x = xa; x <= xb; ++x) {
+            const double dx = centre_coord(g.cx, g.L, x, g.h) - p.x;
+            if (sqrt(dx * dx + dy * dy + dz * dz) - d <= 0.0) mask |= 1u << (x & 31);
         }
-        __syncthreads();
-        const int cnt = nsurv;
-        if (active) {
-            for (int m = 0; m < cnt; ++m) {
-                const double4 p = sat[m];
-                const double dy = py - p.y, dz = pz - p.z;
-                const double ex = p.x < bx0 ? bx0 - p.x : (p.x > bx1 ? p.x - bx1 : 0.0);
-                const double lim = p.w * (1.0 + 1e-9) + 1e-12;
-                if (ex * ex + dy * dy + dz * dz > lim * lim) continue;
-                for (int bb = 0; bb < xl; ++bb) {
-                    const double dx = centre_coord(g.cx, g.L, x0 + bb, g.h) - p.x;
-                    if (sqrt(dx * dx + dy * dy + dz * dz) - p.w <= 0.0) solute |= 1u << bb;
-                }
-            }
-        }
-        __syncthreads();
+        if (mask) atomicAnd(&row[w], ~mask);
     }
-    if (active) bits[g.row(y, z) + 1 + w] = ~solute;  // padding bits past n stay 1
 }
 
 // ------------------------------------------------------------- stencil
@@ -574,12 +550,14 @@ hipError_t launch_init_loose(const Grid& g, double R0, uint32_t* bits, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, uint32_t* bits,
-                             hipStream_t st) {
-    const int64_t np = (g.n + 15) / 16;
-    const int64_t blocks = (int64_t)g.nwin * np * np;
-    hipLaunchKernelGGL(init_tight_kernel, dim3((unsigned)blocks), dim3(IWG), 0, st, g, a, scale,
-                       bits);
+hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, double dmax,
+                             uint32_t* bits, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    // rows within dmax of the atom's cell, plus one for the cell's own offset
+    const int R = (int)std::min(std::ceil(dmax / g.h) + 2.0, (double)g.n + 2.0);
+    const int64_t threads = a.n * (int64_t)(2 * R + 1) * (2 * R + 1);
+    hipLaunchKernelGGL(init_tight_kernel, dim3(nblk(threads, 256)), dim3(256), 0, st, g, a, scale,
+                       R, bits);
     return hipGetLastError();
 }
 
