@@ -7,6 +7,8 @@ labels, colour minimisation, energy) on the host cores, and forces on 64
 seeded atoms.  Every cell's density must lie inside the kernel's certified
 bound; labels, sweep and flip counts must match exactly when the oracle saw
 no decision inside 1e-9 |G|; energies within 1e-6 |G|; forces within 1e-4.
+A last test checks the FP64 force adjoint at this size against
+Richardson-extrapolated central differences of the energy.
 """
 import time
 
@@ -96,4 +98,51 @@ def test_full_size_forces_on_sampled_atoms(full):
     fg = full["g_f"][full["sel"]]
     ok, rel = force_close(fg, full["o_f"], 1e-4)
     log("force max rel err", float(rel.max()))
+    assert ok.all()
+
+
+def test_full_size_forces_match_central_differences_fp64():
+    """The force adjoint at the benchmark's full size against central
+    differences of the energy at fixed labels, with FP64 densities, on 12
+    seeded atoms x 3 directions; 1e-4 relative, as for the oracle comparison.
+
+    At this size the central difference with step h = 1e-4 nm still carries
+    its O(h^2) truncation error (up to ~5e-3 relative here: the difference
+    moves by 4x per doubling of h), so the differences at h and h/2 are
+    combined by Richardson extrapolation, (4 D(h/2) - D(h)) / 3, which
+    cancels the h^2 term."""
+    import time
+
+    w = synth.two_globules()
+    ctx = gpu_context(w, precision=64, with_bonds=True)
+    ctx.init_labels("tight", 1.0)
+    t0 = time.time()
+    f = ctx.forces()
+    rng = synth.SplitMix64(3065)
+    sel = np.unique((rng.uniform(40) * w.natoms).astype(np.int64))[:12]
+    hfd = 1e-4
+
+    def central(a, d, step):
+        xp = w.xyz.copy()
+        xp[a, d] += step
+        ctx.set_positions(xp)
+        ep = ctx.energy()["total"]
+        xm = w.xyz.copy()
+        xm[a, d] -= step
+        ctx.set_positions(xm)
+        em = ctx.energy()["total"]
+        return -(ep - em) / (2 * step)
+
+    fd = np.zeros((len(sel), 3))
+    plain = np.zeros((len(sel), 3))
+    for k, a in enumerate(sel):
+        for d in range(3):
+            d1, d2 = central(a, d, hfd), central(a, d, hfd / 2)
+            plain[k, d] = d1
+            fd[k, d] = (4.0 * d2 - d1) / 3.0
+    ctx.set_positions(w.xyz)
+    ok, rel = force_close(f[sel], fd, 1e-4)
+    _, rel_plain = force_close(f[sel], plain, 1e-4)
+    log("full-size FD (FP64):", len(sel), "atoms, max rel err", float(rel.max()),
+        "(plain h = 1e-4 difference:", float(rel_plain.max()), ")", f"{time.time() - t0:.1f}s")
     assert ok.all()
