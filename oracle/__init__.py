@@ -29,7 +29,51 @@ class _Sys(C.Structure):
                 ("center", _D * 3), ("h", _D), ("na", _I64),
                 ("xyz", _P), ("q", _P), ("sigma", _P), ("eps", _P),
                 ("rho_w", _D), ("gamma0", _D), ("eps_m", _D), ("eps_w", _D),
-                ("coulomb_k", _D), ("rho_s", _D), ("r2_min", _D)]
+                ("coulomb_k", _D), ("rho_s", _D), ("r2_min", _D), ("ss", _P)]
+
+
+class _SS(C.Structure):
+    _fields_ = [("nang", _I64), ("ang", _P), ("theta0", _P), ("kang", _P),
+                ("ntor", _I64), ("tor", _P), ("tc", _P), ("tpsi", _P),
+                ("nonbonded", _I32), ("pad", _I32), ("sigma_ss", _P), ("eps_ss", _P),
+                ("nexcl", _I64), ("excl", _P)]
+
+
+class SoluteTerms:
+    """Solute-solute terms of Eq. "Gss" beyond bonds: bending triplets
+    (i, j, k; vertex j), torsion quadruples with C_0..C_6 and psi_0..psi_6,
+    and the non-bonded LJ + Coulomb pairs (all pairs minus `exclusions`)."""
+
+    def __init__(self, angles=None, theta0=None, k_angle=None, torsions=None, c=None, psi=None,
+                 nonbonded=False, sigma_ss=None, eps_ss=None, exclusions=None):
+        def arr(a, shape, dt):
+            return np.ascontiguousarray(np.zeros(shape) if a is None else a, dtype=dt).reshape(shape)
+        na = 0 if angles is None else len(angles)
+        nt = 0 if torsions is None else len(torsions)
+        ne = 0 if exclusions is None else len(exclusions)
+        self.angles = arr(angles, (na, 3), np.int32)
+        self.theta0 = arr(theta0, (na,), np.float64)
+        self.k_angle = arr(k_angle, (na,), np.float64)
+        self.torsions = arr(torsions, (nt, 4), np.int32)
+        self.c = arr(c, (nt, 7), np.float64)
+        self.psi = arr(psi, (nt, 7), np.float64)
+        self.nonbonded = bool(nonbonded)
+        self.sigma_ss = None if sigma_ss is None else np.ascontiguousarray(sigma_ss, np.float64)
+        self.eps_ss = None if eps_ss is None else np.ascontiguousarray(eps_ss, np.float64)
+        self.exclusions = arr(exclusions, (ne, 2), np.int32)
+
+    def struct(self, sigma, eps) -> _SS:
+        t = _SS()
+        t.nang, t.ang = len(self.angles), self.angles.ctypes.data
+        t.theta0, t.kang = self.theta0.ctypes.data, self.k_angle.ctypes.data
+        t.ntor, t.tor = len(self.torsions), self.torsions.ctypes.data
+        t.tc, t.tpsi = self.c.ctypes.data, self.psi.ctypes.data
+        t.nonbonded = int(self.nonbonded)
+        self._sig = self.sigma_ss if self.sigma_ss is not None else sigma
+        self._eps = self.eps_ss if self.eps_ss is not None else eps
+        t.sigma_ss, t.eps_ss = self._sig.ctypes.data, self._eps.ctypes.data
+        t.nexcl, t.excl = len(self.exclusions), self.exclusions.ctypes.data
+        return t
 
 
 class Mobility(C.Structure):
@@ -52,6 +96,10 @@ class RelaxOpts(C.Structure):
 class RelaxReport(C.Structure):
     _fields_ = [("iters", _I32), ("stop_reason", _I32), ("sweeps", _I32), ("retries", _I32),
                 ("G_final", _D), ("max_grad", _D), ("dG_abs", _D), ("dG_rel", _D)]
+
+
+ENERGY_KEYS = ("geom", "vdw_in", "vdw_far", "elec_in", "elec_far", "bond", "bend", "torsion",
+               "vdw_ss", "elec_ss", "total")
 
 
 def default_mobility(dt: float = 0.1) -> Mobility:
@@ -89,6 +137,8 @@ def lib():
         L.orc_energy.argtypes = [sp, _P, _P, _P, _P, _P]
         L.orc_bond_energy.argtypes = [_I64, _P, _P, _P, _P]
         L.orc_bond_energy.restype = _D
+        L.orc_ss_energy.argtypes = [sp, _P]
+        L.orc_ss_gradient.argtypes = [sp, _P]
         L.orc_delta_e.argtypes = [sp, _P, _P, _I64]
         L.orc_delta_e.restype = _D
         L.orc_in_band.argtypes = [sp, _P, _I64]
@@ -140,7 +190,7 @@ class System:
     """One molecule on one grid, in the oracle's terms."""
 
     def __init__(self, n, h, center, xyz, q, sigma, eps, params, bonds=None, bond_r0=None,
-                 bond_k=None):
+                 bond_k=None, ss: SoluteTerms | None = None):
         self.n = int(n)
         self.h = float(h)
         self.center = np.ascontiguousarray(center, dtype=np.float64)
@@ -154,13 +204,14 @@ class System:
             bonds if bonds is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
         self.bond_r0 = np.ascontiguousarray(bond_r0 if nb else np.zeros(0), dtype=np.float64)
         self.bond_k = np.ascontiguousarray(bond_k if nb else np.zeros(0), dtype=np.float64)
+        self.ss = ss
         self._rebuild()
 
     @classmethod
-    def from_workload(cls, w, with_bonds: bool = False):
+    def from_workload(cls, w, with_bonds: bool = False, ss: SoluteTerms | None = None):
         return cls(w.n, w.h, w.center, w.xyz, w.q, w.sigma, w.eps, w.params,
                    w.bonds if with_bonds else None, w.bond_r0 if with_bonds else None,
-                   w.bond_k if with_bonds else None)
+                   w.bond_k if with_bonds else None, ss)
 
     def _rebuild(self):
         p = self.params
@@ -178,12 +229,15 @@ class System:
         s.eps = self.eps.ctypes.data
         s.rho_w, s.gamma0, s.eps_m, s.eps_w = p.rho_w, p.gamma0, p.eps_m, p.eps_w
         s.coulomb_k, s.rho_s, s.r2_min = p.coulomb_k, p.rho_s, p.r2_min
+        if self.ss is not None:
+            self._ss = self.ss.struct(self.sigma, self.eps)
+            s.ss = C.addressof(self._ss)
         self._s = s
 
     def with_positions(self, xyz):
         return System(self.n, self.h, self.center, xyz, self.q, self.sigma, self.eps,
                       self.params, self.bonds if len(self.bonds) else None, self.bond_r0,
-                      self.bond_k)
+                      self.bond_k, self.ss)
 
     @property
     def ncell(self) -> int:
@@ -323,11 +377,22 @@ class System:
 
     def total_energy(self, phi):
         phi = np.ascontiguousarray(phi, dtype=np.int8)
-        comps = np.zeros(7)
+        comps = np.zeros(11)
         lib().orc_total_energy(self.sref, _ptr(phi), len(self.bonds), _ptr(self.bonds),
                                _ptr(self.bond_r0), _ptr(self.bond_k), _ptr(comps))
-        return dict(geom=comps[0], vdw_in=comps[1], vdw_far=comps[2], elec_in=comps[3],
-                    elec_far=comps[4], bond=comps[5], total=comps[6])
+        return dict(zip(ENERGY_KEYS, (float(v) for v in comps)))
+
+    def ss_energy(self) -> dict:
+        """Bending, torsion, solute-solute LJ and Coulomb energies."""
+        out = np.zeros(4)
+        lib().orc_ss_energy(self.sref, _ptr(out))
+        return dict(bend=out[0], torsion=out[1], vdw_ss=out[2], elec_ss=out[3])
+
+    def ss_gradient(self) -> np.ndarray:
+        """Gradient (na x 3) of the bending, torsion and non-bonded terms."""
+        g = np.zeros((self.xyz.shape[0], 3))
+        lib().orc_ss_gradient(self.sref, _ptr(g))
+        return g
 
     def atom_step(self, xyz, phi, mobility: Mobility, movable=None):
         """One adaptive-mobility step; xyz (na x 3) is updated in place."""

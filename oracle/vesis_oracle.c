@@ -29,7 +29,12 @@
  *     schedule (orc_minimize_colour); the paper's min-heap descent is kept as
  *     orc_minimize_heap and compared by energy only;
  *   - forces are minus the exact gradient of the discrete energy at fixed
- *     labels (in-box midpoint sum + far-field quadrature + bonds);
+ *     labels (in-box midpoint sum + far-field quadrature + bonds + the
+ *     solute-solute terms);
+ *   - solute-solute LJ pairs mix by sigma_ij = (sigma_i + sigma_j)/2 and
+ *     eps_ij = sqrt(eps_i eps_j); the non-bonded pairs are all pairs not on
+ *     an explicit exclusion list; the torsion angle is unsigned, tau in
+ *     [0, pi], and psi_n is 0 or pi (the Appendix's gradient assumes this);
  *   - the adaptive-mobility step follows Step 3.3-3.4 of the algorithm with
  *     delta G* = dG_frac * |G_old|.
  */
@@ -61,7 +66,36 @@ typedef struct {
     double coulomb_k;   /* 1 / (4 pi eps0) */
     double rho_s;       /* delta / h */
     double r2_min;      /* floor on |x - r_i|^2 */
+    const struct orc_ss* ss; /* solute-solute terms beyond bonds, or NULL */
 } orc_sys;
+
+/* Solute-solute terms of Eq. "Gss" beyond the bonds (which are passed to the
+ * energy and force calls directly):
+ *   bending   sum over triplets (i, j, k) of (1/2) B (theta_ijk - theta0)^2,
+ *             theta_ijk the angle at j between r_i - r_j and r_k - r_j;
+ *   torsion   sum over quadruples (i, j, k, l) of
+ *             sum_{n=0..6} C_n [1 + cos(n tau - psi_n)], tau in [0, pi] the
+ *             angle between the planes (i, j, k) and (j, k, l);
+ *   LJ, Coulomb over the pairs i < j not listed in excl:
+ *             4 eps_ij [(sigma_ij/r)^12 - (sigma_ij/r)^6] with
+ *             sigma_ij = (sigma_i + sigma_j)/2, eps_ij = sqrt(eps_i eps_j),
+ *             and coulomb_k Q_i Q_j / (eps_w r). */
+typedef struct orc_ss {
+    int64_t nang;
+    const int32_t* ang;     /* nang x 3: i, j (vertex), k */
+    const double* theta0;   /* equilibrium angle, radians */
+    const double* kang;     /* B */
+    int64_t ntor;
+    const int32_t* tor;     /* ntor x 4: i, j, k, l */
+    const double* tc;       /* ntor x 7: C_0 .. C_6 */
+    const double* tpsi;     /* ntor x 7: psi_0 .. psi_6, each 0 or pi */
+    int32_t nonbonded;      /* nonzero: include the LJ and Coulomb pair terms */
+    int32_t pad;
+    const double* sigma_ss; /* per-atom solute-solute LJ sigma */
+    const double* eps_ss;   /* per-atom solute-solute LJ epsilon */
+    int64_t nexcl;
+    const int32_t* excl;    /* nexcl x 2 excluded pairs (any order) */
+} orc_ss;
 
 /* ------------------------------------------------------------- constants */
 
@@ -318,6 +352,230 @@ double orc_bond_energy(int64_t nb, const int32_t* ij, const double* r0, const do
         e += 0.5 * kb[b] * (r - r0[b]) * (r - r0[b]);
     }
     return e;
+}
+
+/* ------------------------------------------------- solute-solute terms */
+
+static void sub3(const double* a, const double* b, double* o) {
+    o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Bending angle theta_ijk at vertex j (second term of Eq. "Gss"). */
+static double bend_angle(const double* ri, const double* rj, const double* rk) {
+    double qji[3], qjk[3];
+    sub3(ri, rj, qji);
+    sub3(rk, rj, qjk);
+    double c = dot3(qji, qjk) / (sqrt(dot3(qji, qji)) * sqrt(dot3(qjk, qjk)));
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    return acos(c);
+}
+
+/* cos tau of quadruple (i, j, k, l): Lambda = u.v / (|u| |v|), u = q1 x q2,
+ * v = q2 x q3 with q1 = r_j - r_i, q2 = r_k - r_j, q3 = r_l - r_k (Appendix,
+ * "Force calculations of molecular mechanical interactions"). */
+static double torsion_cos(const double* ri, const double* rj, const double* rk, const double* rl) {
+    double q1[3], q2[3], q3[3], u[3], v[3];
+    sub3(rj, ri, q1);
+    sub3(rk, rj, q2);
+    sub3(rl, rk, q3);
+    cross3(q1, q2, u);
+    cross3(q2, q3, v);
+    double c = dot3(u, v) / (sqrt(dot3(u, u)) * sqrt(dot3(v, v)));
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    return c;
+}
+
+/* Sum over triplets of (1/2) B (theta - theta0)^2. */
+double orc_bend_energy(const orc_ss* t, const double* xyz) {
+    double e = 0.0;
+    for (int64_t a = 0; a < t->nang; ++a) {
+        const int32_t* id = t->ang + 3 * a;
+        double th = bend_angle(xyz + 3 * id[0], xyz + 3 * id[1], xyz + 3 * id[2]);
+        e += 0.5 * t->kang[a] * (th - t->theta0[a]) * (th - t->theta0[a]);
+    }
+    return e;
+}
+
+/* Sum over quadruples of sum_n C_n [1 + cos(n tau - psi_n)], tau = acos Lambda. */
+double orc_torsion_energy(const orc_ss* t, const double* xyz) {
+    double e = 0.0;
+    for (int64_t a = 0; a < t->ntor; ++a) {
+        const int32_t* id = t->tor + 4 * a;
+        double tau = acos(torsion_cos(xyz + 3 * id[0], xyz + 3 * id[1], xyz + 3 * id[2],
+                                      xyz + 3 * id[3]));
+        for (int n = 0; n <= 6; ++n)
+            e += t->tc[7 * a + n] * (1.0 + cos(n * tau - t->tpsi[7 * a + n]));
+    }
+    return e;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Sorted keys min(i,j) * na + max(i,j) of the excluded pairs. */
+static int64_t* exclusion_keys(const orc_ss* t, int64_t na) {
+    int64_t* k = malloc(sizeof(int64_t) * (size_t)(t->nexcl > 0 ? t->nexcl : 1));
+    for (int64_t e = 0; e < t->nexcl; ++e) {
+        int64_t i = t->excl[2 * e], j = t->excl[2 * e + 1];
+        k[e] = (i < j ? i : j) * na + (i < j ? j : i);
+    }
+    qsort(k, (size_t)t->nexcl, sizeof(int64_t), cmp_i64);
+    return k;
+}
+
+static int excluded(const int64_t* keys, int64_t nkeys, int64_t na, int64_t i, int64_t j) {
+    int64_t key = (i < j ? i : j) * na + (i < j ? j : i);
+    return bsearch(&key, keys, (size_t)nkeys, sizeof(int64_t), cmp_i64) != NULL;
+}
+
+/* LJ (u[0]) and Coulomb (u[1]) energy of one non-bonded pair, and
+ * dU/dr / r of their sum (the last two terms of Eq. "Gss"). */
+static void pair_terms(const orc_sys* s, int64_t i, int64_t j, double r2, double* u, double* du) {
+    const orc_ss* t = s->ss;
+    double sg = 0.5 * (t->sigma_ss[i] + t->sigma_ss[j]);
+    double ep = sqrt(t->eps_ss[i] * t->eps_ss[j]);
+    double r = sqrt(r2);
+    double sr6 = pow(sg / r, 6.0);
+    double kq = s->coulomb_k * s->q[i] * s->q[j] / s->eps_w;
+    u[0] = 4.0 * ep * (sr6 * sr6 - sr6);
+    u[1] = kq / r;
+    /* d/dr of 4 eps (sr^12 - sr^6) = 4 eps (-12 sr^12 + 6 sr^6) / r */
+    *du = (4.0 * ep * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r - kq / r2) / r;
+}
+
+/* LJ (out[0]) and Coulomb (out[1]) sums over non-excluded pairs i < j; the
+ * row sums of each i are added in index order. */
+void orc_nonbonded_energy(const orc_sys* s, double* out) {
+    const orc_ss* t = s->ss;
+    out[0] = out[1] = 0.0;
+    if (!t || !t->nonbonded) return;
+    int64_t na = s->na;
+    int64_t* keys = exclusion_keys(t, na);
+    double* row = calloc((size_t)(2 * na), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < na; ++i) {
+        for (int64_t j = i + 1; j < na; ++j) {
+            if (excluded(keys, t->nexcl, na, i, j)) continue;
+            double d[3], u[2], du;
+            sub3(s->xyz + 3 * i, s->xyz + 3 * j, d);
+            pair_terms(s, i, j, dot3(d, d), u, &du);
+            row[2 * i] += u[0];
+            row[2 * i + 1] += u[1];
+        }
+    }
+    for (int64_t i = 0; i < na; ++i) {
+        out[0] += row[2 * i];
+        out[1] += row[2 * i + 1];
+    }
+    free(row);
+    free(keys);
+}
+
+/* g (na x 3) += grad of the bending, torsion and non-bonded terms, as the
+ * Appendix writes them: for the bend, B (theta - theta0) grad theta with
+ *   grad_i theta = (cos theta q_ji / q_ji^2 - q_jk / (q_ji q_jk)) / sin theta,
+ *   grad_k theta = (cos theta q_jk / q_jk^2 - q_ji / (q_ji q_jk)) / sin theta,
+ *   grad_j theta = -(grad_i theta + grad_k theta)
+ * (the printed grad_k carries q_ji where the derivative has q_jk; the
+ * printed grad_j equals the sum form used here); for the torsion,
+ *   dW/dLambda grad Lambda with dW/dLambda the polynomial in Lambda of the
+ *   Appendix (psi_n in {0, pi}) and grad Lambda from grad_{q1,q2,q3} Lambda;
+ * for the pairs, U'(r) (r_i - r_j)/r on i and its negative on j. */
+void orc_ss_gradient(const orc_sys* s, double* g) {
+    const orc_ss* t = s->ss;
+    if (!t) return;
+    const double* x = s->xyz;
+    for (int64_t a = 0; a < t->nang; ++a) {
+        const int32_t* id = t->ang + 3 * a;
+        double qji[3], qjk[3];
+        sub3(x + 3 * id[0], x + 3 * id[1], qji);
+        sub3(x + 3 * id[2], x + 3 * id[1], qjk);
+        double lji = sqrt(dot3(qji, qji)), ljk = sqrt(dot3(qjk, qjk));
+        double th = bend_angle(x + 3 * id[0], x + 3 * id[1], x + 3 * id[2]);
+        double c = cos(th), sn = sin(th);
+        double pre = t->kang[a] * (th - t->theta0[a]) / sn;
+        for (int d = 0; d < 3; ++d) {
+            double gi = pre * (c * qji[d] / (lji * lji) - qjk[d] / (lji * ljk));
+            double gk = pre * (c * qjk[d] / (ljk * ljk) - qji[d] / (lji * ljk));
+            g[3 * id[0] + d] += gi;
+            g[3 * id[2] + d] += gk;
+            g[3 * id[1] + d] -= gi + gk;
+        }
+    }
+    for (int64_t a = 0; a < t->ntor; ++a) {
+        const int32_t* id = t->tor + 4 * a;
+        double q1[3], q2[3], q3[3], u[3], v[3];
+        sub3(x + 3 * id[1], x + 3 * id[0], q1);
+        sub3(x + 3 * id[2], x + 3 * id[1], q2);
+        sub3(x + 3 * id[3], x + 3 * id[2], q3);
+        cross3(q1, q2, u);
+        cross3(q2, q3, v);
+        double uu = dot3(u, u), vv = dot3(v, v), uv = dot3(u, v);
+        double nu = sqrt(uu), nv = sqrt(vv);
+        double L = uv / (nu * nv);
+        double cp[7];
+        for (int n = 0; n <= 6; ++n) cp[n] = t->tc[7 * a + n] * cos(t->tpsi[7 * a + n]);
+        double dW = (cp[1] - 3.0 * cp[3] + 5.0 * cp[5]) +
+                    L * (4.0 * cp[2] - 16.0 * cp[4] + 36.0 * cp[6]) +
+                    L * L * (12.0 * cp[3] - 60.0 * cp[5]) +
+                    L * L * L * (32.0 * cp[4] - 192.0 * cp[6]) + L * L * L * L * (80.0 * cp[5]) +
+                    L * L * L * L * L * (192.0 * cp[6]);
+        double q2v[3], q2u[3], q1v[3], q1u[3], q3u[3], q3v[3];
+        cross3(q2, v, q2v);
+        cross3(q2, u, q2u);
+        cross3(q1, v, q1v);
+        cross3(q1, u, q1u);
+        cross3(q3, u, q3u);
+        cross3(q3, v, q3v);
+        double uuu = uu * nu * nv, vvv = nu * vv * nv;
+        for (int d = 0; d < 3; ++d) {
+            double g1 = (q2v[d] * uu - uv * q2u[d]) / uuu;
+            double g2 = (-q1v[d] * uu + uv * q1u[d]) / uuu + (q3u[d] * vv - uv * q3v[d]) / vvv;
+            double g3 = (-q2u[d] * vv + uv * q2v[d]) / vvv;
+            g[3 * id[0] + d] += dW * (-g1);
+            g[3 * id[1] + d] += dW * (g1 - g2);
+            g[3 * id[2] + d] += dW * (g2 - g3);
+            g[3 * id[3] + d] += dW * g3;
+        }
+    }
+    if (t->nonbonded) {
+        int64_t na = s->na;
+        int64_t* keys = exclusion_keys(t, na);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < na; ++i) {
+            double gi[3] = {0.0, 0.0, 0.0};
+            for (int64_t j = 0; j < na; ++j) {
+                if (j == i || excluded(keys, t->nexcl, na, i, j)) continue;
+                double d[3], u[2], du;
+                sub3(x + 3 * i, x + 3 * j, d);
+                pair_terms(s, i, j, dot3(d, d), u, &du);
+                for (int k = 0; k < 3; ++k) gi[k] += du * d[k];
+            }
+            for (int k = 0; k < 3; ++k) g[3 * i + k] += gi[k];
+        }
+        free(keys);
+    }
+}
+
+/* Energies of the terms above: out = {bend, torsion, LJ, Coulomb}. */
+void orc_ss_energy(const orc_sys* s, double* out) {
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (!s->ss) return;
+    out[0] = orc_bend_energy(s->ss, s->xyz);
+    out[1] = orc_torsion_energy(s->ss, s->xyz);
+    orc_nonbonded_energy(s, out + 2);
 }
 
 /* ---------------------------------------------------------------- flips */
@@ -666,6 +924,12 @@ void orc_forces(const orc_sys* s, const int8_t* phi, int64_t nb, const int32_t* 
         f[3 * i + 0] -= c * dx; f[3 * i + 1] -= c * dy; f[3 * i + 2] -= c * dz;
         f[3 * j + 0] += c * dx; f[3 * j + 1] += c * dy; f[3 * j + 2] += c * dz;
     }
+    if (s->ss) {
+        double* g = calloc((size_t)(3 * s->na), sizeof(double));
+        orc_ss_gradient(s, g);
+        for (int64_t k = 0; k < 3 * s->na; ++k) f[k] -= g[k];
+        free(g);
+    }
     free(pts); free(w); free(e); free(tmp);
 }
 
@@ -685,6 +949,8 @@ void orc_forces_subset(const orc_sys* s, const int8_t* phi, const double* efield
     double* tmp = malloc(sizeof(double) * 2 * (size_t)nfar);
     orc_far_nodes(s, fpts, fw);
     orc_density_points(s, nfar, fpts, tmp, tmp + nfar, fe);
+    double* gss = calloc((size_t)(3 * s->na), sizeof(double));
+    orc_ss_gradient(s, gss);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nsel; ++t) {
         int64_t a = sel[t];
@@ -714,15 +980,16 @@ void orc_forces_subset(const orc_sys* s, const int8_t* phi, const double* efield
             double c = kb[b] * (r - r0[b]) / r * (i == a ? 1.0 : -1.0);
             gx += c * dx; gy += c * dy; gz += c * dz;
         }
-        f[3 * t + 0] = -gx;
-        f[3 * t + 1] = -gy;
-        f[3 * t + 2] = -gz;
+        f[3 * t + 0] = -gx - gss[3 * a];
+        f[3 * t + 1] = -gy - gss[3 * a + 1];
+        f[3 * t + 2] = -gz - gss[3 * a + 2];
     }
-    free(fpts); free(fw); free(fe); free(tmp);
+    free(fpts); free(fw); free(fe); free(tmp); free(gss);
 }
 
-/* Total free energy at fixed labels: discrete VISM energy + bonds.
- * comps (optional) = {geom, vdw_in, vdw_far, elec_in, elec_far, bond, total}. */
+/* Total free energy at fixed labels: discrete VISM energy + bonds + the
+ * solute-solute terms of s->ss.  comps (optional) = {geom, vdw_in, vdw_far,
+ * elec_in, elec_far, bond, bend, torsion, vdw_ss, elec_ss, total}. */
 double orc_total_energy(const orc_sys* s, const int8_t* phi, int64_t nb, const int32_t* ij,
                         const double* r0, const double* kb, double* comps) {
     int64_t ncell = (int64_t)s->n * s->n * s->n;
@@ -733,14 +1000,18 @@ double orc_total_energy(const orc_sys* s, const int8_t* phi, int64_t nb, const i
     orc_far_field(s, far);
     orc_energy(s, phi, ulj, ucfa, far, e);
     double eb = orc_bond_energy(nb, ij, r0, kb, s->xyz);
+    double ess[4];
+    orc_ss_energy(s, ess);
+    double total = e[5] + eb + ess[0] + ess[1] + ess[2] + ess[3];
     if (comps) {
         for (int i = 0; i < 5; ++i) comps[i] = e[i];
         comps[5] = eb;
-        comps[6] = e[5] + eb;
+        for (int i = 0; i < 4; ++i) comps[6 + i] = ess[i];
+        comps[10] = total;
     }
     free(ulj);
     free(ucfa);
-    return e[5] + eb;
+    return total;
 }
 
 /* ------------------------------------------------------- adaptive mobility */

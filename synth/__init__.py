@@ -243,6 +243,58 @@ def chain_bonds(natoms: int, offset: int = 0, r0: float = 0.15, k: float = 1.0e5
     return ij.astype(np.int32), np.full(natoms - 1, r0), np.full(natoms - 1, k)
 
 
+@dataclass
+class Topology:
+    """Solute-solute terms beyond the bonds (Eq. "Gss"): bending triplets
+    (i, j, k; vertex j) with theta0 (rad) and B (kJ mol^-1 rad^-2), torsion
+    quadruples with C_0..C_6 (kJ/mol) and phases psi_0..psi_6 (0 or pi), and
+    the non-bonded pairs: every pair not listed in ``exclusions``, with
+    per-atom LJ parameters sigma_ss, eps_ss (None = the atoms' own)."""
+    angles: np.ndarray
+    theta0: np.ndarray
+    k_angle: np.ndarray
+    torsions: np.ndarray
+    c: np.ndarray
+    psi: np.ndarray
+    nonbonded: bool = True
+    sigma_ss: np.ndarray | None = None
+    eps_ss: np.ndarray | None = None
+    exclusions: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
+
+
+def chain_topology(chains, seed: int, nonbonded: bool = True, exclude: int = 2) -> Topology:
+    """Bending triplets (i, i+1, i+2) and torsion quadruples (i .. i+3) along
+    each chain (first atom, atom count) of ``chains``; theta0 ~ U[1.8, 2.0]
+    rad, B ~ U[300, 500], C_0 ~ U[0, 1], C_1..C_3 ~ U[0, 1.5], C_4..C_6 ~
+    U[0, 0.5]; psi_n = 0 for odd n and pi for even n (so that positive C_n
+    have their minimum in the trans position).  Pairs at most ``exclude``
+    bonds apart along a chain are excluded from the non-bonded terms."""
+    rng = SplitMix64(seed ^ 0x70B010)
+    ang, tor, exc = [], [], []
+    for first, count in chains:
+        idx = np.arange(first, first + count, dtype=np.int32)
+        if count >= 3:
+            ang.append(np.stack([idx[:-2], idx[1:-1], idx[2:]], axis=1))
+        if count >= 4:
+            tor.append(np.stack([idx[:-3], idx[1:-2], idx[2:-1], idx[3:]], axis=1))
+        for d in range(1, exclude + 1):
+            if count > d:
+                exc.append(np.stack([idx[:-d], idx[d:]], axis=1))
+    angles = np.concatenate(ang) if ang else np.zeros((0, 3), np.int32)
+    torsions = np.concatenate(tor) if tor else np.zeros((0, 4), np.int32)
+    na, nt = len(angles), len(torsions)
+    u = rng.uniform(2 * na).reshape(na, 2) if na else np.zeros((0, 2))
+    theta0 = 1.8 + 0.2 * u[:, 0]
+    k_angle = 300.0 + 200.0 * u[:, 1]
+    scale = np.array([1.0, 1.5, 1.5, 1.5, 0.5, 0.5, 0.5])
+    c = (rng.uniform(7 * nt).reshape(nt, 7) * scale) if nt else np.zeros((0, 7))
+    psi = np.tile(np.array([math.pi if n % 2 == 0 else 0.0 for n in range(7)]), (nt, 1))
+    excl = np.concatenate(exc).astype(np.int32) if exc else np.zeros((0, 2), np.int32)
+    return Topology(angles=angles.astype(np.int32), theta0=theta0, k_angle=k_angle,
+                    torsions=torsions.astype(np.int32), c=c, psi=psi, nonbonded=nonbonded,
+                    exclusions=excl)
+
+
 # ---------------------------------------------------------------- workloads
 
 def single_atom(n: int = 64) -> Workload:

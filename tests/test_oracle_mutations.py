@@ -55,6 +55,35 @@ MUTATIONS = [
     ("relax_skips_interface",
      "        orc_minimize_colour(&s, phi, u, o->max_sweeps, 0.0, stats, NULL, NULL, 0);\n", "",
      "test_paper_two_atom_relaxation_reaches_printed_state"),
+    ("bend_half_missing", "e += 0.5 * t->kang[a] * (th - t->theta0[a])",
+     "e += t->kang[a] * (th - t->theta0[a])", "test_oracle_solute.py::test_bend_energy_closed_form"),
+    ("bend_grad_k_as_printed",
+     "double gk = pre * (c * qjk[d] / (ljk * ljk) - qji[d] / (lji * ljk));",
+     "double gk = pre * (c * qji[d] / (ljk * ljk) - qji[d] / (lji * ljk));",
+     "test_oracle_solute.py::test_ss_forces_match_central_differences"),
+    ("torsion_plane_orientation", "    cross3(q2, q3, v);\n    double c = dot3(u, v)",
+     "    cross3(q3, q2, v);\n    double c = dot3(u, v)",
+     "test_oracle_solute.py::test_torsion_energy_closed_form"),
+    ("torsion_poly_sign", "double dW = (cp[1] - 3.0 * cp[3] + 5.0 * cp[5])",
+     "double dW = (cp[1] + 3.0 * cp[3] + 5.0 * cp[5])",
+     "test_oracle_solute.py::test_ss_forces_match_central_differences"),
+    ("torsion_grad_j_sign", "g[3 * id[1] + d] += dW * (g1 - g2);",
+     "g[3 * id[1] + d] += dW * (g2 - g1);",
+     "test_oracle_solute.py::test_ss_forces_are_internal"),
+    ("lj_mixing_geometric", "double sg = 0.5 * (t->sigma_ss[i] + t->sigma_ss[j]);",
+     "double sg = sqrt(t->sigma_ss[i] * t->sigma_ss[j]);",
+     "test_oracle_solute.py::test_nonbonded_pair_closed_forms"),
+    ("coulomb_solute_permittivity",
+     "double kq = s->coulomb_k * s->q[i] * s->q[j] / s->eps_w;",
+     "double kq = s->coulomb_k * s->q[i] * s->q[j] / s->eps_m;",
+     "test_oracle_solute.py::test_nonbonded_pair_closed_forms"),
+    ("exclusions_ignored", "            if (excluded(keys, t->nexcl, na, i, j)) continue;\n", "",
+     "test_oracle_solute.py::test_exclusions_remove_exactly_the_listed_pairs"),
+    ("pair_force_drops_coulomb", "*du = (4.0 * ep * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r - kq / r2) / r;",
+     "*du = (4.0 * ep * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r) / r;",
+     "test_oracle_solute.py::test_ss_forces_match_central_differences"),
+    ("total_forces_skip_solute", "        for (int64_t k = 0; k < 3 * s->na; ++k) f[k] -= g[k];\n", "",
+     "test_oracle_solute.py::test_total_forces_include_the_solute_terms"),
 ]
 
 
@@ -69,6 +98,7 @@ def test_pin_catches_planted_mistake(name, old, new, pin, tmp_path):
     lib = ob.build(src=str(mutated), lib=str(tmp_path / "liboracle_mut.so"))
     env = dict(os.environ, VESIS_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        f"tests/test_oracle_pins.py::{pin}"], cwd=ROOT, env=env,
+                        f"tests/{pin}" if "::" in pin else f"tests/test_oracle_pins.py::{pin}"],
+                       cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 1, f"{pin} did not catch {name}:\n{r.stdout[-2000:]}"
