@@ -144,6 +144,36 @@ def batch_comparison(rounds: int = 2):
     return out
 
 
+def solute_solute(w, reps: int = 5):
+    """The solute-solute terms of Eq. "Gss" beyond bonds (bending, torsion,
+    non-bonded LJ + Coulomb) on the same atoms with chain topology: device
+    time of their kernels per evaluation (HIP events), and the energies."""
+    import torch
+
+    import synth
+    from paper_2208_05524_amd import Context
+    half = w.natoms // 2
+    top = synth.chain_topology([(0, half), (half, w.natoms - half)], seed=3070)
+    ctx = Context(0)
+    ctx.setup(w, precision=32, with_bonds=True, topology=top)
+    ctx.init_labels("tight", 1.0)
+    xyz = torch.tensor(w.xyz, dtype=torch.float64, device="cuda").contiguous()
+    ctx.energy()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.set_positions(xyz)
+        e = ctx.energy()
+        ctx.forces()
+    ms, n = ctx.profile_read("solute")
+    ctx.profile(False)
+    ctx.close()
+    pairs = w.natoms * (w.natoms - 1) // 2 - len(top.exclusions)
+    per = ms / max(n, 1)
+    return {"angles": len(top.angles), "torsions": len(top.torsions), "pairs": pairs,
+            "ms_per_eval": per, "pairs_per_s": pairs / (per / 1000.0),
+            "energy": {k: e[k] for k in ("bond", "bend", "torsion", "vdw_ss", "elec_ss")}}
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """Oracle density (FP64, OpenMP) over whole z-planes of the same grid
     until about budget_s seconds of work; returns atom-gridpoint pairs/s."""
@@ -307,6 +337,9 @@ def main():
         "atom_step": {"accepted": last["accepted"], "retries": last["retries"]},
         "G_total": last["e"]["total"],
     }
+    log("solute-solute terms ...")
+    out["solute_solute"] = solute_solute(w)
+    log(f"solute_solute: {out['solute_solute']}")
     if not args.no_batch:
         log("batch comparison ...")
         out["batch"] = batch_comparison()

@@ -83,11 +83,13 @@ typedef struct {
     int32_t reserved;
 } vesis_params;
 
-/* Energy parts of Eq. "4flip" plus the harmonic bond term of Eq. "Gss":
+/* Energy parts of Eq. "4flip" plus the solute-solute terms of Eq. "Gss":
  * geom = surface energy, *_in = h^3 sum over solvent cells, *_far = integral
- * over R^3 outside the box. */
+ * over R^3 outside the box; bond, bend (bending), torsion, vdw_ss and
+ * elec_ss (non-bonded LJ and Coulomb) are 0 when not set; total = their
+ * sum. */
 typedef struct {
-    double geom, vdw_in, vdw_far, elec_in, elec_far, bond, total;
+    double geom, vdw_in, vdw_far, elec_in, elec_far, bond, bend, torsion, vdw_ss, elec_ss, total;
 } vesis_energy_parts;
 
 /* Interface minimisation report.  sweeps counts colour sweeps run, the last
@@ -161,7 +163,38 @@ vesis_status vesis_get_positions(vesis_ctx* ctx, double* xyz);
 vesis_status vesis_set_bonds(vesis_ctx* ctx, int64_t nb, const int32_t* ij, const double* r0,
                              const double* k);
 
-/* Bytes of device workspace needed for the current grid, atoms and bonds. */
+/* Bending terms of Eq. "Gss", (1/2) B (theta_ijk - theta0)^2 with theta_ijk
+ * the angle at atom j between r_i - r_j and r_k - r_j: nang triplets ijk
+ * (nang x 3 atom indices, three different atoms), theta0 in [0, pi] (rad)
+ * and B = k.  The gradient is that of the Appendix; sin theta is floored at
+ * 1e-12 for collinear atoms.  nang = 0 removes them.  Like vesis_set_bonds,
+ * more terms than the workspace was planned for require vesis_set_workspace
+ * again (VESIS_E_WORKSPACE until then). */
+vesis_status vesis_set_angles(vesis_ctx* ctx, int64_t nang, const int32_t* ijk,
+                              const double* theta0, const double* k);
+
+/* Torsion terms of Eq. "Gss", sum_{n=0..6} C_n [1 + cos(n tau - psi_n)] per
+ * quadruple ijkl (ntor x 4 atom indices, four different atoms), tau in
+ * [0, pi] the angle between the planes (r_i, r_j, r_k) and (r_j, r_k, r_l)
+ * (Appendix: cos tau = u.v/(|u||v|), u = (r_j - r_i) x (r_k - r_j),
+ * v = (r_k - r_j) x (r_l - r_k)); c and psi are ntor x 7 (n = 0..6), every
+ * psi_n 0 or pi (the Appendix's gradient assumes so; VESIS_E_ARG
+ * otherwise).  ntor = 0 removes them. */
+vesis_status vesis_set_torsions(vesis_ctx* ctx, int64_t ntor, const int32_t* ijkl,
+                                const double* c, const double* psi);
+
+/* Non-bonded solute-solute terms of Eq. "Gss" over every pair of atoms not
+ * listed in excl (nexcl x 2 atom indices, any order, duplicates allowed):
+ * 4 eps_ij [(sigma_ij/r)^12 - (sigma_ij/r)^6] with sigma_ij = (sigma_i +
+ * sigma_j)/2, eps_ij = sqrt(eps_i eps_j) from sigma_ss, eps_ss (n values
+ * each; NULL = the atoms' sigma and eps of vesis_set_atoms), plus
+ * coulomb_k Q_i Q_j / (eps_w r).  enable = 0 turns them off.  Coincident
+ * non-excluded atoms give a non-finite energy. */
+vesis_status vesis_set_nonbonded(vesis_ctx* ctx, int32_t enable, const double* sigma_ss,
+                                 const double* eps_ss, int64_t nexcl, const int32_t* excl);
+
+/* Bytes of device workspace needed for the current grid, atoms, bonds and
+ * solute-solute terms. */
 vesis_status vesis_workspace_size(vesis_ctx* ctx, size_t* bytes);
 
 /* Hand the context a device buffer of `bytes` bytes (256-byte aligned),
@@ -186,12 +219,13 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
 vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out);
 
 /* Discrete free energy of the current labels and atoms (Eq. "4flip" plus
- * bonds). */
+ * the solute-solute terms that are set). */
 vesis_status vesis_energy(vesis_ctx* ctx, vesis_energy_parts* out);
 
 /* Forces F_n = -grad_{r_n} G at fixed labels (solvent and far-field terms of
  * the Appendix gradient, taken as the exact derivative of the discrete
- * energy, plus bonds), written to f_out (n x 3 host array). */
+ * energy, plus the solute-solute terms that are set), written to f_out
+ * (n x 3 host array). */
 vesis_status vesis_forces(vesis_ctx* ctx, double* f_out);
 
 /* One adaptive-mobility step at fixed labels (Steps 3.1-3.4): gradient at
@@ -288,7 +322,7 @@ vesis_status vesis_profile(vesis_ctx* ctx, int32_t enable);
 /* Accumulated device time (ms) and launch count of kernel kind `kind`
  * since profiling was enabled: 0 density (grid), 1 far-field density,
  * 2 initial labels, 3 flip passes, 4 energy reductions, 5 force adjoint,
- * 6 other.  Synchronises the stream. */
+ * 6 other, 7 solute-solute terms.  Synchronises the stream. */
 vesis_status vesis_profile_read(vesis_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus

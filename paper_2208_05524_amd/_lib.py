@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "VESIS_OK", 1: "VESIS_NOT_CONVERGED", -1: "VESIS_E_ARG", -2: 
 
 EXPORTS = ["vesis_create", "vesis_destroy", "vesis_last_error", "vesis_set_params",
            "vesis_set_grid", "vesis_set_atoms", "vesis_set_positions", "vesis_get_positions",
-           "vesis_set_bonds", "vesis_workspace_size", "vesis_set_workspace", "vesis_init_labels",
+           "vesis_set_bonds", "vesis_set_angles", "vesis_set_torsions", "vesis_set_nonbonded",
+           "vesis_workspace_size", "vesis_set_workspace", "vesis_init_labels",
            "vesis_init_labels_logits",
            "vesis_minimize_interface", "vesis_energy", "vesis_forces", "vesis_atom_step",
            "vesis_relax", "vesis_batch_workspace_size", "vesis_batch_tune", "vesis_minimize_batch",
@@ -36,7 +37,8 @@ class Params(C.Structure):
 
 class EnergyParts(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("geom", "vdw_in", "vdw_far", "elec_in", "elec_far", "bond", "total")]
+                ("geom", "vdw_in", "vdw_far", "elec_in", "elec_far", "bond", "bend", "torsion",
+                 "vdw_ss", "elec_ss", "total")]
 
 
 class MinStats(C.Structure):
@@ -100,6 +102,9 @@ def load():
     L.vesis_set_positions.argtypes = [P, P, I32]
     L.vesis_get_positions.argtypes = [P, P]
     L.vesis_set_bonds.argtypes = [P, I64, P, P, P]
+    L.vesis_set_angles.argtypes = [P, I64, P, P, P]
+    L.vesis_set_torsions.argtypes = [P, I64, P, P, P]
+    L.vesis_set_nonbonded.argtypes = [P, C.c_int32, P, P, I64, P]
     L.vesis_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
     L.vesis_set_workspace.argtypes = [P, P, C.c_size_t]
     L.vesis_init_labels.argtypes = [P, I32, D, P]

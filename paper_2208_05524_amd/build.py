@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvesis.so")
-SOURCES = ["api.hip", "density.hip", "labels.hip", "forces.hip", "nn.hip"]
+SOURCES = ["api.hip", "density.hip", "labels.hip", "forces.hip", "solute.hip", "nn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

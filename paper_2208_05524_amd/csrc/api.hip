@@ -11,6 +11,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <algorithm>
 
 #include "../../include/vesis.h"
 #include "internal.h"
@@ -68,6 +69,9 @@ struct Layout {
     size_t far_pts, far_ulj, far_ucfa, far_ex, far_ey, far_ez, far_part;
     size_t red_d, red_i, scal_d, scal_i, sweep_flips;
     size_t fpart, fstage, fcount, fout;
+    size_t s_ang, s_angp, s_tor, s_torp, s_slot, s_incoff, s_incslot, s_nbp, s_xoff, s_xother;
+    size_t s_part, s_grad, s_eatom, s_red;
+    int s_nsplit;
     size_t total;
     ForceSizes fsz;
 };
@@ -103,6 +107,16 @@ struct vesis_ctx {
     int64_t nb = 0;
     std::vector<int32_t> b_off, b_other;
     std::vector<double> b_r0, b_k;
+    // solute-solute terms beyond bonds (bending, torsion, non-bonded pairs)
+    int64_t nang = 0, ntor = 0;
+    std::vector<int32_t> ang;      // 4 per angle: i, j, k, 0
+    std::vector<double> ang_prm;   // theta0, B
+    std::vector<int32_t> tor;      // 4 per torsion
+    std::vector<double> tor_prm;   // 8 per torsion: a0, K_1 .. K_6, 0
+    std::vector<int32_t> inc_off, inc_slot;
+    bool nonbonded = false;
+    std::vector<double> sig_ss, eps_ss;  // empty: the atoms' sigma and eps
+    std::vector<int32_t> x_off, x_other;
     std::vector<double> far_host;  // x, y, z, w per node
     int64_t nfar = 0;
 
@@ -111,12 +125,16 @@ struct vesis_ctx {
     bool has_ws = false;
     Layout lay{};
     int64_t lay_na = -1, lay_nb = -1, lay_nfar = -1;
+    int64_t lay_nang = 0, lay_ntor = 0, lay_nxo = 0;
+    bool lay_nonbonded = false;
     int lay_n = -1;
 
     bool has_labels = false;
     bool atoms_uploaded = false;
     bool far_uploaded = false;
     bool bonds_uploaded = false;
+    bool ss_uploaded = false;
+    bool ss_valid = false;       // solute-solute energies and gradient are current
     bool dens_valid = false;
     bool forces_valid = false;
 
@@ -308,12 +326,28 @@ Layout plan(const vesis_ctx* c) {
     L.fstage = take(L.fsz.staged_bytes);
     L.fcount = take(4 * (size_t)L.fsz.counts);
     L.fout = take(8 * 3 * na);
+    const int64_t nslot = 3 * c->nang + 4 * c->ntor;
+    L.s_ang = take(16 * c->nang);
+    L.s_angp = take(16 * c->nang);
+    L.s_tor = take(16 * c->ntor);
+    L.s_torp = take(64 * c->ntor);
+    L.s_slot = take(24 * nslot);
+    L.s_incoff = take(4 * (na + 1));
+    L.s_incslot = take(4 * nslot);
+    L.s_nbp = take(32 * na);
+    L.s_xoff = take(4 * (na + 1));
+    L.s_xother = take(4 * c->x_other.size());
+    L.s_nsplit = solute_splits(na);
+    L.s_part = take(c->nonbonded ? 40 * (size_t)L.s_nsplit * na : 0);
+    L.s_grad = take(24 * na);
+    L.s_eatom = take(16 * na);
+    L.s_red = take(8 * 4 * RED_BLOCKS);
     L.total = o;
     return L;
 }
 
 // scalar slots
-enum { SD_VOL = 0, SD_FAR = 2, SD_BOND = 4 };
+enum { SD_VOL = 0, SD_FAR = 2, SD_BOND = 4, SD_SS = 8 };
 enum { SI_GEOM = 0, SI_BAND = 8, SI_CNT = 10 };
 
 vesis_status need(vesis_ctx* ctx, bool labels) {
@@ -368,6 +402,36 @@ vesis_status upload_inputs(vesis_ctx* ctx) {
             CK(hipStreamSynchronize(st));
         }
         ctx->bonds_uploaded = true;
+    }
+    if (!ctx->ss_uploaded) {
+        const Layout& L = ctx->lay;
+        const int64_t n = ctx->na;
+        auto up = [&](size_t off, const void* src, size_t bytes) {
+            return bytes ? hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, st)
+                         : hipSuccess;
+        };
+        std::vector<double> nbp(4 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            const double sg = ctx->sig_ss.empty() ? ctx->sigma[i] : ctx->sig_ss[i];
+            const double ep = ctx->eps_ss.empty() ? ctx->eps[i] : ctx->eps_ss[i];
+            nbp[4 * i + 0] = 0.5 * sg;
+            nbp[4 * i + 1] = std::sqrt(ep);
+            nbp[4 * i + 2] = ctx->q[i];
+            nbp[4 * i + 3] = 0.0;
+        }
+        if (ctx->inc_off.size() != (size_t)(n + 1)) ctx->inc_off.assign(n + 1, 0);
+        if (ctx->x_off.size() != (size_t)(n + 1)) ctx->x_off.assign(n + 1, 0);
+        CK(up(L.s_ang, ctx->ang.data(), 16 * ctx->nang));
+        CK(up(L.s_angp, ctx->ang_prm.data(), 16 * ctx->nang));
+        CK(up(L.s_tor, ctx->tor.data(), 16 * ctx->ntor));
+        CK(up(L.s_torp, ctx->tor_prm.data(), 64 * ctx->ntor));
+        CK(up(L.s_incoff, ctx->inc_off.data(), 4 * (n + 1)));
+        CK(up(L.s_incslot, ctx->inc_slot.data(), 4 * ctx->inc_slot.size()));
+        CK(up(L.s_nbp, nbp.data(), 32 * n));
+        CK(up(L.s_xoff, ctx->x_off.data(), 4 * (n + 1)));
+        CK(up(L.s_xother, ctx->x_other.data(), 4 * ctx->x_other.size()));
+        CK(hipStreamSynchronize(st));
+        ctx->ss_uploaded = true;
     }
     if (!ctx->far_uploaded) {
         CK(hipMemcpyAsync(ctx->ws + ctx->lay.far_pts, ctx->far_host.data(), 32 * ctx->nfar,
@@ -435,8 +499,49 @@ vesis_status density_tail(vesis_ctx* ctx) {
     return VESIS_OK;
 }
 
+bool has_solute_terms(const vesis_ctx* c) { return c->nang > 0 || c->ntor > 0 || c->nonbonded; }
+
+// Bending, torsion and non-bonded energies (scalar slots SD_SS..SD_SS+3)
+// and their gradient (s_grad) at the current positions.
+vesis_status ensure_solute(vesis_ctx* ctx) {
+    if (!has_solute_terms(ctx) || ctx->ss_valid) return VESIS_OK;
+    vesis_status s = upload_inputs(ctx);
+    if (s != VESIS_OK) return s;
+    const Layout& L = ctx->lay;
+    Solute so;
+    so.n = ctx->na;
+    so.pos = at<double4>(ctx, L.pos);
+    so.nang = ctx->nang;
+    so.ang = at<int4>(ctx, L.s_ang);
+    so.ang_prm = at<double2>(ctx, L.s_angp);
+    so.ntor = ctx->ntor;
+    so.tor = at<int4>(ctx, L.s_tor);
+    so.tor_prm = at<double>(ctx, L.s_torp);
+    so.slot = at<double>(ctx, L.s_slot);
+    so.inc_off = at<int32_t>(ctx, L.s_incoff);
+    so.inc_slot = at<int32_t>(ctx, L.s_incslot);
+    so.nonbonded = ctx->nonbonded ? 1 : 0;
+    so.nsplit = L.s_nsplit;
+    so.nb_prm = at<double4>(ctx, L.s_nbp);
+    so.x_off = at<int32_t>(ctx, L.s_xoff);
+    so.x_other = at<int32_t>(ctx, L.s_xother);
+    so.kcoul = ctx->prm.coulomb_k / ctx->prm.eps_w;
+    so.pair_part = at<double>(ctx, L.s_part);
+    so.grad = at<double>(ctx, L.s_grad);
+    so.eatom = at<double>(ctx, L.s_eatom);
+    {
+        Timed t(ctx, K_SOLUTE);
+        CK(launch_solute(so, at<double>(ctx, L.s_red), RED_BLOCKS,
+                         at<double>(ctx, L.scal_d) + SD_SS, ctx->stream));
+    }
+    ctx->ss_valid = true;
+    return VESIS_OK;
+}
+
 vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     vesis_status s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    s = ensure_solute(ctx);
     if (s != VESIS_OK) return s;
     hipStream_t st = ctx->stream;
     const uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
@@ -451,7 +556,7 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
             CK(launch_bond_energy(dev_atoms(ctx), dev_bonds(ctx), at<double>(ctx, ctx->lay.red_d),
                                   RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_BOND, st));
     }
-    double sd[8];
+    double sd[16];
     int64_t si[16];
     CK(hipMemcpyAsync(sd, ctx->ws + ctx->lay.scal_d, sizeof(sd), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(si, ctx->ws + ctx->lay.scal_i, sizeof(si), hipMemcpyDeviceToHost, st));
@@ -465,7 +570,13 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     out->vdw_far = sd[SD_FAR];
     out->elec_far = sd[SD_FAR + 1];
     out->bond = ctx->nb > 0 ? sd[SD_BOND] : 0.0;
-    out->total = out->geom + out->vdw_in + out->vdw_far + out->elec_in + out->elec_far + out->bond;
+    const bool ss = has_solute_terms(ctx);
+    out->bend = ss ? sd[SD_SS] : 0.0;
+    out->torsion = ss ? sd[SD_SS + 1] : 0.0;
+    out->vdw_ss = ss ? sd[SD_SS + 2] : 0.0;
+    out->elec_ss = ss ? sd[SD_SS + 3] : 0.0;
+    out->total = out->geom + out->vdw_in + out->vdw_far + out->elec_in + out->elec_far + out->bond +
+                 out->bend + out->torsion + out->vdw_ss + out->elec_ss;
     return VESIS_OK;
 }
 
@@ -478,6 +589,8 @@ ForceScratch force_scratch(vesis_ctx* ctx) {
 vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
     vesis_status s = ensure_density(ctx);
     if (s != VESIS_OK) return s;
+    s = ensure_solute(ctx);
+    if (s != VESIS_OK) return s;
     hipStream_t st = ctx->stream;
     const Physics ph = dev_physics(ctx);
     if (!ctx->forces_valid) {
@@ -487,8 +600,9 @@ vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
                          at<double>(ctx, ctx->lay.ey), at<double>(ctx, ctx->lay.ez),
                          at<double4>(ctx, ctx->lay.far_pts), at<double>(ctx, ctx->lay.far_ex),
                          at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
-                         ctx->nfar, dev_bonds(ctx), force_scratch(ctx),
-                         at<double>(ctx, ctx->lay.fout), st));
+                         ctx->nfar, dev_bonds(ctx),
+                         has_solute_terms(ctx) ? at<double>(ctx, ctx->lay.s_grad) : nullptr,
+                         force_scratch(ctx), at<double>(ctx, ctx->lay.fout), st));
         ctx->forces_valid = true;
     }
     CK(hipMemcpyAsync(f_host, ctx->ws + ctx->lay.fout, 24 * ctx->na, hipMemcpyDeviceToHost, st));
@@ -509,6 +623,7 @@ vesis_status put_positions(vesis_ctx* ctx, const double* xyz) {
                       ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->dens_valid = false;
+    ctx->ss_valid = false;
     ctx->forces_valid = false;
     return VESIS_OK;
 }
@@ -518,6 +633,44 @@ bool inside_box(const vesis_ctx* c, const double* xyz, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
         for (int d = 0; d < 3; ++d)
             if (!(std::fabs(xyz[3 * i + d] - ctr[d]) < c->g.L)) return false;
+    return true;
+}
+
+// Per-atom list of the gradient rows of the bending and torsion terms, in
+// term order (angle rows first).
+void rebuild_incidence(vesis_ctx* c) {
+    const int64_t n = c->na;
+    std::vector<int32_t> deg(n + 1, 0);
+    for (int64_t t = 0; t < c->nang; ++t)
+        for (int r = 0; r < 3; ++r) deg[c->ang[4 * t + r]]++;
+    for (int64_t t = 0; t < c->ntor; ++t)
+        for (int r = 0; r < 4; ++r) deg[c->tor[4 * t + r]]++;
+    c->inc_off.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) c->inc_off[i + 1] = c->inc_off[i] + deg[i];
+    std::vector<int32_t> fill(c->inc_off.begin(), c->inc_off.end() - 1);
+    c->inc_slot.assign(c->inc_off[n], 0);
+    for (int64_t t = 0; t < c->nang; ++t)
+        for (int r = 0; r < 3; ++r) c->inc_slot[fill[c->ang[4 * t + r]]++] = (int32_t)(3 * t + r);
+    for (int64_t t = 0; t < c->ntor; ++t)
+        for (int r = 0; r < 4; ++r)
+            c->inc_slot[fill[c->tor[4 * t + r]]++] = (int32_t)(3 * c->nang + 4 * t + r);
+}
+
+// The workspace stays usable while every solute-solute array fits the
+// layout it was planned for.
+void check_solute_layout(vesis_ctx* c) {
+    if (c->nang > c->lay_nang || c->ntor > c->lay_ntor ||
+        (int64_t)c->x_other.size() > c->lay_nxo || (c->nonbonded && !c->lay_nonbonded))
+        c->has_ws = false;
+    c->ss_uploaded = false;
+    c->ss_valid = false;
+    c->forces_valid = false;
+}
+
+bool distinct(const int32_t* id, int m) {
+    for (int a = 0; a < m; ++a)
+        for (int b = a + 1; b < m; ++b)
+            if (id[a] == id[b]) return false;
     return true;
 }
 
@@ -571,6 +724,7 @@ vesis_status vesis_set_params(vesis_ctx* ctx, const vesis_params* p) {
     ctx->prm = *p;
     ctx->has_params = true;
     ctx->dens_valid = false;
+    ctx->ss_valid = false;
     ctx->forces_valid = false;
     if (rho_changed) ctx->atoms_uploaded = false;
     if (ctx->has_grid) {
@@ -609,6 +763,7 @@ vesis_status vesis_set_grid(vesis_ctx* ctx, int32_t n, const double center[3], d
     ctx->has_ws = false;
     ctx->has_labels = false;
     ctx->dens_valid = false;
+    ctx->ss_valid = false;
     ctx->forces_valid = false;
     if (ctx->has_atoms && !inside_box(ctx, ctx->xyz.data(), ctx->na)) {
         ctx->has_atoms = false;
@@ -634,6 +789,18 @@ vesis_status vesis_set_atoms(vesis_ctx* ctx, int64_t n, const double* xyz, const
         ctx->b_other.clear();
         ctx->b_r0.clear();
         ctx->b_k.clear();
+        ctx->nang = ctx->ntor = 0;
+        ctx->ang.clear();
+        ctx->ang_prm.clear();
+        ctx->tor.clear();
+        ctx->tor_prm.clear();
+        ctx->inc_off.assign(n + 1, 0);
+        ctx->inc_slot.clear();
+        ctx->nonbonded = false;
+        ctx->sig_ss.clear();
+        ctx->eps_ss.clear();
+        ctx->x_off.assign(n + 1, 0);
+        ctx->x_other.clear();
     }
     ctx->na = n;
     ctx->xyz.assign(xyz, xyz + 3 * n);
@@ -647,7 +814,9 @@ vesis_status vesis_set_atoms(vesis_ctx* ctx, int64_t n, const double* xyz, const
     ctx->has_atoms = true;
     ctx->atoms_uploaded = false;
     ctx->bonds_uploaded = false;
+    ctx->ss_uploaded = false;
     ctx->dens_valid = false;
+    ctx->ss_valid = false;
     ctx->forces_valid = false;
     return VESIS_OK;
 }
@@ -668,7 +837,8 @@ vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_d
                           hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         ctx->dens_valid = false;
-    ctx->forces_valid = false;
+        ctx->ss_valid = false;
+        ctx->forces_valid = false;
         return VESIS_OK;
     }
     if (!finite_all(xyz, 3 * ctx->na)) return fail(ctx, VESIS_E_NONFINITE, "non-finite positions");
@@ -677,7 +847,8 @@ vesis_status vesis_set_positions(vesis_ctx* ctx, const double* xyz, int32_t on_d
         ctx->xyz.assign(xyz, xyz + 3 * ctx->na);
         ctx->atoms_uploaded = false;
         ctx->dens_valid = false;
-    ctx->forces_valid = false;
+        ctx->ss_valid = false;
+        ctx->forces_valid = false;
         return VESIS_OK;
     }
     return put_positions(ctx, xyz);
@@ -732,6 +903,110 @@ vesis_status vesis_set_bonds(vesis_ctx* ctx, int64_t nb, const int32_t* ij, cons
     return VESIS_OK;
 }
 
+vesis_status vesis_set_angles(vesis_ctx* ctx, int64_t nang, const int32_t* ijk,
+                              const double* theta0, const double* k) {
+    if (!ctx) return VESIS_E_ARG;
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    if (nang < 0 || nang > (1LL << 28) || (nang > 0 && (!ijk || !theta0 || !k)))
+        return fail(ctx, VESIS_E_ARG, "bad angle arrays");
+    if (nang > 0 && (!finite_all(theta0, nang) || !finite_all(k, nang)))
+        return fail(ctx, VESIS_E_NONFINITE, "non-finite angle data");
+    for (int64_t t = 0; t < nang; ++t) {
+        for (int r = 0; r < 3; ++r)
+            if (ijk[3 * t + r] < 0 || ijk[3 * t + r] >= ctx->na)
+                return fail(ctx, VESIS_E_ARG, "angle atom index out of range");
+        if (!distinct(ijk + 3 * t, 3)) return fail(ctx, VESIS_E_ARG, "angle atoms must differ");
+        if (theta0[t] < 0 || theta0[t] > PI)
+            return fail(ctx, VESIS_E_ARG, "theta0 must lie in [0, pi]");
+    }
+    ctx->nang = nang;
+    ctx->ang.assign(4 * nang, 0);
+    ctx->ang_prm.assign(2 * nang, 0.0);
+    for (int64_t t = 0; t < nang; ++t) {
+        for (int r = 0; r < 3; ++r) ctx->ang[4 * t + r] = ijk[3 * t + r];
+        ctx->ang_prm[2 * t] = theta0[t];
+        ctx->ang_prm[2 * t + 1] = k[t];
+    }
+    rebuild_incidence(ctx);
+    check_solute_layout(ctx);
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_torsions(vesis_ctx* ctx, int64_t ntor, const int32_t* ijkl,
+                                const double* c, const double* psi) {
+    if (!ctx) return VESIS_E_ARG;
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    if (ntor < 0 || ntor > (1LL << 28) || (ntor > 0 && (!ijkl || !c || !psi)))
+        return fail(ctx, VESIS_E_ARG, "bad torsion arrays");
+    if (ntor > 0 && (!finite_all(c, 7 * ntor) || !finite_all(psi, 7 * ntor)))
+        return fail(ctx, VESIS_E_NONFINITE, "non-finite torsion data");
+    std::vector<double> prm(8 * ntor, 0.0);
+    for (int64_t t = 0; t < ntor; ++t) {
+        for (int r = 0; r < 4; ++r)
+            if (ijkl[4 * t + r] < 0 || ijkl[4 * t + r] >= ctx->na)
+                return fail(ctx, VESIS_E_ARG, "torsion atom index out of range");
+        if (!distinct(ijkl + 4 * t, 4)) return fail(ctx, VESIS_E_ARG, "torsion atoms must differ");
+        // C_n [1 + cos(n tau - psi_n)] = C_n + C_n cos(psi_n) T_n(cos tau) when sin psi_n = 0
+        double a0 = 0.0;
+        for (int m = 0; m <= 6; ++m) {
+            const double ps = psi[7 * t + m];
+            if (std::fabs(std::sin(ps)) > 1e-9)
+                return fail(ctx, VESIS_E_ARG, "every psi_n must be 0 or pi");
+            const double cp = std::cos(ps) > 0 ? 1.0 : -1.0;
+            const double cn = c[7 * t + m];
+            a0 += cn;
+            if (m == 0)
+                a0 += cn * cp;
+            else
+                prm[8 * t + m] = cn * cp;
+        }
+        prm[8 * t] = a0;
+    }
+    ctx->ntor = ntor;
+    ctx->tor.assign(ijkl, ijkl + 4 * ntor);
+    ctx->tor_prm = prm;
+    rebuild_incidence(ctx);
+    check_solute_layout(ctx);
+    return VESIS_OK;
+}
+
+vesis_status vesis_set_nonbonded(vesis_ctx* ctx, int32_t enable, const double* sigma_ss,
+                                 const double* eps_ss, int64_t nexcl, const int32_t* excl) {
+    if (!ctx) return VESIS_E_ARG;
+    if (!ctx->has_atoms) return fail(ctx, VESIS_E_STATE, "atoms not set");
+    const int64_t n = ctx->na;
+    if (nexcl < 0 || nexcl > (1LL << 28) || (nexcl > 0 && !excl))
+        return fail(ctx, VESIS_E_ARG, "bad exclusion arrays");
+    if ((sigma_ss && !finite_all(sigma_ss, n)) || (eps_ss && !finite_all(eps_ss, n)))
+        return fail(ctx, VESIS_E_NONFINITE, "non-finite solute-solute LJ parameters");
+    for (int64_t i = 0; i < n; ++i)
+        if ((sigma_ss && !(sigma_ss[i] > 0)) || (eps_ss && eps_ss[i] < 0))
+            return fail(ctx, VESIS_E_ARG, "sigma_ss > 0, eps_ss >= 0 required");
+    for (int64_t e = 0; e < nexcl; ++e) {
+        const int32_t i = excl[2 * e], j = excl[2 * e + 1];
+        if (i < 0 || j < 0 || i >= n || j >= n || i == j)
+            return fail(ctx, VESIS_E_ARG, "exclusion atom index out of range");
+    }
+    std::vector<std::vector<int32_t>> part(n);
+    for (int64_t e = 0; e < nexcl; ++e) {
+        part[excl[2 * e]].push_back(excl[2 * e + 1]);
+        part[excl[2 * e + 1]].push_back(excl[2 * e]);
+    }
+    ctx->x_off.assign(n + 1, 0);
+    ctx->x_other.clear();
+    for (int64_t i = 0; i < n; ++i) {
+        std::sort(part[i].begin(), part[i].end());
+        part[i].erase(std::unique(part[i].begin(), part[i].end()), part[i].end());
+        ctx->x_other.insert(ctx->x_other.end(), part[i].begin(), part[i].end());
+        ctx->x_off[i + 1] = (int32_t)ctx->x_other.size();
+    }
+    ctx->nonbonded = enable != 0;
+    if (sigma_ss) ctx->sig_ss.assign(sigma_ss, sigma_ss + n); else ctx->sig_ss.clear();
+    if (eps_ss) ctx->eps_ss.assign(eps_ss, eps_ss + n); else ctx->eps_ss.clear();
+    check_solute_layout(ctx);
+    return VESIS_OK;
+}
+
 vesis_status vesis_workspace_size(vesis_ctx* ctx, size_t* bytes) {
     if (!ctx || !bytes) return fail(ctx, VESIS_E_ARG, "null argument");
     if (!ctx->has_params || !ctx->has_grid || !ctx->has_atoms)
@@ -756,13 +1031,19 @@ vesis_status vesis_set_workspace(vesis_ctx* ctx, void* device_ptr, size_t bytes)
     ctx->lay = L;
     ctx->lay_na = ctx->na;
     ctx->lay_nb = ctx->nb;
+    ctx->lay_nang = ctx->nang;
+    ctx->lay_ntor = ctx->ntor;
+    ctx->lay_nxo = (int64_t)ctx->x_other.size();
+    ctx->lay_nonbonded = ctx->nonbonded;
     ctx->lay_nfar = ctx->nfar;
     ctx->lay_n = ctx->g.n;
     ctx->has_ws = true;
     ctx->atoms_uploaded = false;
     ctx->bonds_uploaded = false;
     ctx->far_uploaded = false;
+    ctx->ss_uploaded = false;
     ctx->dens_valid = false;
+    ctx->ss_valid = false;
     ctx->forces_valid = false;
     if (!same) ctx->has_labels = false;
     return VESIS_OK;
@@ -1220,6 +1501,7 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
     // the densities now come from the last variant tried: recompute on use
     for (int i = 0; i < m; ++i) {
         ctxs[i]->dens_valid = false;
+        ctxs[i]->ss_valid = false;
         ctxs[i]->forces_valid = false;
     }
     return s;

@@ -333,12 +333,13 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     out[2] = gd[2] + kq * ge[2];
 }
 
-// F_n = -(sum over chunk groups of the partial gradients + bond gradient).
+// F_n = -(sum over chunk groups of the partial gradients + bond gradient +
+// g_extra[n], the gradient of the other solute-solute terms, when given).
 // Each of RSPLIT lanes per atom sums a fixed slice of the groups in order;
 // the slices are then added in slice order.
 __global__ __launch_bounds__(RATOMS * RSPLIT) void force_reduce_kernel(
     int64_t natoms, int64_t ngroups, const double* partial, const double4* pos, Bonds bonds,
-    double* f_out) {
+    const double* g_extra, double* f_out) {
     __shared__ double sh[RSPLIT][RATOMS][3];
     const int la = threadIdx.x % RATOMS, sl = threadIdx.x / RATOMS;
     const int64_t atom = (int64_t)blockIdx.x * RATOMS + la;
@@ -375,6 +376,11 @@ __global__ __launch_bounds__(RATOMS * RSPLIT) void force_reduce_kernel(
             g1s += c * dy;
             g2s += c * dz;
         }
+    }
+    if (g_extra) {
+        g0s += g_extra[3 * atom + 0];
+        g1s += g_extra[3 * atom + 1];
+        g2s += g_extra[3 * atom + 2];
     }
     f_out[3 * atom + 0] = -g0s;
     f_out[3 * atom + 1] = -g1s;
@@ -423,8 +429,8 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
                          const uint32_t* bits, const double* ex, const double* ey,
                          const double* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
-                         const Bonds& bonds, const ForceScratch& scr, double* f_out,
-                         hipStream_t st) {
+                         const Bonds& bonds, const double* g_extra, const ForceScratch& scr,
+                         double* f_out, hipStream_t st) {
     const ChunkPlan p = chunk_plan(g.n, nfar);
     const ForceSizes need = force_sizes(g, a.n, nfar);
     if (need.partial_doubles > scr.partial_doubles || need.staged_bytes > scr.staged_bytes ||
@@ -461,7 +467,7 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
     }
     hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((a.n + RATOMS - 1) / RATOMS)),
                        dim3(RATOMS * RSPLIT), 0, st, a.n, p.ngroups(), scr.partial, a.pos, bonds,
-                       f_out);
+                       g_extra, f_out);
     return hipGetLastError();
 }
 

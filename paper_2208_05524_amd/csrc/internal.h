@@ -66,7 +66,10 @@ struct CellFields {
     double* bound;   // bound on |U - U_exact| (U units)
 };
 
-enum KernelKind { K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6, K_NKINDS = 7 };
+enum KernelKind {
+    K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6,
+    K_SOLUTE = 7, K_NKINDS = 8
+};
 
 // One molecule of a batch, in device memory: what the batched density and
 // flip-pass kernels need.  brick0 / slot0: the molecule's first brick and
@@ -176,10 +179,45 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
                          const uint32_t* bits, const double* ex, const double* ey,
                          const double* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
-                         const Bonds& bonds, const ForceScratch& scr, double* f_out,
-                         hipStream_t st);
+                         const Bonds& bonds, const double* g_extra, const ForceScratch& scr,
+                         double* f_out, hipStream_t st);
 
 hipError_t launch_bond_energy(const Atoms& a, const Bonds& bonds, double* partial, int nblocks,
                               double* out, hipStream_t st);
+
+// Solute-solute terms beyond bonds (bending, torsion, non-bonded pairs) on
+// the device.  slot: (3 nang + 4 ntor) x 3 gradient rows, angle t's rows
+// 3t .. 3t+2 (atoms i, j, k), torsion t's rows 3 nang + 4t .. +3; inc_off /
+// inc_slot list, per atom, the rows that act on it.  Exclusion partners per
+// atom are sorted ascending.  pair_part: nsplit x n x 5 (used when
+// nonbonded).  Outputs: grad (n x 3), eatom (n x 2).
+constexpr int SOLUTE_SPLITS_MAX = 32;
+struct Solute {
+    int64_t n;
+    const double4* pos;
+    int64_t nang;
+    const int4* ang;          // i, j (vertex), k, 0
+    const double2* ang_prm;   // theta0, B
+    int64_t ntor;
+    const int4* tor;          // i, j, k, l
+    const double* tor_prm;    // 8 per torsion: a0, K_1 .. K_6, 0
+    double* slot;
+    const int32_t* inc_off;
+    const int32_t* inc_slot;
+    int nonbonded;
+    int nsplit;
+    const double4* nb_prm;    // sigma / 2, sqrt(eps), Q, 0
+    const int32_t* x_off;
+    const int32_t* x_other;
+    double kcoul;             // coulomb_k / eps_w
+    double* pair_part;
+    double* grad;
+    double* eatom;
+};
+int solute_splits(int64_t natoms);
+// partial: 4 x nblocks doubles (1 <= nblocks <= 4096); out[0..3] = bending,
+// torsion, LJ and Coulomb energies.
+hipError_t launch_solute(const Solute& s, double* partial, int nblocks, double* out,
+                         hipStream_t st);
 
 }  // namespace vesis

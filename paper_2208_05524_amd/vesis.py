@@ -15,7 +15,7 @@ from ._lib import (EnergyParts, MinStats, Mobility, Params, RelaxOpts, RelaxRepo
                    VesisError)
 
 KERNEL_KINDS = {"density": 0, "far_field": 1, "init": 2, "flip": 3, "energy": 4, "force": 5,
-                "other": 6}
+                "other": 6, "solute": 7}
 
 
 def _f64(a, shape=None):
@@ -98,6 +98,30 @@ class Context:
         self._check(self.lib.vesis_set_bonds(self.h, ij.shape[0], _ptr(ij), _ptr(_f64(r0)),
                                              _ptr(_f64(k))))
 
+    def set_angles(self, ijk, theta0, k):
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+        self._check(self.lib.vesis_set_angles(self.h, ijk.shape[0], _ptr(ijk),
+                                              _ptr(_f64(theta0)), _ptr(_f64(k))))
+
+    def set_torsions(self, ijkl, c, psi):
+        ijkl = np.ascontiguousarray(ijkl, dtype=np.int32).reshape(-1, 4)
+        self._check(self.lib.vesis_set_torsions(self.h, ijkl.shape[0], _ptr(ijkl),
+                                                _ptr(_f64(c, (-1, 7))), _ptr(_f64(psi, (-1, 7)))))
+
+    def set_nonbonded(self, enable=True, sigma_ss=None, eps_ss=None, exclusions=None):
+        ex = np.ascontiguousarray(np.zeros((0, 2)) if exclusions is None else exclusions,
+                                  dtype=np.int32).reshape(-1, 2)
+        self._check(self.lib.vesis_set_nonbonded(
+            self.h, int(bool(enable)), None if sigma_ss is None else _ptr(_f64(sigma_ss)),
+            None if eps_ss is None else _ptr(_f64(eps_ss)), ex.shape[0], _ptr(ex)))
+
+    def set_topology(self, top):
+        """Bending, torsion and non-bonded terms of a ``synth.Topology``.
+        Call before allocate_workspace (or allocate again afterwards)."""
+        self.set_angles(top.angles, top.theta0, top.k_angle)
+        self.set_torsions(top.torsions, top.c, top.psi)
+        self.set_nonbonded(top.nonbonded, top.sigma_ss, top.eps_ss, top.exclusions)
+
     def set_positions(self, xyz):
         """Host array (n x 3) or a CUDA float64 tensor of n x 3 (device copy)."""
         t = self._torch
@@ -127,13 +151,16 @@ class Context:
         self._check(self.lib.vesis_set_workspace(self.h, C.c_void_p(aligned), nbytes))
         return nbytes
 
-    def setup(self, w, precision=None, with_bonds: bool = False):
-        """Params, grid, atoms (and bonds) of a ``synth.Workload``, then workspace."""
+    def setup(self, w, precision=None, with_bonds: bool = False, topology=None):
+        """Params, grid, atoms (bonds, other solute-solute terms of a
+        ``synth.Topology``) of a ``synth.Workload``, then workspace."""
         self.set_params(w.params, precision if precision is not None else w.precision)
         self.set_grid(w.n, w.center, w.h)
         self.set_atoms(w.xyz, w.q, w.sigma, w.eps)
         if with_bonds and len(w.bonds):
             self.set_bonds(w.bonds, w.bond_r0, w.bond_k)
+        if topology is not None:
+            self.set_topology(topology)
         self.allocate_workspace()
         return self
 
