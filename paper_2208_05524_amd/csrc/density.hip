@@ -45,11 +45,12 @@ constexpr int TILE = 256;
 // u = 2^-24:
 //  * coordinates: d = fl(c - fl(r_i - O)) has |d_err| <= u (|a| + |c| + r)
 //    <= u (2|c| + 2r), so rel(r^2) <= 4u(|c|/r + 1) + 2u <= 16u;
-//  * rsqrt (1 ulp): rel(1/r) <= 9u; r^-2: 18.5u; r^-6: 56.5u; the s^3 term
-//    c6 r^-6: 57u; the s^6 term c12 r^-6 r^-6: 114u;
+//  * rsqrt (1 ulp): rel(1/r) <= 9u; r^-2: 18.5u; r^-3 = r^-2 r^-1: 28.5u;
+//    r^-6 = (r^-3)^2: 58u; the s^3 term c6 r^-6: 59u; the s^6 term
+//    c12 r^-6 r^-6: 118u;
 //  * sums: 32-term FP32 partials (31u), 8 of them summed in FP32 per tile
 //    (7u), then FP64.
-// So |U_LJ,fp32 - U_LJ| <= 152u sum_far 4 rho_w eps (s^6 + s^3) (KAPPA_LJ =
+// So |U_LJ,fp32 - U_LJ| <= 156u sum_far 4 rho_w eps (s^6 + s^3) (KAPPA_LJ =
 // 192 with margin) and each component of E carries <= 74u sum_far |Q|/r^2
 // (Q r^-3: 29u, d: 6.8u relative to r; KAPPA_E = 96).  The FP64 near terms:
 // a cell centre that is not a binary fraction puts an absolute error of
@@ -209,11 +210,12 @@ __device__ __forceinline__ void density_brick_f32(const Grid& g, const Atoms& a,
                     const float r2 = fmaf(dz, dz, dxy);
                     const float ir = __builtin_amdgcn_rsqf(r2);
                     const float ir2 = ir * ir;
-                    const float ir6 = ir2 * ir2 * ir2;
+                    const float ir3 = ir2 * ir;
+                    const float ir6 = ir3 * ir3;
                     // 4 rho_w eps (s^6, s^3) = (c12 r^-12, c6 r^-6)
                     P[k] = fmaf(q.y * ir6, ir6, P[k]);
                     Q[k] = fmaf(q.x, ir6, Q[k]);
-                    const float qr3 = q.z * (ir2 * ir);
+                    const float qr3 = q.z * ir3;
                     Ex[k] = fmaf(qr3, dx, Ex[k]);
                     Ey[k] = fmaf(qr3, dy, Ey[k]);
                     Ez[k] = fmaf(qr3, dz, Ez[k]);

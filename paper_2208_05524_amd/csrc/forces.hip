@@ -199,7 +199,10 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
 // Pairs of one staged tile.  FLOOR: apply the r2_min floor (only needed when
 // an atom of the wave may lie within sqrt(r2_min) of a cell of the chunk).
 // With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the LJ part
-// of the coefficient is w r^-2 r^-6 (c1 r^-6 - c2).
+// of the coefficient along d is w r^-8 (c1 r^-6 - c2) and the CFA part
+// -k3 (wE.d) r^-5, so the coefficient is r^-5 [w r^-3 (c1 r^-6 - c2) -
+// k3 (wE.d)] (powers from r^-1: r^-2, r^-3, r^-5 = r^-2 r^-3, r^-6 =
+// (r^-3)^2).
 // UNIT_W: the staged weights are all 1 (grid cells, whose common weight h^3
 // is applied to the tile's sums instead).
 template <typename T, bool FLOOR, bool UNIT_W>
@@ -223,10 +226,11 @@ __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int c
         }
         const T ir2 = ir * ir;
         const T ir3 = ir2 * ir;
-        const T ir6 = ir2 * ir2 * ir2;
-        const T lj = (UNIT_W ? ir2 * ir6 : (c.w * ir2) * ir6) * (c1 * ir6 - c2);
+        const T ir5 = ir3 * ir2;
+        const T ir6 = ir3 * ir3;
         const T ed = e.x * dx + e.y * dy + e.z * dz;
-        T coef = lj - k3 * (ed * (ir3 * ir2));
+        const T lj3 = (UNIT_W ? ir3 : c.w * ir3) * (c1 * ir6 - c2);
+        T coef = ir5 * (lj3 - k3 * ed);
         if (FLOOR) coef = inside ? (T)0 : coef;
         dx_ += coef * dx;
         dy_ += coef * dy;
