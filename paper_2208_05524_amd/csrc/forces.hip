@@ -16,8 +16,9 @@
 // w) and w E in the working precision (for grid cells w = 1: their common
 // weight h^3 multiplies the sums of each tile instead, which saves a
 // multiply per pair); it writes the count per chunk.  The
-// force kernel gives a workgroup 256 atoms (one per lane) and a group of
-// consecutive chunks; the staged cells of each chunk stream through a
+// force kernel gives a workgroup 512 atoms (two per lane: every cell read
+// from LDS serves two pairs, which halves the LDS traffic that bounds the
+// loop) and a group of consecutive chunks; the staged cells of each chunk stream through a
 // double-buffered LDS tile of 256 (the next tile is fetched into registers
 // while the current one is summed, one barrier per tile) and are read by
 // broadcast.  Every lane keeps FP32 partials per tile, folded into FP64.  Per
@@ -34,7 +35,8 @@
 namespace vesis {
 namespace {
 
-constexpr int AWG = 256;        // atoms per workgroup
+constexpr int AWG = 256;        // lanes per workgroup
+constexpr int APL = 2;          // atoms per lane
 constexpr int CT = 256;         // staged cells per LDS tile
 constexpr int CB = 16;          // grid chunk edge (cells)
 constexpr int CB3 = CB * CB * CB;
@@ -196,55 +198,63 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
     if (t == 0) f.count[chunk] = run;
 }
 
-// Pairs of one staged tile.  FLOOR: apply the r2_min floor (only needed when
-// an atom of the wave may lie within sqrt(r2_min) of a cell of the chunk).
-// With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the LJ part
-// of the coefficient along d is w r^-8 (c1 r^-6 - c2) and the CFA part
-// -k3 (wE.d) r^-5, so the coefficient is r^-5 [w r^-3 (c1 r^-6 - c2) -
+// Pairs of one staged tile for the APL atoms of a lane: each staged cell is
+// read from LDS once and serves APL pairs (the LDS, not the VALU, bounds a
+// loop with one pair per read).  FLOOR: apply the r2_min floor (only needed
+// when an atom of the wave may lie within sqrt(r2_min) of a cell of the
+// chunk).  With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the
+// LJ part of the coefficient along d is w r^-8 (c1 r^-6 - c2) and the CFA
+// part -k3 (wE.d) r^-5, so the coefficient is r^-5 [w r^-3 (c1 r^-6 - c2) -
 // k3 (wE.d)] (powers from r^-1: r^-2, r^-3, r^-5 = r^-2 r^-3, r^-6 =
-// (r^-3)^2).
-// UNIT_W: the staged weights are all 1 (grid cells, whose common weight h^3
-// is applied to the tile's sums instead).
+// (r^-3)^2).  UNIT_W: the staged weights are all 1 (grid cells, whose
+// common weight h^3 is applied to the tile's sums instead).
 template <typename T, bool FLOOR, bool UNIT_W>
-__device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt, T ax, T ay,
-                                           T az, T c1, T c2, T k3, T r2min, T (&acc)[6]) {
+__device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt,
+                                           const T (&ax)[APL], const T (&ay)[APL],
+                                           const T (&az)[APL], const T (&c1)[APL],
+                                           const T (&c2)[APL], const T (&k3)[APL], T r2min,
+                                           T (&acc)[APL][6]) {
     using T4 = typename V4<T>::type;
-    T dx_ = 0, dy_ = 0, dz_ = 0, ex_ = 0, ey_ = 0, ez_ = 0;
-#pragma unroll 2
+    T s[APL][6];
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[q][k] = 0;
     for (int m = 0; m < cnt; ++m) {
         const T4 c = sc[2 * m];
         const T4 e = sc[2 * m + 1];
-        const T dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        bool inside = false;
-        T ir;
-        if (FLOOR) {
-            inside = r2 < r2min;
-            ir = rsq<T>(inside ? r2min : r2);
-        } else {
-            ir = rsq<T>(r2);
+#pragma unroll
+        for (int q = 0; q < APL; ++q) {
+            const T dx = c.x - ax[q], dy = c.y - ay[q], dz = c.z - az[q];
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            bool inside = false;
+            T ir;
+            if (FLOOR) {
+                inside = r2 < r2min;
+                ir = rsq<T>(inside ? r2min : r2);
+            } else {
+                ir = rsq<T>(r2);
+            }
+            const T ir2 = ir * ir;
+            const T ir3 = ir2 * ir;
+            const T ir5 = ir3 * ir2;
+            const T ir6 = ir3 * ir3;
+            const T ed = e.x * dx + e.y * dy + e.z * dz;
+            const T lj3 = (UNIT_W ? ir3 : c.w * ir3) * (c1[q] * ir6 - c2[q]);
+            T coef = ir5 * (lj3 - k3[q] * ed);
+            if (FLOOR) coef = inside ? (T)0 : coef;
+            s[q][0] += coef * dx;
+            s[q][1] += coef * dy;
+            s[q][2] += coef * dz;
+            s[q][3] += ir3 * e.x;
+            s[q][4] += ir3 * e.y;
+            s[q][5] += ir3 * e.z;
         }
-        const T ir2 = ir * ir;
-        const T ir3 = ir2 * ir;
-        const T ir5 = ir3 * ir2;
-        const T ir6 = ir3 * ir3;
-        const T ed = e.x * dx + e.y * dy + e.z * dz;
-        const T lj3 = (UNIT_W ? ir3 : c.w * ir3) * (c1 * ir6 - c2);
-        T coef = ir5 * (lj3 - k3 * ed);
-        if (FLOOR) coef = inside ? (T)0 : coef;
-        dx_ += coef * dx;
-        dy_ += coef * dy;
-        dz_ += coef * dz;
-        ex_ += ir3 * e.x;
-        ey_ += ir3 * e.y;
-        ez_ += ir3 * e.z;
     }
-    acc[0] = dx_;
-    acc[1] = dy_;
-    acc[2] = dz_;
-    acc[3] = ex_;
-    acc[4] = ey_;
-    acc[5] = ez_;
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[q][k] = s[q][k];
 }
 
 template <typename T>
@@ -252,31 +262,42 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     using T4 = typename V4<T>::type;
     __shared__ T4 sbuf[2][2 * CT];
     const int t = threadIdx.x;
-    const int64_t atom = (int64_t)blockIdx.x * AWG + t;
-    const bool has_atom = atom < f.a.n;
     const Grid& g = f.g;
     const T4* staged = static_cast<const T4*>(f.staged);
 
-    double px = 0, py = 0, pz = 0;
-    T c1 = 0, c2 = 0, k3 = 0;
-    double kq = 0.0;
-    if (has_atom) {
-        const double4 p = f.a.pos[atom];
-        const double4 q = f.a.prm64[atom];  // sigma^2, 4 rho_w eps, Q, sigma
-        px = p.x;
-        py = p.y;
-        pz = p.z;
-        const double s6 = q.x * q.x * q.x;
-        c2 = (T)(6.0 * q.y * s6);
-        c1 = (T)(12.0 * q.y * s6 * s6);
-        kq = -2.0 * f.ph.ccfa * q.z;
-        k3 = (T)(3.0 * kq);
+    // lane t holds atoms base + t and base + AWG + t
+    int64_t atom[APL];
+    bool has[APL];
+    double px[APL], py[APL], pz[APL], kq[APL];
+    T c1[APL], c2[APL], k3[APL];
+#pragma unroll
+    for (int q = 0; q < APL; ++q) {
+        atom[q] = (int64_t)blockIdx.x * (AWG * APL) + q * AWG + t;
+        has[q] = atom[q] < f.a.n;
+        px[q] = py[q] = pz[q] = kq[q] = 0.0;
+        c1[q] = c2[q] = k3[q] = 0;
+        if (has[q]) {
+            const double4 p = f.a.pos[atom[q]];
+            const double4 prm = f.a.prm64[atom[q]];  // sigma^2, 4 rho_w eps, Q, sigma
+            px[q] = p.x;
+            py[q] = p.y;
+            pz[q] = p.z;
+            const double s6 = prm.x * prm.x * prm.x;
+            c2[q] = (T)(6.0 * prm.y * s6);
+            c1[q] = (T)(12.0 * prm.y * s6 * s6);
+            kq[q] = -2.0 * f.ph.ccfa * prm.z;
+            k3[q] = (T)(3.0 * kq[q]);
+        }
     }
     const T r2min = (T)f.ph.r2min;
     // an atom farther than this from the chunk centre along some axis is at
     // least 2 sqrt(r2_min) from every cell centre of the chunk
     const double reach = 0.5 * (CB - 1) * g.h + 2.0 * sqrt(f.ph.r2min);
-    double gd[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
+    double gd[APL][3], ge[APL][3];
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gd[q][k] = ge[q][k] = 0.0;
 
     const int64_t ch0 = (int64_t)blockIdx.y * GROUP;
     const int64_t ch1 = ch0 + GROUP < f.nchunks ? ch0 + GROUP : f.nchunks;
@@ -285,9 +306,16 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         if (cnt == 0) continue;  // uniform over the workgroup
         double ox, oy, oz;
         chunk_origin(f, chunk, ox, oy, oz);
-        const T ax = (T)(px - ox), ay = (T)(py - oy), az = (T)(pz - oz);
-        const bool near = has_atom && fabs(px - ox) <= reach && fabs(py - oy) <= reach &&
-                          fabs(pz - oz) <= reach;
+        T ax[APL], ay[APL], az[APL];
+        bool near = false;
+#pragma unroll
+        for (int q = 0; q < APL; ++q) {
+            ax[q] = (T)(px[q] - ox);
+            ay[q] = (T)(py[q] - oy);
+            az[q] = (T)(pz[q] - oz);
+            near = near || (has[q] && fabs(px[q] - ox) <= reach && fabs(py[q] - oy) <= reach &&
+                            fabs(pz[q] - oz) <= reach);
+        }
         const bool is_grid = chunk < f.ngrid;
         const bool floor = !is_grid || __ballot(near) != 0;
         const double wscale = is_grid ? f.ph.h3 : 1.0;
@@ -308,19 +336,20 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
                 rb = src[2 * nxt + 1];
             }
             const int m = cnt - tile * CT < CT ? cnt - tile * CT : CT;
-            T acc[6];
+            T acc[APL][6];
             if (!is_grid)
                 tile_pairs<T, true, false>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else if (floor)
                 tile_pairs<T, true, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else
                 tile_pairs<T, false, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
-            gd[0] += wscale * acc[0];
-            gd[1] += wscale * acc[1];
-            gd[2] += wscale * acc[2];
-            ge[0] += wscale * acc[3];
-            ge[1] += wscale * acc[4];
-            ge[2] += wscale * acc[5];
+#pragma unroll
+            for (int q = 0; q < APL; ++q)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gd[q][k] += wscale * acc[q][k];
+                    ge[q][k] += wscale * acc[q][3 + k];
+                }
             if (tile + 1 < ntiles) {
                 // the other buffer was last read in tile - 1, before the
                 // barrier that ended it
@@ -330,11 +359,14 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
             __syncthreads();
         }
     }
-    if (!has_atom) return;
-    double* out = f.partial + ((int64_t)blockIdx.y * f.a.n + atom) * 3;
-    out[0] = gd[0] + kq * ge[0];
-    out[1] = gd[1] + kq * ge[1];
-    out[2] = gd[2] + kq * ge[2];
+#pragma unroll
+    for (int q = 0; q < APL; ++q) {
+        if (!has[q]) continue;
+        double* out = f.partial + ((int64_t)blockIdx.y * f.a.n + atom[q]) * 3;
+        out[0] = gd[q][0] + kq[q] * ge[q][0];
+        out[1] = gd[q][1] + kq[q] * ge[q][1];
+        out[2] = gd[q][2] + kq[q] * ge[q][2];
+    }
 }
 
 // F_n = -(sum over chunk groups of the partial gradients + bond gradient +
@@ -459,7 +491,7 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
     f.staged = scr.staged;
     f.count = scr.count;
     f.partial = scr.partial;
-    const dim3 grid((unsigned)((a.n + AWG - 1) / AWG), (unsigned)p.ngroups());
+    const dim3 grid((unsigned)((a.n + AWG * APL - 1) / (AWG * APL)), (unsigned)p.ngroups());
     if (precision == 64) {
         hipLaunchKernelGGL(force_stage_kernel<double>, dim3((unsigned)p.nchunks()), dim3(256), 0,
                            st, f);
