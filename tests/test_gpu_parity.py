@@ -139,6 +139,22 @@ def test_minimize_fp64_single_atom_64():
     _compare_minimisation(w, "loose", 1.2, 64)
 
 
+@pytest.mark.parametrize("mode,param", [("loose", 6.0), ("tight", 1.0)])
+def test_minimize_dry_and_wet_two_atoms(mode, param):
+    """Two LJ atoms 8 A apart in the paper's units ((-8, 8)^3 A, 64^3, FP64):
+    the loose start ends in one dry region holding both atoms, the tight
+    start in two wet spheres; both bit-exact against the oracle."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "two_atom_tables.json")))
+    m = g["model"]
+    w = synth.Workload(name="two_atoms_8A", n=64, h=16.0 / 64, center=np.zeros(3),
+                       xyz=np.asarray(g["r0_8"]["final_positions"], float).reshape(-1, 3),
+                       q=np.zeros(2), sigma=np.full(2, m["sigma"]), eps=np.full(2, m["eps"]),
+                       params=synth.paper_units_params(), precision=64)
+    _compare_minimisation(w, mode, param, 64)
+
+
 def test_minimize_chain1000_128():
     """1,000-atom globule, 128^3 grid at 0.05 nm, tight start, FP32 densities."""
     w = synth.chain_1000()

@@ -331,6 +331,78 @@ def test_minimised_labels_are_a_local_minimum():
         assert s.energy(phi2, ulj, ucfa, far)["total"] >= e_fin - 1e-12 * abs(e_fin)
 
 
+def test_colour_pass_equals_a_serial_pass_in_reverse_order():
+    """A colour pass (every band cell of one colour evaluated on the labels at
+    the start of the pass, those with Delta E < 0 flipped) equals visiting the
+    same candidates one at a time, here in reverse index order, each judged on
+    the labels the earlier flips left: cells of one colour lie outside each
+    other's kernel support and face neighbourhood, so a flip leaves every
+    other candidate's Delta E unchanged (bit for bit) and lowers the energy by
+    its own Delta E."""
+    s, phi = _tiny_case(seed=9, n=12)
+    ulj, ucfa = s.density_grid()
+    u = ulj + ucfa
+    far = s.far_field()
+    L = oracle.lib()
+    for c in range(s.colours()):
+        ref = phi.copy()
+        s.colour_pass(ref, u, c)
+        ser = phi.copy()
+        cand = [j for j in range(s.ncell) if L.orc_colour_of(s.sref, j) == c and s.in_band(phi, j)]
+        for j in reversed(cand):
+            d0 = s.delta_e(phi, u, j)
+            d = s.delta_e(ser, u, j)
+            assert d == d0
+            if d < 0:
+                e0 = s.energy(ser, ulj, ucfa, far)["total"]
+                ser[j] = -ser[j]
+                e1 = s.energy(ser, ulj, ucfa, far)["total"]
+                assert e1 < e0
+                assert e1 - e0 == pytest.approx(d, abs=1e-11 * (abs(e0) + 1))
+        assert np.array_equal(ser, ref)
+        phi = ref
+
+
+def test_loose_and_tight_starts_agree_for_a_convex_solute():
+    """One atom: the relaxation from a loose sphere and from the tight
+    surface (Sec. "Initial surfaces") ends in the same labels."""
+    w = synth.single_atom(40)
+    s = oracle.System.from_workload(w)
+    ulj, ucfa = s.density_grid()
+    u = ulj + ucfa
+    a = s.init_loose(1.2)
+    b = s.init_tight()
+    s.minimize_colour(a, u)
+    s.minimize_colour(b, u)
+    assert np.array_equal(a, b)
+
+
+def test_loose_start_keeps_a_dry_region_between_separated_atoms():
+    """Two LJ atoms 8 A apart (the paper's r0 = 8 A state, its units): from a
+    loose sphere enclosing both the relaxation stops in one solute region
+    holding both atoms (a dry state), from the tight surface in two separate
+    spheres (wet) -- the dependence on the initial surface the paper reports
+    for its two plates and the two domains of BphC.  Here the dry state is
+    the higher local minimum."""
+    from scipy import ndimage
+    g = _golden()
+    m = g["model"]
+    s = _sys(64, 16.0 / 64, g["r0_8"]["final_positions"], [0, 0], [m["sigma"]] * 2,
+             [m["eps"]] * 2, synth.paper_units_params())
+    ulj, ucfa = s.density_grid()
+    u = ulj + ucfa
+    far = s.far_field()
+    dry = s.init_loose(6.0)
+    wet = s.init_tight()
+    s.minimize_colour(dry, u)
+    s.minimize_colour(wet, u)
+    n = s.n
+    ndry = ndimage.label(dry.reshape(n, n, n) == -1)[1]
+    nwet = ndimage.label(wet.reshape(n, n, n) == -1)[1]
+    assert (ndry, nwet) == (1, 2)
+    assert s.energy(dry, ulj, ucfa, far)["total"] > s.energy(wet, ulj, ucfa, far)["total"]
+
+
 def test_heap_and_colour_schedules_agree_on_single_atom():
     w = synth.single_atom(48)
     s = oracle.System.from_workload(w)
