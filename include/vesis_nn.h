@@ -38,6 +38,18 @@ extern "C" {
 int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* bias, void* y,
                        int n, int d, int h, int wd, int cin, int cout, int relu);
 
+/* y = [relu](conv3x3x3([up2(a) | b], w) + bias): the convolution of the
+ * channel concatenation of a, upsampled 2x by nearest neighbour, and b,
+ * read in place (no upsampled or concatenated tensor is formed; for
+ * inference, where the decoder's inputs need not be kept).  a:
+ * (n, d/2, h/2, w/2, ca), b: (n, d, h, w, cb), w: (27, cout, ca + cb),
+ * y: (n, d, h, w, cout), all BF16.  ca % 16 == 0, cb % 16 == 0,
+ * cout % 32 == 0, d, h, w even and w >= 16.  The result equals, bit for
+ * bit, vesis_nn_conv3_fwd of vesis_nn_concat(vesis_nn_up2(a), b). */
+int vesis_nn_conv3_fwd_upcat(void* stream, const void* a, int ca, const void* b, int cb,
+                             const void* w, const float* bias, void* y, int n, int d, int h,
+                             int wd, int cout, int relu);
+
 /* Bytes of FP32 scratch vesis_nn_conv3_wgrad needs (one partial weight
  * gradient per chunk of 8192 positions, and per-channel partial sums for
  * the bias gradient). */

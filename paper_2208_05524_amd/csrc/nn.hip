@@ -128,9 +128,24 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict
 // wavefront w takes y-row w of each of the MT z-layers of the tile (MT
 // operands of 32 positions) against NT output-channel tiles, the weights
 // read from global memory (shared by every workgroup, they stay in cache).
+//
+// The input may be the channel concatenation [up2(A) | B] read in place:
+// channels [0, ca) come from A, which holds them at half resolution
+// (nearest-neighbour upsampling: position (z, y, x) reads A at (z/2, y/2,
+// x/2)) when `up` is set, and channels [ca, Cin) from B at full
+// resolution.  ca is a multiple of 16, so a staged chunk of 16 channels
+// comes from one tensor; the staged values, and hence the result, are those
+// of the convolution of the materialised concatenation.
+struct ConvIn {
+    const __bf16* a;
+    int ca;
+    int up;
+    const __bf16* b;
+};
+
 constexpr int TX = 32, TY = 4, HX = TX + 2, HY = TY + 2;
 template <int MT, int NT, bool RELU>
-__global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const __bf16* __restrict__ X,
+__global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const ConvIn in,
                                                             const __bf16* __restrict__ Wt,
                                                             const float* __restrict__ bias,
                                                             __bf16* __restrict__ Y, int N, int D,
@@ -151,17 +166,28 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const __bf16* __rest
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
     const __bf16* wrow = Wt + ((int64_t)co0 + row) * Cin + 8 * half;
+    const int cb = Cin - in.ca;
+    const int Da = in.up ? D / 2 : D, Ha = in.up ? H / 2 : H, Wa = in.up ? W / 2 : W;
     for (int c0 = 0; c0 < Cin; c0 += 16) {
         __syncthreads();  // the previous chunk's reads are done
+        const bool from_a = c0 < in.ca;  // uniform over the workgroup
         // stage the halo tile: two lanes per position, 8 channels each
         for (int e = threadIdx.x; e < 2 * HPOS; e += CWG) {
             const int hp = e >> 1, hh = e & 1;
             const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
             const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D)
-                v = *reinterpret_cast<const uint4*>(
-                    X + ((((int64_t)nb * D + zz) * H + yy) * W + xx) * Cin + c0 + 8 * hh);
+            if (xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D) {
+                const __bf16* src;
+                if (from_a) {
+                    const int za = in.up ? zz >> 1 : zz, ya = in.up ? yy >> 1 : yy,
+                              xa = in.up ? xx >> 1 : xx;
+                    src = in.a + ((((int64_t)nb * Da + za) * Ha + ya) * Wa + xa) * in.ca + c0;
+                } else {
+                    src = in.b + ((((int64_t)nb * D + zz) * H + yy) * W + xx) * cb + (c0 - in.ca);
+                }
+                v = *reinterpret_cast<const uint4*>(src + 8 * hh);
+            }
             *reinterpret_cast<uint4*>(&tile[hp * 16 + 8 * hh]) = v;
         }
         __syncthreads();
@@ -367,6 +393,28 @@ __global__ void relu_bwd_kernel(const __bf16* Y, const __bf16* dY, __bf16* dPre,
 }
 
 // 2x2x2 average pooling and its adjoint (even sizes).
+// Eight channels per thread (C % 8 == 0): 16-byte loads and stores; the
+// eight inputs of each output are summed in the same order as below.
+__global__ void pool2_fwd_vec_kernel(const __bf16* X, __bf16* Y, int N, int D, int H, int W, int C) {
+    const int d = D / 2, h = H / 2, w = W / 2, C8 = C / 8;
+    const int64_t n_out = (int64_t)N * d * h * w * C8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    const int c = (int)(i % C8) * 8;
+    int n, z, y, x;
+    pos_coords(i / C8, d, h, w, n, z, y, x);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k) {
+        const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
+        const bf16x8 v = load8(X + ((((int64_t)n * D + zz) * H + yy) * W + xx) * C + c);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += (float)v[j];
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (__bf16)(0.125f * s[j]);
+    *reinterpret_cast<bf16x8*>(Y + (i / C8) * C + c) = o;
+}
 __global__ void pool2_fwd_kernel(const __bf16* X, __bf16* Y, int N, int D, int H, int W, int C) {
     const int d = D / 2, h = H / 2, w = W / 2;
     const int64_t n_out = (int64_t)N * d * h * w * C;
@@ -453,12 +501,22 @@ __global__ void add_kernel(const __bf16* A, const __bf16* B, __bf16* Y, int64_t 
 }
 
 // 1x1x1 head: logits[p] = w . X[p] + b (FP32), and its adjoint.
+// One position per thread; channels added in order (16-byte loads when
+// C % 8 == 0).
 __global__ void head_fwd_kernel(const __bf16* X, const float* w, const float* b, float* logits,
                                 int64_t P, int C) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     float s = b[0];
-    for (int c = 0; c < C; ++c) s += w[c] * (float)X[p * C + c];
+    if (C % 8 == 0) {
+        for (int c = 0; c < C; c += 8) {
+            const bf16x8 v = load8(X + p * C + c);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += w[c + j] * (float)v[j];
+        }
+    } else {
+        for (int c = 0; c < C; ++c) s += w[c] * (float)X[p * C + c];
+    }
     logits[p] = s;
 }
 __global__ void head_bwd_x_kernel(const float* dlogit, const float* w, __bf16* dX, int64_t P,
@@ -506,29 +564,67 @@ __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_
 // Input features on the cell grid (n^3 cells of edge h, first centre x0):
 // channel 0 = sum_i exp(-|x - r_i|^2 / (2 s_i^2)), channel 1 = the same
 // weighted by q_i, with s_i = sigma_i / 2, cut at 4 s_i; channels 2..C-1 = 0.
+// A workgroup takes an 8 x 8 x 4 brick of cells; per tile of 256 atoms it
+// keeps, in atom order, those whose distance to the brick's box of cell
+// centres is below the cut (with a margin for rounding), and every cell then
+// applies the exact cut to those: the same terms, summed in the same order,
+// as a loop over all atoms.
+constexpr int FBX = 8, FBY = 8, FBZ = 4;
 __global__ __launch_bounds__(256) void featurize_kernel(const double4* pos, const double* sigma,
                                                         const double* q, int64_t na, int n,
                                                         double h, double x0, double y0, double z0,
                                                         int C, __bf16* X) {
     __shared__ float4 sa[256];
     __shared__ float2 sp[256];
-    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t ncell = (int64_t)n * n * n;
-    const int x = (int)(cell % n), y = (int)((cell / n) % n), z = (int)(cell / ((int64_t)n * n));
+    __shared__ int wcnt[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int nbx = (n + FBX - 1) / FBX, nby = (n + FBY - 1) / FBY;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    const int bz = b / nby;
+    const int x = bx * FBX + (t % FBX), y = by * FBY + ((t / FBX) % FBY), z = bz * FBZ + t / (FBX * FBY);
     const float cx = (float)(x0 + x * h), cy = (float)(y0 + y * h), cz = (float)(z0 + z * h);
+    // box of the brick's cell centres (clipped to the grid)
+    const int xe = min(bx * FBX + FBX - 1, n - 1), ye = min(by * FBY + FBY - 1, n - 1),
+              ze = min(bz * FBZ + FBZ - 1, n - 1);
+    const float lx = (float)(x0 + bx * FBX * h), hx = (float)(x0 + xe * h);
+    const float ly = (float)(y0 + by * FBY * h), hy = (float)(y0 + ye * h);
+    const float lz = (float)(z0 + bz * FBZ * h), hz = (float)(z0 + ze * h);
     float d0 = 0.f, d1 = 0.f;
     for (int64_t base = 0; base < na; base += 256) {
-        __syncthreads();
-        const int64_t a = base + threadIdx.x;
+        const int64_t a = base + t;
+        bool keep = false;
+        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 pq = make_float2(0.f, 0.f);
         if (a < na) {
             const double4 p = pos[a];
             const float s = (float)(0.5 * sigma[a]);
-            sa[threadIdx.x] = make_float4((float)p.x, (float)p.y, (float)p.z, 1.f / (2.f * s * s));
-            sp[threadIdx.x] = make_float2((float)q[a], 16.f * s * s);
+            pa = make_float4((float)p.x, (float)p.y, (float)p.z, 1.f / (2.f * s * s));
+            pq = make_float2((float)q[a], 16.f * s * s);
+            const float ex = fmaxf(fmaxf(lx - pa.x, pa.x - hx), 0.f);
+            const float ey = fmaxf(fmaxf(ly - pa.y, pa.y - hy), 0.f);
+            const float ez = fmaxf(fmaxf(lz - pa.z, pa.z - hz), 0.f);
+            keep = ex * ex + ey * ey + ez * ez < 1.001f * pq.y;
+        }
+        const uint64_t bal = __ballot(keep);
+        __syncthreads();  // the previous tile has been read
+        if (lane == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            off += k < wv ? wcnt[k] : 0;
+            tot += wcnt[k];
+        }
+        if (keep) {
+            const int at = off + __popcll(bal & ((1ull << lane) - 1ull));
+            sa[at] = pa;
+            sp[at] = pq;
         }
         __syncthreads();
-        const int cnt = (int)(na - base < 256 ? na - base : 256);
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = 0; k < tot; ++k) {
             const float4 p = sa[k];
             const float dx = cx - p.x, dy = cy - p.y, dz = cz - p.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -539,7 +635,8 @@ __global__ __launch_bounds__(256) void featurize_kernel(const double4* pos, cons
             }
         }
     }
-    if (cell >= ncell) return;
+    if (x >= n || y >= n || z >= n) return;
+    const int64_t cell = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
     for (int c = 0; c < C; ++c) X[cell * C + c] = (__bf16)(c == 0 ? d0 : (c == 1 ? d1 : 0.f));
 }
 
@@ -561,6 +658,38 @@ inline int status(hipError_t e) { return e == hipSuccess ? 0 : VESIS_NN_E_DEVICE
 inline const __bf16* B(const void* p) { return static_cast<const __bf16*>(p); }
 inline __bf16* Bm(void* p) { return static_cast<__bf16*>(p); }
 bool dims_ok(int N, int D, int H, int W) { return N > 0 && D > 0 && H > 0 && W > 0; }
+
+// LDS-staged tiles: 4 x-rows (y) x MT z-layers x 32 positions, by 32 NT
+// output channels.  MT = 2, NT = 2 (or MT = 4, NT = 1 for 32 output
+// channels) reuse each staged operand most; a layer that would then have
+// fewer workgroups than CUs (the coarsest level) takes MT = NT = 1.
+void launch_conv3_lds(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
+                      int n, int d, int h, int wd, int cin, int cout, int relu) {
+    const unsigned nt_xy = (unsigned)(((wd + TX - 1) / TX) * ((h + TY - 1) / TY));
+    const int64_t big = (int64_t)nt_xy * (cout % 64 == 0 ? cout / 64 * ((d + 1) / 2)
+                                                         : cout / 32 * ((d + 3) / 4)) * n;
+    if (big < 256) {
+        const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * d));
+        if (relu)
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+        else
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    } else if (cout % 64 == 0) {
+        constexpr int MT = 2;
+        const dim3 grid(nt_xy, (unsigned)(cout / 64), (unsigned)(n * ((d + MT - 1) / MT)));
+        if (relu)
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+        else
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    } else {
+        constexpr int MT = 4;
+        const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + MT - 1) / MT)));
+        if (relu)
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+        else
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    }
+}
 }  // namespace
 
 extern "C" {
@@ -572,23 +701,8 @@ int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* 
     const int64_t P = (int64_t)n * d * h * wd;
     const bool two = cout % 64 == 0;
     if (wd >= TX / 2) {
-        // LDS-staged tiles: 4 x-rows (y) x MT z-layers x 32 positions
-        const unsigned nt_xy = (unsigned)(((wd + TX - 1) / TX) * ((h + TY - 1) / TY));
-        if (two) {
-            constexpr int MT = 2;
-            const dim3 grid(nt_xy, (unsigned)(cout / 64), (unsigned)(n * ((d + MT - 1) / MT)));
-            if (relu)
-                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-            else
-                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-        } else {
-            constexpr int MT = 4;
-            const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + MT - 1) / MT)));
-            if (relu)
-                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-            else
-                hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-        }
+        launch_conv3_lds(S(stream), ConvIn{B(x), cin, 0, nullptr}, w, bias, y, n, d, h, wd, cin,
+                         cout, relu);
         return status(hipGetLastError());
     }
     const dim3 grid(nblk(P, 128), (unsigned)(cout / (two ? 64 : 32)));
@@ -600,6 +714,17 @@ int vesis_nn_conv3_fwd(void* stream, const void* x, const void* w, const float* 
         hipLaunchKernelGGL((conv3_fwd_kernel<1, true>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
     else
         hipLaunchKernelGGL((conv3_fwd_kernel<1, false>), grid, dim3(CWG), 0, S(stream), B(x), B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    return status(hipGetLastError());
+}
+
+int vesis_nn_conv3_fwd_upcat(void* stream, const void* a, int ca, const void* b, int cb,
+                             const void* w, const float* bias, void* y, int n, int d, int h,
+                             int wd, int cout, int relu) {
+    if (!a || !b || !w || !y || !dims_ok(n, d, h, wd) || d % 2 || h % 2 || wd % 2 ||
+        wd < TX / 2 || ca <= 0 || ca % 16 || cb <= 0 || cb % 16 || cout <= 0 || cout % 32)
+        return VESIS_NN_E_ARG;
+    launch_conv3_lds(S(stream), ConvIn{B(a), ca, 1, B(b)}, w, bias, y, n, d, h, wd, ca + cb,
+                     cout, relu);
     return status(hipGetLastError());
 }
 
@@ -628,7 +753,8 @@ int vesis_nn_conv3_wgrad(void* stream, const void* x, const void* dy, float* dw,
     if (db) {
         // bias partials after the weight partials (256-byte aligned)
         const size_t off = (sizeof(float) * (size_t)nch * nw + 255) / 256 * 256 / sizeof(float);
-        channel_sums(B(dy), nullptr, P, cout, ws + off, db, S(stream));
+        if (channel_sums(B(dy), nullptr, P, cout, ws + off, db, S(stream)) != hipSuccess)
+            return VESIS_NN_E_DEVICE;
     }
     return status(hipGetLastError());
 }
@@ -654,7 +780,10 @@ int vesis_nn_pool2(void* stream, const void* x, void* y, int n, int d, int h, in
         hipLaunchKernelGGL(pool2_bwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
     } else {
         const int64_t cnt = (int64_t)n * (d / 2) * (h / 2) * (wd / 2) * c;
-        hipLaunchKernelGGL(pool2_fwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+        if (c % 8 == 0)
+            hipLaunchKernelGGL(pool2_fwd_vec_kernel, dim3(nblk(cnt / 8, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
+        else
+            hipLaunchKernelGGL(pool2_fwd_kernel, dim3(nblk(cnt, 256)), dim3(256), 0, S(stream), B(x), Bm(y), n, d, h, wd, c);
     }
     return status(hipGetLastError());
 }
@@ -703,8 +832,9 @@ int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const fl
     if (!dlogit || !x || !w || !dx || !dw || !db || !ws || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
     if (ws_bytes < channel_sums_bytes(p, c)) return VESIS_NN_E_ARG;
     hipLaunchKernelGGL(head_bwd_x_kernel, dim3(nblk(p * c, 256)), dim3(256), 0, S(stream), dlogit, w, Bm(dx), p, c);
-    channel_sums(B(x), dlogit, p, c, ws, dw, S(stream));
-    channel_sums(nullptr, dlogit, p, 1, ws, db, S(stream));
+    if (channel_sums(B(x), dlogit, p, c, ws, dw, S(stream)) != hipSuccess ||
+        channel_sums(nullptr, dlogit, p, 1, ws, db, S(stream)) != hipSuccess)
+        return VESIS_NN_E_DEVICE;
     return status(hipGetLastError());
 }
 
@@ -729,8 +859,8 @@ int vesis_nn_featurize(void* stream, const double* pos4, const double* sigma, co
                        int64_t na, int n, double h, const double* center, int c, void* x) {
     if (!pos4 || !sigma || !q || !center || !x || na < 0 || n <= 0 || c < 2) return VESIS_NN_E_ARG;
     const double L = 0.5 * n * h;
-    const int64_t ncell = (int64_t)n * n * n;
-    hipLaunchKernelGGL(featurize_kernel, dim3(nblk(ncell, 256)), dim3(256), 0, S(stream),
+    const unsigned nbricks = (unsigned)(((n + FBX - 1) / FBX) * ((n + FBY - 1) / FBY) * ((n + FBZ - 1) / FBZ));
+    hipLaunchKernelGGL(featurize_kernel, dim3(nbricks), dim3(256), 0, S(stream),
                        reinterpret_cast<const double4*>(pos4), sigma, q, na, n, h,
                        center[0] - L + 0.5 * h, center[1] - L + 0.5 * h, center[2] - L + 0.5 * h, c, Bm(x));
     return status(hipGetLastError());

@@ -121,6 +121,17 @@ class UNet:
                                           1 if relu else 0), "conv " + name)
         return y
 
+    def conv_upcat(self, name, a, b, relu=True):
+        """conv of [up2(a) | b] without forming the upsampled concatenation."""
+        q = self.p[name]
+        s = b.shape[1]
+        y = self._act(s, q["cout"])
+        N.check(self.L.vesis_nn_conv3_fwd_upcat(self._s(), N.ptr(a), a.shape[4], N.ptr(b),
+                                                b.shape[4], N.ptr(q["wf"]), N.ptr(q["bias"]),
+                                                N.ptr(y), self.b, s, s, s, q["cout"],
+                                                1 if relu else 0), "conv " + name)
+        return y
+
     def pool(self, x):
         s, c = x.shape[1], x.shape[4]
         y = self._act(s // 2, c)
@@ -152,9 +163,12 @@ class UNet:
                                           C.cast(cen, C.c_void_p), IN_C, N.ptr(x)), "featurize")
         return x
 
-    def forward(self, x):
-        """x: (b, n, n, n, 32) BF16.  Returns logits (b n^3 FP32); keeps the
-        activations for backward."""
+    def forward(self, x, keep: bool = True):
+        """x: (b, n, n, n, 32) BF16.  Returns logits (b n^3 FP32).  keep: hold
+        the activations for backward; without it (inference) the decoder
+        convolutions read [up2(deeper) | skip] in place."""
+        if not keep:
+            return self._infer(x)
         a = {"x": x}
         a["a1"] = self.conv("e1a", x)
         a["s1"] = self.conv("e1b", a["a1"])
@@ -182,6 +196,26 @@ class UNet:
         N.check(self.L.vesis_nn_head_fwd(self._s(), N.ptr(a["b7"]), N.ptr(h["w"]), N.ptr(h["bias"]),
                                          N.ptr(logits), P, LEVELS[0]), "head")
         self.acts = a
+        return logits
+
+    def _infer(self, x):
+        def upcat(name, a, b):
+            if b.shape[1] >= 16:
+                return self.conv_upcat(name, a, b)
+            return self.conv(name, self.cat(self.up(a), b))
+        s1 = self.conv("e1b", self.conv("e1a", x))
+        s2 = self.conv("e2b", self.conv("e2a", self.pool(s1)))
+        s3 = self.conv("e3b", self.conv("e3a", self.pool(s2)))
+        b4 = self.conv("e4b", self.conv("e4a", self.pool(s3)))
+        b5 = self.conv("d3b", upcat("d3a", b4, s3))
+        b6 = self.conv("d2b", upcat("d2a", b5, s2))
+        b7 = self.conv("d1b", upcat("d1a", b6, s1))
+        P = self.b * self.n ** 3
+        logits = self.t.empty(P, dtype=self.t.float32, device=self.dev)
+        h = self.p["head"]
+        N.check(self.L.vesis_nn_head_fwd(self._s(), N.ptr(b7), N.ptr(h["w"]), N.ptr(h["bias"]),
+                                         N.ptr(logits), P, LEVELS[0]), "head")
+        self.acts = None
         return logits
 
     # ------------------------------------------------------------ backward
@@ -370,7 +404,7 @@ def train(model: UNet, samples, steps: int, lr: float = 1e-3, pos_weight: float 
 
 def predict_logits(model: UNet, pos4, sigma, q, h, center):
     x = model.featurize(pos4, sigma, q, h, center)
-    return model.forward(x)
+    return model.forward(x, keep=False)
 
 
 def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1,

@@ -9,7 +9,7 @@ import ctypes as C
 
 from . import _lib
 
-NN_EXPORTS = ["vesis_nn_conv3_fwd", "vesis_nn_wgrad_workspace", "vesis_nn_conv3_wgrad",
+NN_EXPORTS = ["vesis_nn_conv3_fwd", "vesis_nn_conv3_fwd_upcat", "vesis_nn_wgrad_workspace", "vesis_nn_conv3_wgrad",
               "vesis_nn_prep_weights", "vesis_nn_relu_bwd", "vesis_nn_pool2", "vesis_nn_up2",
               "vesis_nn_concat", "vesis_nn_split", "vesis_nn_add", "vesis_nn_head_fwd",
               "vesis_nn_head_bwd",
@@ -28,6 +28,7 @@ def lib():
         L = _lib.load()
         P, I, I64, F, D = C.c_void_p, C.c_int, C.c_int64, C.c_float, C.c_double
         L.vesis_nn_conv3_fwd.argtypes = [P, P, P, P, P, I, I, I, I, I, I, I]
+        L.vesis_nn_conv3_fwd_upcat.argtypes = [P, P, I, P, I, P, P, P, I, I, I, I, I, I]
         L.vesis_nn_wgrad_workspace.argtypes = [I, I, I, I, I, I, C.POINTER(C.c_size_t)]
         L.vesis_nn_conv3_wgrad.argtypes = [P, P, P, P, P, P, C.c_size_t, I, I, I, I, I, I]
         L.vesis_nn_prep_weights.argtypes = [P, P, I, I, P, P]

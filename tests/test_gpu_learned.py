@@ -32,6 +32,50 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+@pytest.mark.parametrize("n,ca,cb,cout,relu", [(16, 64, 32, 32, 1), (20, 32, 16, 64, 0),
+                                               (32, 256, 128, 128, 1), (36, 64, 32, 32, 1)])
+def test_conv_upcat_equals_conv_of_the_concatenated_upsample(n, ca, cb, cout, relu):
+    """The decoder convolution that reads [up2(a) | b] in place equals, bit
+    for bit, the convolution of the materialised concatenation (both
+    output-channel tilings, grids ragged against the 32 x 4 x MT tiles)."""
+    import torch
+
+    from paper_2208_05524_amd import nn
+    r = np.random.default_rng(n * 1000 + ca + cb)
+    a = _dev_bf16(r.standard_normal((1, n // 2, n // 2, n // 2, ca)))
+    b = _dev_bf16(r.standard_normal((1, n, n, n, cb)))
+    w = _dev_bf16(0.1 * r.standard_normal((27, cout, ca + cb)))
+    bias = torch.tensor(r.standard_normal(cout).astype(np.float32), device="cuda")
+    L = nn.lib()
+    up = torch.empty((1, n, n, n, ca), dtype=torch.bfloat16, device="cuda")
+    cat = torch.empty((1, n, n, n, ca + cb), dtype=torch.bfloat16, device="cuda")
+    y0 = torch.empty((1, n, n, n, cout), dtype=torch.bfloat16, device="cuda")
+    y1 = torch.full((1, n, n, n, cout), float("nan"), dtype=torch.bfloat16, device="cuda")
+    nn.check(L.vesis_nn_up2(_stream(), nn.ptr(a), nn.ptr(up), 1, n, n, n, ca, 0), "up")
+    nn.check(L.vesis_nn_concat(_stream(), nn.ptr(up), ca, nn.ptr(b), cb, nn.ptr(cat), n ** 3), "cat")
+    nn.check(L.vesis_nn_conv3_fwd(_stream(), nn.ptr(cat), nn.ptr(w), nn.ptr(bias), nn.ptr(y0), 1,
+                                  n, n, n, ca + cb, cout, relu), "conv")
+    nn.check(L.vesis_nn_conv3_fwd_upcat(_stream(), nn.ptr(a), ca, nn.ptr(b), cb, nn.ptr(w),
+                                        nn.ptr(bias), nn.ptr(y1), 1, n, n, n, cout, relu), "upcat")
+    torch.cuda.synchronize()
+    assert torch.equal(y0.view(torch.int16), y1.view(torch.int16))
+
+
+def test_inference_forward_equals_training_forward():
+    """The network's inference pass (decoder inputs read in place) gives the
+    training forward's logits bit for bit (64^3: every decoder level >= 16)."""
+    import torch
+
+    from paper_2208_05524_amd.learned import IN_C, UNet
+    m = UNet(64, seed=3)
+    r = np.random.default_rng(7)
+    x = _dev_bf16(np.abs(r.standard_normal((1, 64, 64, 64, IN_C))))
+    l0 = m.forward(x).clone()
+    l1 = m.forward(x, keep=False)
+    torch.cuda.synchronize()
+    assert torch.equal(l0, l1)
+
+
 @pytest.mark.parametrize("n,cin,cout,relu", [(8, 32, 64, 1), (6, 16, 32, 0), (5, 96, 32, 1),
                                              (16, 32, 64, 1), (20, 32, 32, 1), (18, 16, 64, 0),
                                              (24, 96, 32, 1)])
@@ -62,6 +106,37 @@ def test_conv_forward_matches_reference(n, cin, cout, relu):
     err = np.abs(y - ref)
     lim = 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max()
     log("conv max err/lim", float((err / lim).max()))
+    assert np.all(err <= lim)
+
+
+@pytest.mark.parametrize("d,h,w,cin,cout", [(128, 6, 36, 16, 64), (256, 6, 36, 16, 32),
+                                             (24, 6, 36, 32, 64)])
+def test_conv_forward_tilings_match_reference(d, h, w, cin, cout):
+    """The three LDS tilings (MT = 2, NT = 2; MT = 4, NT = 1; and MT = NT = 1
+    for layers with fewer workgroups than CUs), chosen by the grid's size: long
+    grids ragged in x and y against the 32 x 4 x MT tiles, every output
+    within BF16 rounding of the FP64 convolution of the same inputs."""
+    import torch
+
+    from oracle import unet
+    from paper_2208_05524_amd import nn
+    r = np.random.default_rng(d + cout)
+    x = _bf(r.standard_normal((1, d, h, w, cin)))
+    wt = _bf(0.1 * r.standard_normal((27, cout, cin)))
+    b = r.standard_normal(cout).astype(np.float32)
+    ref = unet.conv(torch.as_tensor(x).permute(0, 4, 1, 2, 3), unet.to_torch_weight(wt),
+                    torch.as_tensor(b.astype(np.float64)), relu=True)
+    ref = ref.permute(0, 2, 3, 4, 1).numpy()
+    L = nn.lib()
+    xd, wd = _dev_bf16(x), _dev_bf16(wt)
+    bd = torch.tensor(b, device="cuda")
+    yd = torch.empty((1, d, h, w, cout), dtype=torch.bfloat16, device="cuda")
+    nn.check(L.vesis_nn_conv3_fwd(_stream(), nn.ptr(xd), nn.ptr(wd), nn.ptr(bd), nn.ptr(yd), 1, d,
+                                  h, w, cin, cout, 1), "conv")
+    y = yd.float().cpu().numpy()
+    err = np.abs(y - ref)
+    lim = 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+    log("conv tiling", (d, h, w, cin, cout), "max err/lim", float((err / lim).max()))
     assert np.all(err <= lim)
 
 
