@@ -81,6 +81,43 @@ def test_relax_fp32_trajectory_stays_close_to_oracle():
     assert rg.G_final == pytest.approx(ro.G_final, rel=1e-5)
 
 
+def test_relax_with_solute_terms_matches_oracle_fp64():
+    """Six outer iterations of a 30-atom chain with every term of Eq. "Gss"
+    (bonds, bending, torsion, non-bonded LJ and Coulomb), FP64 densities:
+    same iteration, sweep and retry counts, positions within 1e-6 nm, labels
+    identical, G within 1e-6."""
+    natoms, iters = 30, 6
+    w = synth.random_small(32, natoms, 23, h=0.07)
+    w.xyz = synth.globule(natoms, seed=23)
+    w.bonds, w.bond_r0, w.bond_k = synth.chain_bonds(natoms, k=1.0e3)
+    top = synth.chain_topology([(0, natoms)], seed=23)
+    ss = oracle.SoluteTerms(top.angles, top.theta0, top.k_angle, top.torsions, top.c, top.psi,
+                            top.nonbonded, top.sigma_ss, top.eps_ss, top.exclusions)
+    s = oracle.System.from_workload(w, with_bonds=True, ss=ss)
+    phi = s.init_tight()
+    ctx = gpu_context(w, precision=64, with_bonds=True)
+    ctx.set_topology(top)
+    ctx.allocate_workspace()
+    ctx.init_labels("tight", 1.0)
+    from paper_2208_05524_amd import default_mobility
+    xo = w.xyz.copy()
+    opts = oracle.RelaxOpts(max_iters=iters, persist=100, max_sweeps=10000, pad=0,
+                            tol_grad=1e-4, tol_energy=1e-5)
+    rc_o, ro = s.relax(xo, phi, opts, oracle.default_mobility(0.1))
+    rc_g, rg = ctx.relax(default_mobility(0.1), max_iters=iters, persist=100, max_sweeps=10000)
+    xg, lg = ctx.positions(), ctx.labels()
+    log("oracle", ro.iters, ro.stop_reason, ro.sweeps, ro.retries, ro.G_final,
+        "gpu", rg.iters, rg.stop_reason, rg.sweeps, rg.retries, rg.G_final,
+        "max |dx|", float(np.abs(xg - xo).max()))
+    assert rc_o == rc_g
+    assert (ro.iters, ro.stop_reason, ro.retries, ro.sweeps) == \
+        (rg.iters, rg.stop_reason, rg.retries, rg.sweeps)
+    assert rg.G_final == pytest.approx(ro.G_final, rel=1e-6)
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-6)
+    assert np.array_equal(lg, phi)
+    ctx.close()
+
+
 def test_relax_two_atoms_reaches_paper_state():
     """Experiment with r0 = 8 A (paper units): bond 8.00 A, atoms at +-4.00
     A, G within 3 % of the printed 33.93 k_B T, and within 1e-6 of the
