@@ -426,22 +426,36 @@ __global__ void batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int
 // ------------------------------------------------------------ reductions
 
 // h^3-less sums of U_LJ and U_CFA over solvent cells (FP64).
+// Sums of U_LJ and U_CFA over solvent cells.  A wavefront takes whole
+// x-rows, two at a time (lanes along x: each load instruction reads 512
+// contiguous bytes), rows strided over the grid; U is loaded for every cell
+// and selected by its label bit, so the loads do not wait for the labels.
+// Per-lane FP64 sums in a fixed order, then a fixed tree per workgroup.
 __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uint32_t* bits,
                                                                const double* ulj,
                                                                const double* ucfa,
                                                                double* partial) {
     __shared__ double sh[RED_WG];
     double sa = 0.0, sb = 0.0;
-    const int64_t ncell = g.ncell();
-    const int64_t stride = (int64_t)gridDim.x * RED_WG;
-    for (int64_t c = (int64_t)blockIdx.x * RED_WG + threadIdx.x; c < ncell; c += stride) {
-        const int x = (int)(c % g.n);
-        const int64_t r = c / g.n;
-        const int y = (int)(r % g.n), z = (int)(r / g.n);
-        const uint32_t word = bits[g.row(y, z) + 1 + (x >> 5)];
-        if ((word >> (x & 31)) & 1u) {
-            sa += ulj[c];
-            sb += ucfa[c];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = g.n, nrows = g.n * g.n;
+    const int wstride = gridDim.x * (RED_WG / 64);
+    for (int r0 = blockIdx.x * (RED_WG / 64) + wv; r0 < nrows; r0 += 2 * wstride) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = r0 + k * wstride;
+            if (r >= nrows) break;
+            const int y = r % n, z = r / n;
+            const uint32_t* wrow = bits + g.row(y, z) + 1;
+            const double* a = ulj + (int64_t)r * n;
+            const double* b = ucfa + (int64_t)r * n;
+#pragma unroll 4
+            for (int x = lane; x < n; x += 64) {
+                const double va = a[x], vb = b[x];
+                const bool solvent = (wrow[x >> 5] >> (x & 31)) & 1u;
+                sa += solvent ? va : 0.0;
+                sb += solvent ? vb : 0.0;
+            }
         }
     }
     sa = block_sum(sa, sh);
