@@ -174,6 +174,52 @@ def solute_solute(w, reps: int = 5):
             "energy": {k: e[k] for k in ("bond", "bend", "torsion", "vdw_ss", "elec_ss")}}
 
 
+def chain_config(rounds: int = 3):
+    """The 1,000-atom chain on 128^3 cells (0.05 nm): time to equilibrium of
+    the interface (density, far field and colour sweeps, from fresh
+    positions) from the tight and from the loose start, FP32 densities."""
+    import torch
+
+    import synth
+    from paper_2208_05524_amd import Context
+    w = synth.chain_1000()
+    ctx = Context(0)
+    ctx.setup(w, precision=32, with_bonds=True)
+    out = {"atoms": w.natoms, "grid": w.n}
+    for mode, param in (("tight", 1.0), ("loose", 2.6)):
+        times = []
+        for r in range(rounds + 1):
+            ctx.set_positions(w.xyz)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.init_labels(mode, param)
+            rc, st = ctx.minimize()
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(time.perf_counter() - t0)
+        ms = 1e3 * sum(times) / len(times)
+        out[mode] = {"time_to_equilibrium_ms": ms, "sweeps": st["sweeps"], "flips": st["flips"],
+                     "us_per_sweep": 1e3 * ms / max(st["sweeps"], 1), "G": ctx.energy()["total"]}
+    ctx.close()
+    return out
+
+
+def cpu_chain_equilibrium():
+    """The oracle's full run on the same 1,000-atom chain and start: FP64
+    density over the 128^3 grid, far field, colour sweeps to equilibrium."""
+    import oracle
+    import synth
+    w = synth.chain_1000()
+    s = oracle.System.from_workload(w)
+    t0 = time.perf_counter()
+    ulj, ucfa = s.density_grid()
+    s.far_field()
+    phi = s.init_tight()
+    rc, st, _, _ = s.minimize_colour(phi, ulj + ucfa)
+    return {"time_to_equilibrium_s": time.perf_counter() - t0, "sweeps": st["sweeps"],
+            "start": "tight"}
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """Oracle density (FP64, OpenMP) over whole z-planes of the same grid
     until about budget_s seconds of work; returns atom-gridpoint pairs/s."""
@@ -203,7 +249,9 @@ def cpu_baseline(w, budget_s: float = 12.0):
                 break
     except OSError:
         pass
+    chain = cpu_chain_equilibrium()
     return {"value": pairs / dt, "unit": "atom·gridpt/s", "cores": cores, "kind": "oracle",
+            "chain_1000_128": chain,
             "sample": f"FP64 oracle density over {planes} z-planes ({planes * n * n} cells) of "
                       f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s on {cores} threads of "
                       f"{model}; the GPU value is a whole hot-path step, whose density work "
@@ -337,6 +385,9 @@ def main():
         "atom_step": {"accepted": last["accepted"], "retries": last["retries"]},
         "G_total": last["e"]["total"],
     }
+    log("1,000-atom chain at 128^3 ...")
+    out["chain_1000_128"] = chain_config()
+    log(f"chain_1000_128: {out['chain_1000_128']}")
     log("solute-solute terms ...")
     out["solute_solute"] = solute_solute(w)
     log(f"solute_solute: {out['solute_solute']}")
