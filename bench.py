@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--relax-iters", type=int, default=200,
                     help="after the timed steps, run this many outer iterations of the full "
                          "alternation (Steps 2-5) from the same start and report them (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 1,000-atom chain and the solute-solute sections (profiling "
+                         "runs that should see the two-globule kernels only)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -385,12 +388,13 @@ def main():
         "atom_step": {"accepted": last["accepted"], "retries": last["retries"]},
         "G_total": last["e"]["total"],
     }
-    log("1,000-atom chain at 128^3 ...")
-    out["chain_1000_128"] = chain_config()
-    log(f"chain_1000_128: {out['chain_1000_128']}")
-    log("solute-solute terms ...")
-    out["solute_solute"] = solute_solute(w)
-    log(f"solute_solute: {out['solute_solute']}")
+    if not args.no_extra:
+        log("1,000-atom chain at 128^3 ...")
+        out["chain_1000_128"] = chain_config()
+        log(f"chain_1000_128: {out['chain_1000_128']}")
+        log("solute-solute terms ...")
+        out["solute_solute"] = solute_solute(w)
+        log(f"solute_solute: {out['solute_solute']}")
     if not args.no_batch:
         log("batch comparison ...")
         out["batch"] = batch_comparison()
