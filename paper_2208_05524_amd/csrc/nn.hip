@@ -231,6 +231,123 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const ConvIn in,
     }
 }
 
+// Prefetching variant for the large layers (MT = 4 z-layers, one tile of
+// 32 output channels): per chunk of 16 input channels both the input tile
+// and the chunk's weights (27 taps x 32 output channels x 16 channels) are
+// staged in LDS, and the next chunk's are loaded into registers while the
+// current one is multiplied, so the matrix loop reads LDS only and the
+// global loads overlap it (loads issued inside the loop would have to wait
+// for the prefetch: they retire in order).  The products and their order
+// are those of conv3_fwd_lds_kernel<4, 1>, so the results are identical.
+template <bool RELU>
+__global__ __launch_bounds__(CWG) void conv3_fwd_pf_kernel(const ConvIn in,
+                                                           const __bf16* __restrict__ Wt,
+                                                           const float* __restrict__ bias,
+                                                           __bf16* __restrict__ Y, int N, int D,
+                                                           int H, int W, int Cin, int Cout) {
+    constexpr int MT = 4, TZ = MT, HZ = TZ + 2, HPOS = HZ * HY * HX;
+    constexpr int NA = (2 * HPOS + CWG - 1) / CWG;  // input 16-byte pieces per thread
+    constexpr int WQ = 27 * 32 * 2;                  // weight 16-byte pieces per chunk
+    constexpr int NW = (WQ + CWG - 1) / CWG;
+    __shared__ __attribute__((aligned(16))) __bf16 tile[HPOS * 16];
+    __shared__ __attribute__((aligned(16))) __bf16 wts[27 * 32 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 31, half = lane >> 5;
+    const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
+    const int x0 = (blockIdx.x % ntx) * TX;
+    const int y0 = ((int)(blockIdx.x / ntx) % nty) * TY;
+    const int co0 = blockIdx.y * 32;
+    const int z0 = ((int)blockIdx.z % ntz) * TZ;
+    const int nb = (int)blockIdx.z / ntz;
+    const int cb = Cin - in.ca;
+    const int Da = in.up ? D / 2 : D, Ha = in.up ? H / 2 : H, Wa = in.up ? W / 2 : W;
+    f32x16 acc[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) acc[i] = f32x16{};
+    uint4 pa[NA], pw[NW];
+    auto fetch = [&](int c0) {
+        const bool from_a = c0 < in.ca;  // uniform over the workgroup
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int e = threadIdx.x + k * CWG;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (e < 2 * HPOS) {
+                const int hp = e >> 1, hh = e & 1;
+                const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
+                const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+                if (xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D) {
+                    const __bf16* src;
+                    if (from_a) {
+                        const int za = in.up ? zz >> 1 : zz, ya = in.up ? yy >> 1 : yy,
+                                  xa = in.up ? xx >> 1 : xx;
+                        src = in.a + ((((int64_t)nb * Da + za) * Ha + ya) * Wa + xa) * in.ca + c0;
+                    } else {
+                        src = in.b + ((((int64_t)nb * D + zz) * H + yy) * W + xx) * cb +
+                              (c0 - in.ca);
+                    }
+                    v = *reinterpret_cast<const uint4*>(src + 8 * hh);
+                }
+            }
+            pa[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int e = threadIdx.x + k * CWG;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (e < WQ) {
+                const int tap = e >> 6, co = (e >> 1) & 31, hh = e & 1;
+                v = *reinterpret_cast<const uint4*>(Wt + ((int64_t)tap * Cout + co0 + co) * Cin +
+                                                    c0 + 8 * hh);
+            }
+            pw[k] = v;
+        }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+        __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int e = threadIdx.x + k * CWG;
+            if (e < 2 * HPOS) *reinterpret_cast<uint4*>(&tile[(e >> 1) * 16 + 8 * (e & 1)]) = pa[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int e = threadIdx.x + k * CWG;
+            if (e < WQ) *reinterpret_cast<uint4*>(&wts[(e >> 1) * 16 + 8 * (e & 1)]) = pw[k];
+        }
+        __syncthreads();
+        if (c0 + 16 < Cin) fetch(c0 + 16);
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // halo offsets 0..2
+            const bf16x8 b = load8(&wts[(tap * 32 + row) * 16 + 8 * half]);
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int hp = ((i + dz) * HY + (wv + dy)) * HX + (row + dx);
+                const bf16x8 a = load8(&tile[hp * 16 + 8 * half]);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+            }
+        }
+    }
+    // D[8 (r/4) + 4 half + r%4][row]: x = x0 + that, channel co0 + row
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int z = z0 + i, y = y0 + wv;
+        if (z >= D || y >= H) continue;
+        const int64_t rowbase = (((int64_t)nb * D + z) * H + y) * W;
+        const int co = co0 + row;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int x = x0 + 8 * (r / 4) + 4 * half + (r % 4);
+            if (x >= W) continue;
+            float v = acc[i][r] + bv;
+            if (RELU) v = v > 0.f ? v : 0.f;
+            Y[(rowbase + x) * Cout + co] = (__bf16)v;
+        }
+    }
+}
+
 // Weight gradient partials: for one tap, a 32 x 32 (co, ci) tile and one
 // chunk of positions: part[chunk][tap][co][ci] = sum_p dY[p][co] X[p+off][ci].
 // Per step a wavefront takes 16 consecutive positions: each lane loads 8
@@ -659,35 +776,34 @@ inline const __bf16* B(const void* p) { return static_cast<const __bf16*>(p); }
 inline __bf16* Bm(void* p) { return static_cast<__bf16*>(p); }
 bool dims_ok(int N, int D, int H, int W) { return N > 0 && D > 0 && H > 0 && W > 0; }
 
-// LDS-staged tiles: 4 x-rows (y) x MT z-layers x 32 positions, by 32 NT
-// output channels.  MT = 2, NT = 2 (or MT = 4, NT = 1 for 32 output
-// channels) reuse each staged operand most; a layer that would then have
-// fewer workgroups than CUs (the coarsest level) takes MT = NT = 1.
+// LDS-staged tiles of 4 x-rows (y) x MT z-layers x 32 positions, one tile of
+// 32 output channels per workgroup.  Layers with at least as many such
+// workgroups (MT = 4) as CUs take the prefetching kernel when they have 64
+// or more output channels; with 32 (the finest level) the operand reads
+// from LDS bound the loop and the plain kernel, at twice the workgroups per
+// CU, is as fast.  The coarsest levels take MT = 1 (more, smaller
+// workgroups).
 void launch_conv3_lds(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
                       int n, int d, int h, int wd, int cin, int cout, int relu) {
     const unsigned nt_xy = (unsigned)(((wd + TX - 1) / TX) * ((h + TY - 1) / TY));
-    const int64_t big = (int64_t)nt_xy * (cout % 64 == 0 ? cout / 64 * ((d + 1) / 2)
-                                                         : cout / 32 * ((d + 3) / 4)) * n;
+    const int64_t big = (int64_t)nt_xy * (cout / 32) * ((d + 3) / 4) * n;
+    const dim3 grid4(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + 3) / 4)));
     if (big < 256) {
         const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * d));
         if (relu)
             hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
         else
             hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-    } else if (cout % 64 == 0) {
-        constexpr int MT = 2;
-        const dim3 grid(nt_xy, (unsigned)(cout / 64), (unsigned)(n * ((d + MT - 1) / MT)));
+    } else if (cout >= 64) {
         if (relu)
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            hipLaunchKernelGGL((conv3_fwd_pf_kernel<true>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
         else
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 2, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            hipLaunchKernelGGL((conv3_fwd_pf_kernel<false>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
     } else {
-        constexpr int MT = 4;
-        const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + MT - 1) / MT)));
         if (relu)
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<4, 1, true>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
         else
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<MT, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+            hipLaunchKernelGGL((conv3_fwd_lds_kernel<4, 1, false>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
     }
 }
 }  // namespace

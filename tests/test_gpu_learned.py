@@ -112,8 +112,9 @@ def test_conv_forward_matches_reference(n, cin, cout, relu):
 @pytest.mark.parametrize("d,h,w,cin,cout", [(128, 6, 36, 16, 64), (256, 6, 36, 16, 32),
                                              (24, 6, 36, 32, 64)])
 def test_conv_forward_tilings_match_reference(d, h, w, cin, cout):
-    """The three LDS tilings (MT = 2, NT = 2; MT = 4, NT = 1; and MT = NT = 1
-    for layers with fewer workgroups than CUs), chosen by the grid's size: long
+    """The three LDS-tiled kernels (the prefetching one for 64 or more output
+    channels, MT = 4 for 32, and MT = 1 for layers with fewer workgroups
+    than CUs), chosen by the grid's size and channels: long
     grids ragged in x and y against the 32 x 4 x MT tiles, every output
     within BF16 rounding of the FP64 convolution of the same inputs."""
     import torch
