@@ -65,3 +65,29 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.replace("oracles", ""), f
+
+
+def test_new_calls_reject_bad_arguments_before_touching_a_device():
+    """The solute-solute set-up calls refuse a null context, and the fused
+    decoder convolution refuses odd or too narrow grids and channel counts
+    that are not multiples of 16 (or of 32 for the outputs), all before any
+    device work (so this runs without a GPU)."""
+    from paper_2208_05524_amd import _lib, nn
+    lib = _lib.load()
+    one = (ctypes.c_int32 * 4)(0, 1, 2, 3)
+    val = (ctypes.c_double * 7)(*([1.0] * 7))
+    assert lib.vesis_set_angles(None, 1, one, val, val) == -1
+    assert lib.vesis_set_torsions(None, 1, one, val, val) == -1
+    assert lib.vesis_set_nonbonded(None, 1, None, None, 0, None) == -1
+    L = nn.lib()
+    p = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails its checks
+    bad = [(16, 64, 32, 32, 15),   # odd grid
+           (16, 64, 32, 32, 8),    # narrower than 16
+           (16, 60, 32, 32, 16),   # ca % 16
+           (16, 64, 20, 32, 16),   # cb % 16
+           (16, 64, 32, 48, 16)]   # cout % 32
+    for d, ca, cb, cout, wd in bad:
+        assert L.vesis_nn_conv3_fwd_upcat(None, p, ca, p, cb, p, None, p, 1, d, d, wd, cout,
+                                          1) == -1
+    assert L.vesis_nn_conv3_fwd_upcat(None, None, 64, p, 32, p, None, p, 1, 16, 16, 16, 32,
+                                      1) == -1
