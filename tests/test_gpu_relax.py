@@ -118,36 +118,39 @@ def test_relax_with_solute_terms_matches_oracle_fp64():
     ctx.close()
 
 
-def test_relax_two_atoms_reaches_paper_state():
-    """Experiment with r0 = 8 A (paper units): bond 8.00 A, atoms at +-4.00
-    A, G within 3 % of the printed 33.93 k_B T, and within 1e-6 of the
-    oracle's alternation from the same start."""
+@pytest.mark.parametrize("case", ["r0_8", "r0_3"])
+def test_relax_two_atoms_reaches_paper_state(case):
+    """The paper's two-atom experiments (paper units; r0 = 8 A: the spheres
+    stay apart, r0 = 3 A: they merge), from 14 A apart: bond at the printed
+    length, atoms as printed, G within 3 % of the printed free energy, and
+    within 1e-6 of the oracle's alternation from the same start."""
     with open(os.path.join(HERE, "golden", "two_atom_tables.json")) as f:
         g = json.load(f)
     m = g["model"]
-    w = synth.Workload(name="two_atoms_r0_8", n=48, h=16.0 / 48, center=np.zeros(3),
+    r0 = g[case]["bond_length"]
+    w = synth.Workload(name="two_atoms_" + case, n=48, h=16.0 / 48, center=np.zeros(3),
                        xyz=np.array([[7.0, 0.0, 0.0], [-7.0, 0.0, 0.0]]), q=np.zeros(2),
                        sigma=np.full(2, m["sigma"]), eps=np.full(2, m["eps"]),
                        params=synth.paper_units_params(), init_mode="tight", init_param=1.0,
                        precision=64, bonds=np.array([[0, 1]], np.int32),
-                       bond_r0=np.array([8.0]), bond_k=np.array([m["bond_A"]]))
+                       bond_r0=np.array([r0]), bond_k=np.array([m["bond_A"]]))
     ctx = gpu_context(w, with_bonds=True)
     ctx.init_labels("tight", 1.0)
     from paper_2208_05524_amd import default_mobility
     rc, rep = ctx.relax(default_mobility(1.0), max_iters=3000, persist=100, max_sweeps=10000)
     x = ctx.positions()
-    log("gpu relax", rc, rep.iters, rep.stop_reason, rep.G_final, x[:, 0])
+    log("gpu relax", case, rc, rep.iters, rep.stop_reason, rep.G_final, x[:, 0])
     assert rc == 0 and rep.stop_reason in (1, 2)
-    assert np.linalg.norm(x[0] - x[1]) == pytest.approx(8.0, abs=0.02)
-    np.testing.assert_allclose(x, g["r0_8"]["final_positions"], atol=0.05)
-    assert rep.G_final == pytest.approx(g["r0_8"]["free_energy"], rel=0.03)
+    assert np.linalg.norm(x[0] - x[1]) == pytest.approx(r0, abs=0.02)
+    np.testing.assert_allclose(x, g[case]["final_positions"], atol=0.05)
+    assert rep.G_final == pytest.approx(g[case]["free_energy"], rel=0.03)
     s = oracle_system(w, with_bonds=True)
     xo = w.xyz.copy()
     phi = s.init_tight()
     opts = oracle.RelaxOpts(max_iters=3000, persist=100, max_sweeps=10000, pad=0,
                             tol_grad=1e-4, tol_energy=1e-5)
     _, ro = s.relax(xo, phi, opts, oracle.default_mobility(1.0))
-    log("oracle relax", ro.iters, ro.stop_reason, ro.G_final, xo[:, 0])
+    log("oracle relax", case, ro.iters, ro.stop_reason, ro.G_final, xo[:, 0])
     assert rep.iters == ro.iters
     assert rep.G_final == pytest.approx(ro.G_final, rel=1e-6)
     np.testing.assert_allclose(x, xo, rtol=0, atol=1e-6)
