@@ -155,13 +155,33 @@ __device__ inline void load_rows(const Grid& g, const uint32_t* bits, int w, int
     }
 }
 
-// S_j = sum over offsets 0 < |o|^2 <= 8 of w_{|o|^2} phi_{j+o} for the cell
-// at bit b of the lane's word, via integer counts per squared offset taken
-// from 5-bit windows (bit 0 = x-2, bit 2 = x) of the preloaded rows.
-__device__ inline double stencil_sum(const Stencil& sc, const Rows25& R, int b) {
-    int net[9];
+// Per row of Rows25, the labels of cells x0 - 2 .. x0 + 61 (x0 = 32 w) as two
+// words: bit j of (hi:lo) is cell x0 - 2 + j, so the 5-cell window of the
+// cell at bit b (bit 0 = x - 2, bit 2 = x) is the low 5 bits of
+// alignbit(hi, lo, b).  Built once per word, shared by its candidates.
+struct Win25 {
+    uint32_t lo[25], hi[25];
+};
+
+__device__ inline void make_windows(const Rows25& R, Win25& W) {
 #pragma unroll
-    for (int s = 0; s < 9; ++s) net[s] = 0;
+    for (int k = 0; k < 25; ++k) {
+        W.lo[k] = __builtin_amdgcn_alignbit(R.c[k], R.l[k], 30u);
+        W.hi[k] = __builtin_amdgcn_alignbit(R.r[k], R.c[k], 30u);
+    }
+}
+
+// S_j = sum over offsets 0 < |o|^2 <= 8 of w_{|o|^2} phi_{j+o} for the cell
+// at bit b of the lane's word.  cnt[s] counts the solvent neighbours at
+// squared offset s, from the window of each row: for a row at dy^2 + dz^2 =
+// q, the centre bit lies at s = q, the two bits at dx = +-1 at s = q + 1 and
+// the two at dx = +-2 at s = q + 4.  With N_s offsets at squared distance s,
+// sum_{|o|^2 = s} phi = 2 cnt[s] - N_s (phi = +1 solvent, -1 solute).
+__device__ inline double stencil_sum(const Stencil& sc, const Win25& W, int b) {
+    constexpr int N[9] = {0, 6, 12, 8, 6, 24, 24, 0, 12};
+    int cnt[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) cnt[s] = 0;
     int k = 0;
 #pragma unroll
     for (int dz = -2; dz <= 2; ++dz) {
@@ -169,18 +189,16 @@ __device__ inline double stencil_sum(const Stencil& sc, const Rows25& R, int b) 
         for (int dy = -2; dy <= 2; ++dy) {
             const int q = dy * dy + dz * dz;
             if (q > 8) continue;
-            const uint32_t hi = b >= 2 ? R.r[k] : R.c[k];
-            const uint32_t lo = b >= 2 ? R.c[k] : R.l[k];
-            const uint32_t v = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b >= 2 ? b - 2 : b + 30)) & 31u;
-            if (q > 0) net[q] += ((v >> 2) & 1u) ? 1 : -1;
-            if (q + 1 <= 8) net[q + 1] += 2 * __popc(v & 0xAu) - 2;
-            if (q + 4 <= 8) net[q + 4] += 2 * __popc(v & 0x11u) - 2;
+            const uint32_t v = __builtin_amdgcn_alignbit(W.hi[k], W.lo[k], (uint32_t)b);
+            if (q > 0) cnt[q] += __popc(v & 0x4u);
+            if (q + 1 <= 8) cnt[q + 1] += __popc(v & 0xAu);
+            if (q + 4 <= 8) cnt[q + 4] += __popc(v & 0x11u);
             ++k;
         }
     }
     double S = 0.0;
 #pragma unroll
-    for (int s = 1; s <= 8; ++s) S += sc.w[s] * (double)net[s];
+    for (int s = 1; s <= 8; ++s) S += sc.w[s] * (double)(2 * cnt[s] - N[s]);
     return S;
 }
 
@@ -196,23 +214,37 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
     const double py = centre_coord(g.cy, g.L, y, g.h);
     const double pz = centre_coord(g.cz, g.L, z, g.h);
     double lj = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-    for (int64_t i = t; i < a.n; i += FWG) {
-        const double4 p = a.pos[i];
-        const double4 q = a.prm64[i];
-        const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
-        const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
-        // 1/r from the hardware estimate and two Newton steps (full FP64 accuracy)
-        double ir = __builtin_amdgcn_rsq(r2);
-        ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
-        ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
-        const double ir2 = ir * ir;
-        const double s = q.x * ir2;
-        const double s3 = s * s * s;
-        lj += q.y * (s3 * s3 - s3);
-        const double f = q.z * ir2 * ir;
-        ex += f * dx;
-        ey += f * dy;
-        ez += f * dz;
+    // TU atoms per thread in flight: their loads are issued together (indices
+    // clamped to the last atom) and the atoms are added in index order with
+    // no branch between them; a slot past the last atom adds +0.0, so each
+    // thread's sum is the plain sequential one.
+    constexpr int TU = 8;
+    for (int64_t i0 = t; i0 < a.n; i0 += TU * FWG) {
+        double4 P[TU], Q[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+            const int64_t i = i0 + (int64_t)u * FWG < a.n ? i0 + (int64_t)u * FWG : a.n - 1;
+            P[u] = a.pos[i];
+            Q[u] = a.prm64[i];
+        }
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+            const bool in = i0 + (int64_t)u * FWG < a.n;
+            const double dx = px - P[u].x, dy = py - P[u].y, dz = pz - P[u].z;
+            const double r2 = fmax(dx * dx + dy * dy + dz * dz, ph.r2min);
+            // 1/r from the hardware estimate and two Newton steps (full FP64 accuracy)
+            double ir = __builtin_amdgcn_rsq(r2);
+            ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+            ir = ir * fma(-0.5 * r2, ir * ir, 1.5);
+            const double ir2 = ir * ir;
+            const double s = Q[u].x * ir2;
+            const double s3 = s * s * s;
+            lj += in ? Q[u].y * (s3 * s3 - s3) : 0.0;
+            const double f = Q[u].z * ir2 * ir;
+            ex += in ? f * dx : 0.0;
+            ey += in ? f * dy : 0.0;
+            ez += in ? f * dz : 0.0;
+        }
     }
     sh[t] = lj;
     sh[FWG + t] = ex;
@@ -239,24 +271,26 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
 // --------------------------------------------------------------- flip pass
 
 // Activity stamps (one int per label word): a lane that flips cells of word
-// (w, y, z) in global pass P writes P into the words w-1..w+1 of the rows
+// (w, y, z) in global pass q writes q into the words w-1..w+1 of the rows
 // y-2..y+2, z-2..z+2, which hold every cell whose flip energy or band status
 // that flip can change.  The previous evaluation of a word in this colour was
-// pass P - ncol; if its stamp is older than that, nothing in its cells'
+// pass q - ncol; if its stamp is older than that, nothing in its cells'
 // neighbourhoods changed since then, every decision would repeat (no flip),
 // and the word is skipped.  The first sweep of a call evaluates every word.
-// One colour pass.  BATCH = false: one molecule, described by `one`; BATCH =
+// One colour pass of colour period P (2 or 3).  BATCH = false: one molecule, described by `one`; BATCH =
 // true: block b works on molecule block_mol[b] of `descs` (a molecule's
 // blocks are consecutive from slot0 / FWG, so a block never spans two).
 // In a batch, molecules flagged in `done` are skipped and the pass index is
 // *pass_base + gpass, so that one captured sequence of passes can be
 // replayed.
-template <bool BATCH>
+template <bool BATCH, int P>
 __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDesc* descs,
                                                         const int* block_mol, const int* done,
                                                         const int* pass_base, int colour,
                                                         int sweep, int gpass, int ncol) {
+    constexpr int K = (32 + P - 1) / P;  // cells of one colour in a word
     __shared__ double s_red[4 * FWG];
+    __shared__ double s_cs[K * FWG];     // c S_j of the near ties, slot-major
     __shared__ int s_leader;
     __shared__ int s_tie[4];
     if (BATCH) {
@@ -278,9 +312,8 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     int64_t* counters = D.counters;
     // a sweep that follows a sweep without flips has nothing to do
     if (sweep > 0 && sweep_flips[sweep - 1] == 0) return;
-    const int p = sc.p;
-    const int ca = colour % p, cb = (colour / p) % p, cc = colour / (p * p);
-    const int ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
+    const int ca = colour % P, cb = (colour / P) % P, cc = colour / (P * P);
+    const int ny = (g.n - cb + P - 1) / P, nz = (g.n - cc + P - 1) / P;
     const int64_t total = (int64_t)g.nwin * ny * nz;
     const int64_t tid = (int64_t)blockIdx.x * FWG - (BATCH ? D.slot0 : 0) + threadIdx.x;
     const bool active = tid < total;
@@ -288,48 +321,65 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     if (active) {
         w = (int)(tid % g.nwin);
         const int64_t r = tid / g.nwin;
-        y = cb + p * (int)(r % ny);
-        z = cc + p * (int)(r / ny);
+        y = cb + P * (int)(r % ny);
+        z = cc + P * (int)(r / ny);
     }
     const int x0 = 32 * w;
     uint32_t* rowc = bits + g.row(y, z);
     uint32_t C = 0, cand = 0;
-    const bool stale = gpass >= ncol && stamp[g.row(y, z) + 1 + w] < gpass - ncol;
-    if (active && !stale) {
+    if (active) {
+        // the stamp and the band words are loaded together, so that a word
+        // still to be evaluated waits for one round trip, not two
+        const int stw = stamp[g.row(y, z) + 1 + w];
         C = rowc[w + 1];
         const uint32_t Lw = rowc[w], Rw = rowc[w + 2];
-        const uint32_t left = (C << 1) | (Lw >> 31);
-        const uint32_t right = (C >> 1) | (Rw << 31);
         const uint32_t ym = bits[g.row(y - 1, z) + w + 1], yp = bits[g.row(y + 1, z) + w + 1];
         const uint32_t zm = bits[g.row(y, z - 1) + w + 1], zp = bits[g.row(y, z + 1) + w + 1];
+        const uint32_t fresh = (gpass >= ncol && stw < gpass - ncol) ? 0u : 0xffffffffu;
+        const uint32_t left = (C << 1) | (Lw >> 31);
+        const uint32_t right = (C >> 1) | (Rw << 31);
         const uint32_t band = (C ^ left) | (C ^ right) | (C ^ ym) | (C ^ yp) | (C ^ zm) | (C ^ zp);
-        cand = band & colour_mask(p, ca, x0) & valid_mask(g.n, x0);
+        // bits b with (x0 + b) mod P == ca: a fixed pattern shifted by the
+        // first such b
+        const uint32_t cmask = (P == 2 ? 0x55555555u : 0x49249249u) << (((ca - x0) % P + P) % P);
+        cand = band & cmask & valid_mask(g.n, x0) & fresh;
     }
     uint32_t flipmask = 0, tiemask = 0;
-    Rows25 R;
+    const int b0 = ((ca - x0) % P + P) % P;  // first bit of this colour in the word
+    const int t = threadIdx.x;
     if (cand) {
-        load_rows(g, bits, w, y, z, R);
-        while (cand) {
-            const int b = __ffs(cand) - 1;
-            cand &= cand - 1;
-            const int x = x0 + b;
-            const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-            const double S = stencil_sum(sc, R, b);
+        // The 5-cell windows of the 25 rows are built once for all of the
+        // word's candidates (at most K = ceil(32 / P)), taken in bit order.
+        // A near tie keeps c S_j in LDS for the FP64 decision below.
+        const int64_t cw = (int64_t)x0 + (int64_t)g.n * (y + (int64_t)g.n * z);
+        Win25 Wn;
+        {
+            Rows25 R;
+            load_rows(g, bits, w, y, z, R);
+            make_windows(R, Wn);
+        }
+        uint32_t cm = cand;
+        while (cm) {
+            const int b = __ffs(cm) - 1;
+            cm &= cm - 1;
+            const int64_t c = cw + b;
+            const double S = stencil_sum(sc, Wn, b);
             const double phi = ((C >> b) & 1u) ? 1.0 : -1.0;
             const double hU = ph.h3 * (ulj[c] + ucfa[c]);
             const double cS = sc.c * S;
             const double dE = phi * (cS - hU);
             const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
-            if (!(fabs(dE) > tol))
+            if (!(fabs(dE) > tol)) {
                 tiemask |= 1u << b;
-            else if (dE < 0.0)
+                s_cs[((b - b0) / P) * FWG + t] = cS;
+            } else if (dE < 0.0) {
                 flipmask |= 1u << b;
+            }
         }
     }
     // near ties: the whole workgroup resolves them one at a time in FP64,
     // lowest thread first; each cell's FP64 parts are computed once per atom
     // configuration and cached (2 x ncell doubles: LJ, then CFA; NaN = none)
-    const int t = threadIdx.x;
     while (__syncthreads_or(tiemask != 0u)) {
         if (t == 0) s_leader = FWG;
         __syncthreads();
@@ -355,9 +405,9 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
             }
         }
         if (t == leader) {
-            const double S = stencil_sum(sc, R, bL);
+            const double cS = s_cs[((bL - b0) / P) * FWG + t];
             const double phi = ((C >> bL) & 1u) ? 1.0 : -1.0;
-            const double dE = phi * (sc.c * S - ph.h3 * (lj + cfa));
+            const double dE = phi * (cS - ph.h3 * (lj + cfa));
             if (dE < 0.0) flipmask |= 1u << bL;
             tiemask &= ~(1u << bL);
             atomicAdd((unsigned long long*)&counters[0], 1ull);
@@ -597,8 +647,14 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     d.u64cache = u64cache;
     d.sweep_flips = sweep_flips;
     d.counters = counters;
-    hipLaunchKernelGGL(flip_pass_kernel<false>, dim3(nblk(total, FWG)), dim3(FWG), 0, st, d,
-                       nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, p * p * p);
+    if (p == 2)
+        hipLaunchKernelGGL((flip_pass_kernel<false, 2>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
+                           d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 8);
+    else if (p == 3)
+        hipLaunchKernelGGL((flip_pass_kernel<false, 3>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
+                           d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 27);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -623,8 +679,14 @@ hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, co
                                   int sweep, int gpass_off, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     MolDesc unused{};
-    hipLaunchKernelGGL(flip_pass_kernel<true>, dim3((unsigned)nblocks), dim3(FWG), 0, st, unused,
-                       descs, block_mol, done, pass_base, colour, sweep, gpass_off, p * p * p);
+    if (p == 2)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 2>), dim3((unsigned)nblocks), dim3(FWG), 0, st,
+                           unused, descs, block_mol, done, pass_base, colour, sweep, gpass_off, 8);
+    else if (p == 3)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 3>), dim3((unsigned)nblocks), dim3(FWG), 0, st,
+                           unused, descs, block_mol, done, pass_base, colour, sweep, gpass_off, 27);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
