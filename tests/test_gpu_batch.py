@@ -4,6 +4,8 @@ Each molecule of a batch must end exactly where the oracle's colour
 schedule takes it, and where a single-molecule call takes it: same labels,
 same sweep, flip and band counts, and energies within 1e-6.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -22,8 +24,18 @@ def _molecules():
 
 @pytest.mark.parametrize("variant", [0, 1])
 def test_batch_matches_oracle_and_single_contexts(variant):
+    _check_batch(_molecules(), variant)
+
+
+def test_batch_colour_period_two():
+    """The same with rho_s = 2 (colour period 2, 8 colours per sweep)."""
+    ws = [dataclasses.replace(w, params=dataclasses.replace(w.params, rho_s=2.0))
+          for w in _molecules()]
+    _check_batch(ws, 0)
+
+
+def _check_batch(ws, variant):
     from paper_2208_05524_amd import Batch
-    ws = _molecules()
     ctxs = [gpu_context(w) for w in ws]
     for c in ctxs:
         c.init_labels("tight", 1.0)
@@ -45,7 +57,7 @@ def test_batch_matches_oracle_and_single_contexts(variant):
                                                                  ost["band"])
         e = c.energy()
         ref = s.energy(phi, ulj, ucfa, far)
-        assert not energies_close(e, ref, 1e-6)
+        assert not energies_close(e, ref, 1e-6, volume_scale=True)
         # the single-molecule path from the same start
         single = gpu_context(w)
         single.init_labels("tight", 1.0)

@@ -132,6 +132,15 @@ def test_minimize_bit_exact_ragged(mode, param):
     _compare_minimisation(w, mode, param, 32)
 
 
+@pytest.mark.parametrize("rho_s,mode,param", [(2.0, "tight", 1.0), (1.5, "loose", 0.95)])
+def test_minimize_colour_period_two(rho_s, mode, param):
+    """Kernel radius rho_s <= 2: colour period p = 2 (8 colours, 16 cells of a
+    colour per 32-cell word), on a grid ragged against the words."""
+    w = ragged_small(seed=13, n=37, natoms=257)
+    w = dataclasses.replace(w, params=dataclasses.replace(w.params, rho_s=rho_s))
+    _compare_minimisation(w, mode, param, 32)
+
+
 def test_minimize_fp64_single_atom_64():
     """One LJ atom at the centre of [-1.5, 1.5]^3 nm, 64^3, FP64, loose sphere
     R0 = 1.2 nm."""
