@@ -207,6 +207,7 @@ constexpr int FWG = 256;  // flip-pass workgroup: four wavefronts
 // FP64 density parts at cell (x, y, z), summed by the whole workgroup:
 // thread t takes atoms t, t + FWG, ...; the partial sums meet in a fixed
 // tree in LDS, so the result does not depend on timing.  All threads call.
+template <int TU>
 __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x,
                                          int y, int z, double* sh, double& u_lj, double& u_cfa) {
     const int t = threadIdx.x;
@@ -217,8 +218,7 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
     // TU atoms per thread in flight: their loads are issued together (indices
     // clamped to the last atom) and the atoms are added in index order with
     // no branch between them; a slot past the last atom adds +0.0, so each
-    // thread's sum is the plain sequential one.
-    constexpr int TU = 8;
+    // thread's sum is the plain sequential one whatever TU is.
     for (int64_t i0 = t; i0 < a.n; i0 += TU * FWG) {
         double4 P[TU], Q[TU];
 #pragma unroll
@@ -397,7 +397,10 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
         const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
         double lj = u64cache[cL], cfa = u64cache[g.ncell() + cL];
         if (isnan(lj)) {  // same value for every thread
-            block_density_f64(g, a, ph, xL, yL, zL, s_red, lj, cfa);
+            // one molecule leaves about one workgroup per CU, so latency
+            // rules: 8 atoms in flight; a batch keeps several workgroups
+            // per CU, so registers rule: 2
+            block_density_f64<BATCH ? 2 : 8>(g, a, ph, xL, yL, zL, s_red, lj, cfa);
             if (t == leader) {
                 u64cache[cL] = lj;
                 u64cache[g.ncell() + cL] = cfa;
