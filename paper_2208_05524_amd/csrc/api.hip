@@ -139,6 +139,11 @@ struct vesis_ctx {
     bool forces_valid = false;
 
     hipStream_t capture = nullptr;  // private stream for graph capture (made on first use)
+    // pinned host staging of the batch calls' tables (descriptors, block
+    // maps, read-backs), so that their copies need not be waited for
+    char* hstage = nullptr;
+    size_t hstage_bytes = 0;
+    bool hstage_busy = false;  // a copy from it may still be pending
 
     bool prof = false;
     double prof_ms[K_NKINDS] = {0};
@@ -701,6 +706,7 @@ void vesis_destroy(vesis_ctx* ctx) {
     if (!ctx) return;
     if (!ctx->pending.empty()) drain_events(ctx);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     delete ctx;
 }
 
@@ -1349,6 +1355,53 @@ BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
     return L;
 }
 
+// Host staging of a batch call (in the first context's pinned buffer):
+// density descriptors and brick map, colour-pass descriptors and block map,
+// and three int64 read-backs per molecule.  The regions are disjoint, so a
+// call never overwrites a table whose copy may still be pending; every call
+// ends synchronised, so the next one may reuse them.
+struct StageLayout {
+    size_t ddesc, dmap, fdesc, fmap, stats, total;
+};
+
+StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
+    StageLayout S{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o += align256(bytes ? bytes : 1);
+        return r;
+    };
+    S.ddesc = take(sizeof(MolDesc) * (size_t)m);
+    S.dmap = take(4 * (size_t)dens_blocks);
+    S.fdesc = take(sizeof(MolDesc) * (size_t)m);
+    S.fmap = take(4 * (size_t)flip_blocks);
+    S.stats = take(8 * 3 * (size_t)m);
+    S.total = o;
+    return S;
+}
+
+// Grows the pinned staging buffer of c to at least `bytes` (waiting for the
+// stream first, so that no copy from the old buffer is pending).
+vesis_status ensure_stage(vesis_ctx* c, size_t bytes) {
+    vesis_ctx* ctx = c;
+    if (c->hstage_busy) {  // a call that stopped early may have left copies queued
+        CK(hipStreamSynchronize(c->stream));
+        c->hstage_busy = false;
+    }
+    if (c->hstage_bytes >= bytes) return VESIS_OK;
+    if (c->hstage) {
+        (void)hipHostFree(c->hstage);
+        c->hstage = nullptr;
+        c->hstage_bytes = 0;
+    }
+    void* p = nullptr;
+    CK(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    c->hstage = static_cast<char*>(p);
+    c->hstage_bytes = bytes;
+    return VESIS_OK;
+}
+
 // The largest block counts any density variant or the flip passes need.
 void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip) {
     dens = 0;
@@ -1378,7 +1431,7 @@ MolDesc mol_desc(vesis_ctx* c) {
 
 // Common checks of a batch call; on success `L` is the batch workspace layout.
 vesis_status batch_check(vesis_ctx* const* c, int32_t m, void* bws, size_t bytes, bool labels,
-                         BatchLayout& L) {
+                         BatchLayout& L, StageLayout& S) {
     if (!c || m < 1 || m > BATCH_MAX)
         return fail(m >= 1 && c ? c[0] : nullptr, VESIS_E_ARG, "need 1 to 4096 contexts");
     vesis_ctx* c0 = c[0];
@@ -1407,6 +1460,9 @@ vesis_status batch_check(vesis_ctx* const* c, int32_t m, void* bws, size_t bytes
     if (bytes < L.total)
         return fail(c0, VESIS_E_WORKSPACE, "batch workspace too small: need " +
                                                std::to_string(L.total) + " bytes");
+    S = stage_layout(m, db, fb);
+    vesis_status se = ensure_stage(c0, S.total);
+    if (se != VESIS_OK) return se;
     for (int i = 0; i < m; ++i) {
         vesis_status s = upload_inputs(c[i]);
         if (s != VESIS_OK) {
@@ -1421,7 +1477,7 @@ vesis_status batch_check(vesis_ctx* const* c, int32_t m, void* bws, size_t bytes
 // blocks of the costliest molecules are dispatched first, the light ones
 // fill the tail).
 vesis_status batch_density(vesis_ctx* c0, vesis_ctx* const* c, const std::vector<int>& which,
-                           char* bws, const BatchLayout& L, int variant) {
+                           char* bws, const BatchLayout& L, const StageLayout& S, int variant) {
     vesis_ctx* ctx = c0;
     hipStream_t st = c0->stream;
     if (which.empty()) return VESIS_OK;
@@ -1429,24 +1485,27 @@ vesis_status batch_density(vesis_ctx* c0, vesis_ctx* const* c, const std::vector
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return (double)c[x]->na * (double)c[x]->g.ncell() > (double)c[y]->na * (double)c[y]->g.ncell();
     });
-    std::vector<MolDesc> desc(order.size());
-    std::vector<int> map;
+    // the tables go through the pinned staging buffer, so nothing here waits
+    // for the device
+    MolDesc* desc = reinterpret_cast<MolDesc*>(c0->hstage + S.ddesc);
+    int* map = reinterpret_cast<int*>(c0->hstage + S.dmap);
+    int64_t nmap = 0;
     for (size_t k = 0; k < order.size(); ++k) {
         desc[k] = mol_desc(c[order[k]]);
-        desc[k].brick0 = (int64_t)map.size();
-        map.insert(map.end(), (size_t)density_bricks(c[order[k]]->g, variant), (int)k);
+        desc[k].brick0 = nmap;
+        const int64_t nb = density_bricks(c[order[k]]->g, variant);
+        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = (int)k;
+        nmap += nb;
     }
-    CK(hipMemcpyAsync(bws + L.desc, desc.data(), sizeof(MolDesc) * desc.size(),
-                      hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(bws + L.dmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
+    c0->hstage_busy = true;
+    CK(hipMemcpyAsync(bws + L.desc, desc, sizeof(MolDesc) * order.size(), hipMemcpyHostToDevice,
+                      st));
+    CK(hipMemcpyAsync(bws + L.dmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, st));
     {
         Timed t(c0, K_DENSITY);
         CK(launch_density_batch(reinterpret_cast<const MolDesc*>(bws + L.desc),
-                                reinterpret_cast<const int*>(bws + L.dmap), (int64_t)map.size(),
-                                variant, st));
+                                reinterpret_cast<const int*>(bws + L.dmap), nmap, variant, st));
     }
-    // the host vectors must outlive the copies
-    CK(hipStreamSynchronize(st));
     return VESIS_OK;
 }
 
@@ -1466,7 +1525,8 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
 vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
                               int32_t* best, double* ms) {
     BatchLayout L;
-    vesis_status s = batch_check(ctxs, m, bws, bytes, false, L);
+    StageLayout S;
+    vesis_status s = batch_check(ctxs, m, bws, bytes, false, L, S);
     if (s != VESIS_OK) return s;
     if (!best) return fail(ctxs[0], VESIS_E_ARG, "null argument");
     vesis_ctx* ctx = ctxs[0];
@@ -1481,10 +1541,11 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
         double tv = 1e300;
         for (int rep = 0; rep < 2; ++rep) {  // the first run also warms the caches
             CK(hipEventRecord(e0, st));
-            s = batch_density(ctx, ctxs, all, static_cast<char*>(bws), L, v);
+            s = batch_density(ctx, ctxs, all, static_cast<char*>(bws), L, S, v);
             if (s != VESIS_OK) break;
             CK(hipEventRecord(e1, st));
             CK(hipEventSynchronize(e1));
+            ctx->hstage_busy = false;
             float t = 0.f;
             CK(hipEventElapsedTime(&t, e0, e1));
             tv = std::min(tv, (double)t);
@@ -1511,7 +1572,8 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
                                   int32_t max_sweeps, int32_t variant, int32_t flags,
                                   vesis_min_stats* out) {
     BatchLayout L;
-    vesis_status s = batch_check(ctxs, m, bws, bytes, true, L);
+    StageLayout S;
+    vesis_status s = batch_check(ctxs, m, bws, bytes, true, L, S);
     if (s != VESIS_OK) return s;
     vesis_ctx* ctx = ctxs[0];
     if (max_sweeps < 1) return fail(ctx, VESIS_E_ARG, "max_sweeps must be >= 1");
@@ -1523,7 +1585,7 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     std::vector<int> stale;
     for (int i = 0; i < m; ++i)
         if (!ctxs[i]->dens_valid) stale.push_back(i);
-    s = batch_density(ctx, ctxs, stale, b, L, variant);
+    s = batch_density(ctx, ctxs, stale, b, L, S, variant);
     if (s != VESIS_OK) return s;
     for (int i : stale) {
         s = density_tail(ctxs[i]);
@@ -1531,33 +1593,34 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     }
     // a3 + a4: one launch per colour pass over every unconverged molecule
     const int p = ctx->sc.p, ncol = p * p * p;
-    std::vector<MolDesc> desc(m);
+    MolDesc* desc = reinterpret_cast<MolDesc*>(ctx->hstage + S.fdesc);
+    int* map = reinterpret_cast<int*>(ctx->hstage + S.fmap);
+    int64_t nmap = 0, max_words = 0;
     for (int i = 0; i < m; ++i) {
-        vesis_ctx* c = ctxs[i];
-        desc[i] = mol_desc(c);
-        CK(launch_fill_i64(desc[i].counters, 2, 0, st));
-        CK(launch_fill_u32(reinterpret_cast<uint32_t*>(desc[i].stamp), c->g.nwords(),
-                           (uint32_t)(-(1 << 30)), st));
+        desc[i] = mol_desc(ctxs[i]);
+        desc[i].slot0 = nmap * FLIP_WG;
+        const int64_t nb = flip_slots(ctxs[i]->g, p) / FLIP_WG;
+        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = i;
+        nmap += nb;
+        max_words = std::max(max_words, ctxs[i]->g.nwords());
     }
     std::vector<char> done(m, 0);
     std::vector<int> msweeps(m, 0);
     std::vector<int64_t> mflips(m, 0);
-    std::vector<int> map, hf((size_t)m * SWEEP_BATCH);
-    for (int i = 0; i < m; ++i) {
-        desc[i].slot0 = (int64_t)map.size() * FLIP_WG;
-        map.insert(map.end(), (size_t)(flip_slots(ctxs[i]->g, p) / FLIP_WG), i);
-    }
+    std::vector<int> hf((size_t)m * SWEEP_BATCH);
     const MolDesc* ddesc = reinterpret_cast<const MolDesc*>(b + L.desc);
     const int* dmap = reinterpret_cast<const int*>(b + L.fmap);
     int* ddone = reinterpret_cast<int*>(b + L.done);
     int* dpass = reinterpret_cast<int*>(b + L.pass);
     int* dflips = reinterpret_cast<int*>(b + L.flips);
-    const int64_t nblocks = (int64_t)map.size();
-    CK(hipMemcpyAsync(b + L.desc, desc.data(), sizeof(MolDesc) * m, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(b + L.fmap, map.data(), 4 * map.size(), hipMemcpyHostToDevice, st));
+    const int64_t nblocks = nmap;
+    ctx->hstage_busy = true;
+    CK(hipMemcpyAsync(b + L.desc, desc, sizeof(MolDesc) * m, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(b + L.fmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, st));
+    // every molecule's stamps older than any pass and its tie counters zero
+    CK(launch_batch_prepare(ddesc, m, max_words, st));
     CK(launch_fill_u32(reinterpret_cast<uint32_t*>(ddone), m, 0u, st));
     CK(launch_fill_u32(reinterpret_cast<uint32_t*>(dpass), 1, 0u, st));
-    CK(hipStreamSynchronize(st));  // the host tables must outlive the copies
     // one group of sweeps: every pass of every colour over the molecules not
     // yet done, then the done flags, the pass counter and the flip counts
     auto enqueue_group = [&](hipStream_t s2, int nb) -> hipError_t {
@@ -1609,6 +1672,7 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), dflips, 4 * hf.size(), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) ctx->hstage_busy = false;
         if (e != hipSuccess) {
             release();
             return fail(ctx, VESIS_E_DEVICE, std::string("batched sweeps: ") + hipGetErrorString(e));
@@ -1629,27 +1693,31 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
         sweeps += nb;
     }
     release();
-    for (int i = 0; i < m; ++i) {
-        vesis_ctx* c = ctxs[i];
-        if (mflips[i] > 0) c->forces_valid = false;
-        if (!out) continue;
-        int64_t cnt[2] = {0, 0}, band = 0;
-        vesis_ctx* ctx_i = c;
-        {
-            vesis_ctx* ctx = ctx_i;  // error reporting goes to the member
+    for (int i = 0; i < m; ++i)
+        if (mflips[i] > 0) ctxs[i]->forces_valid = false;
+    if (out) {
+        // every molecule's band count and tie counters, read back together
+        int64_t* hs = reinterpret_cast<int64_t*>(ctx->hstage + S.stats);
+        ctx->hstage_busy = true;
+        for (int i = 0; i < m; ++i) {
+            vesis_ctx* c = ctxs[i];
             CK(launch_band_count(c->g, at<uint32_t>(c, c->lay.bits), at<int64_t>(c, c->lay.red_i),
                                  RED_BLOCKS, at<int64_t>(c, c->lay.scal_i) + SI_BAND, st));
-            CK(hipMemcpyAsync(cnt, desc[i].counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
-            CK(hipMemcpyAsync(&band, c->ws + c->lay.scal_i + 8 * SI_BAND, sizeof(band),
+            CK(hipMemcpyAsync(hs + 3 * i, desc[i].counters, 2 * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
-            CK(hipStreamSynchronize(st));
+            CK(hipMemcpyAsync(hs + 3 * i + 2, c->ws + c->lay.scal_i + 8 * SI_BAND, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
         }
-        out[i].sweeps = msweeps[i];
-        out[i].converged = done[i] ? 1 : 0;
-        out[i].flips = mflips[i];
-        out[i].band_cells = band;
-        out[i].near_ties = cnt[0];
-        out[i].fp64_recomputes = cnt[1];
+        CK(hipStreamSynchronize(st));
+        ctx->hstage_busy = false;
+        for (int i = 0; i < m; ++i) {
+            out[i].sweeps = msweeps[i];
+            out[i].converged = done[i] ? 1 : 0;
+            out[i].flips = mflips[i];
+            out[i].band_cells = hs[3 * i + 2];
+            out[i].near_ties = hs[3 * i];
+            out[i].fp64_recomputes = hs[3 * i + 1];
+        }
     }
     ctx->err.clear();
     return active == 0 ? VESIS_OK : VESIS_NOT_CONVERGED;

@@ -141,6 +141,9 @@ hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, co
 hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,
                                   int* pass_base, hipStream_t st);
 hipError_t launch_batch_clear_flips(const MolDesc* descs, int m, int nsweeps, hipStream_t st);
+// Stamps of every molecule set older than any pass, tie counters zeroed;
+// max_words: the largest label word count of the m molecules.
+hipError_t launch_batch_prepare(const MolDesc* descs, int m, int64_t max_words, hipStream_t st);
 hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out,
                                      hipStream_t st);
 hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,

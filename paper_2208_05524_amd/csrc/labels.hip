@@ -450,6 +450,18 @@ __global__ void labels_from_logits_kernel(Grid g, const float* logits, uint32_t*
     bits[g.row(y, z) + 1 + w] = word;
 }
 
+// Before a batch's colour passes: every molecule's activity stamps set older
+// than any pass (so its first sweep evaluates every word) and its near-tie
+// counters zeroed.  Block (x, k) strides over molecule k's label words.
+__global__ void batch_prepare(const MolDesc* descs) {
+    const MolDesc& D = descs[blockIdx.y];
+    const int64_t nw = D.g.nwords();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride)
+        D.stamp[i] = -(1 << 30);
+    if (blockIdx.x == 0 && threadIdx.x < 2) D.counters[threadIdx.x] = 0;
+}
+
 // Zero the sweep flip counters of every molecule of a batch.
 __global__ void batch_clear_flips(const MolDesc* descs, int m, int nsweeps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -697,6 +709,13 @@ hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int 
                                   int* pass_base, hipStream_t st) {
     hipLaunchKernelGGL(batch_end_group, dim3(nblk(m, 256)), dim3(256), 0, st, descs, m, nsweeps,
                        ncol, done, pass_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prepare(const MolDesc* descs, int m, int64_t max_words, hipStream_t st) {
+    if (m <= 0 || max_words <= 0) return hipSuccess;
+    const int64_t bx = std::min<int64_t>((max_words + 4 * 256 - 1) / (4 * 256), 1024);
+    hipLaunchKernelGGL(batch_prepare, dim3((unsigned)bx, (unsigned)m), dim3(256), 0, st, descs);
     return hipGetLastError();
 }
 
