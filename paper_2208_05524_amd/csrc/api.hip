@@ -1334,10 +1334,10 @@ namespace {
 constexpr int BATCH_MAX = 4096;
 
 struct BatchLayout {
-    size_t desc, dmap, fmap, flips, done, pass, total;
+    size_t desc, dmap, fmap, flips, done, pass, far, farmap, total;
 };
 
-BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
+BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks, int64_t far_blocks) {
     BatchLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -1351,6 +1351,8 @@ BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
     L.flips = take(4 * (size_t)m * SWEEP_BATCH);
     L.done = take(4 * (size_t)m);
     L.pass = take(4);
+    L.far = take(sizeof(FarDesc) * (size_t)m);
+    L.farmap = take(4 * (size_t)far_blocks);
     L.total = o;
     return L;
 }
@@ -1361,10 +1363,10 @@ BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
 // call never overwrites a table whose copy may still be pending; every call
 // ends synchronised, so the next one may reuse them.
 struct StageLayout {
-    size_t ddesc, dmap, fdesc, fmap, stats, total;
+    size_t ddesc, dmap, fdesc, fmap, far, farmap, stats, total;
 };
 
-StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
+StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks, int64_t far_blocks) {
     StageLayout S{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -1376,6 +1378,8 @@ StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks) {
     S.dmap = take(4 * (size_t)dens_blocks);
     S.fdesc = take(sizeof(MolDesc) * (size_t)m);
     S.fmap = take(4 * (size_t)flip_blocks);
+    S.far = take(sizeof(FarDesc) * (size_t)m);
+    S.farmap = take(4 * (size_t)far_blocks);
     S.stats = take(8 * 3 * (size_t)m);
     S.total = o;
     return S;
@@ -1403,9 +1407,11 @@ vesis_status ensure_stage(vesis_ctx* c, size_t bytes) {
 }
 
 // The largest block counts any density variant or the flip passes need.
-void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip) {
+void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip, int64_t& far) {
     dens = 0;
     flip = 0;
+    far = 0;
+    for (int i = 0; i < m; ++i) far += points_blocks(c[i]->nfar, c[i]->na);
     for (int v = 0; v < DENSITY_VARIANTS; ++v) {
         int64_t s = 0;
         for (int i = 0; i < m; ++i) s += density_bricks(c[i]->g, v);
@@ -1453,14 +1459,15 @@ vesis_status batch_check(vesis_ctx* const* c, int32_t m, void* bws, size_t bytes
             return fail(c0, VESIS_E_ARG, "batch members must share the colour period");
     }
     int64_t db, fb;
-    batch_blocks(c, m, db, fb);
-    L = batch_layout(m, db, fb);
+    int64_t pb;
+    batch_blocks(c, m, db, fb, pb);
+    L = batch_layout(m, db, fb, pb);
     if (!bws || (reinterpret_cast<uintptr_t>(bws) & 255))
         return fail(c0, VESIS_E_ARG, "batch workspace must be a 256-byte aligned device pointer");
     if (bytes < L.total)
         return fail(c0, VESIS_E_WORKSPACE, "batch workspace too small: need " +
                                                std::to_string(L.total) + " bytes");
-    S = stage_layout(m, db, fb);
+    S = stage_layout(m, db, fb, pb);
     vesis_status se = ensure_stage(c0, S.total);
     if (se != VESIS_OK) return se;
     for (int i = 0; i < m; ++i) {
@@ -1509,6 +1516,56 @@ vesis_status batch_density(vesis_ctx* c0, vesis_ctx* const* c, const std::vector
     return VESIS_OK;
 }
 
+// After batch_density: what density_tail does for each molecule in `which`
+// (NaN fill of the near-tie cache, far field, its sums), in five launches.
+vesis_status batch_far(vesis_ctx* c0, vesis_ctx* const* c, const std::vector<int>& which,
+                       char* bws, const BatchLayout& L, const StageLayout& S) {
+    vesis_ctx* ctx = c0;
+    hipStream_t st = c0->stream;
+    if (which.empty()) return VESIS_OK;
+    FarDesc* fd = reinterpret_cast<FarDesc*>(c0->hstage + S.far);
+    int* map = reinterpret_cast<int*>(c0->hstage + S.farmap);
+    int64_t nmap = 0, max_np = 0, max_ncell = 0;
+    for (size_t k = 0; k < which.size(); ++k) {
+        vesis_ctx* x = c[which[k]];
+        FarDesc& d = fd[k];
+        d.pts = at<double4>(x, x->lay.far_pts);
+        d.np = x->nfar;
+        d.a = dev_atoms(x);
+        d.ph = dev_physics(x);
+        d.nsplit = points_split(x->nfar, x->na);
+        d.chunk = (x->na + d.nsplit - 1) / d.nsplit;
+        d.part = at<double>(x, x->lay.far_part);
+        d.ulj = at<double>(x, x->lay.far_ulj);
+        d.ucfa = at<double>(x, x->lay.far_ucfa);
+        d.ex = at<double>(x, x->lay.far_ex);
+        d.ey = at<double>(x, x->lay.far_ey);
+        d.ez = at<double>(x, x->lay.far_ez);
+        d.partial = at<double>(x, x->lay.red_d);
+        d.out = at<double>(x, x->lay.scal_d) + SD_FAR;
+        d.u64cache = at<double>(x, x->lay.u64cache);
+        d.ncell = x->g.ncell();
+        d.block0 = nmap;
+        const int64_t nb = x->nfar > 0 ? points_blocks(x->nfar, x->na) : 0;
+        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = (int)k;
+        nmap += nb;
+        max_np = std::max(max_np, x->nfar);
+        max_ncell = std::max(max_ncell, d.ncell);
+    }
+    c0->hstage_busy = true;
+    CK(hipMemcpyAsync(bws + L.far, fd, sizeof(FarDesc) * which.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(bws + L.farmap, map, 4 * (size_t)std::max<int64_t>(nmap, 1),
+                      hipMemcpyHostToDevice, st));
+    {
+        Timed t(c0, K_FAR);
+        CK(launch_far_batch(reinterpret_cast<const FarDesc*>(bws + L.far),
+                            reinterpret_cast<const int*>(bws + L.farmap), (int)which.size(), nmap,
+                            max_np, max_ncell, RED_BLOCKS, st));
+    }
+    for (int i : which) c[i]->dens_valid = true;
+    return VESIS_OK;
+}
+
 }  // namespace
 
 vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_t* bytes) {
@@ -1517,8 +1574,9 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
         if (!ctxs[i] || !ctxs[i]->has_grid || !ctxs[i]->has_params)
             return fail(ctxs[0], VESIS_E_STATE, "batch members need parameters and a grid");
     int64_t db, fb;
-    batch_blocks(ctxs, m, db, fb);
-    *bytes = batch_layout(m, db, fb).total;
+    int64_t pb;
+    batch_blocks(ctxs, m, db, fb, pb);
+    *bytes = batch_layout(m, db, fb, pb).total;
     return VESIS_OK;
 }
 
@@ -1587,10 +1645,8 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
         if (!ctxs[i]->dens_valid) stale.push_back(i);
     s = batch_density(ctx, ctxs, stale, b, L, S, variant);
     if (s != VESIS_OK) return s;
-    for (int i : stale) {
-        s = density_tail(ctxs[i]);
-        if (s != VESIS_OK) return s;
-    }
+    s = batch_far(ctx, ctxs, stale, b, L, S);
+    if (s != VESIS_OK) return s;
     // a3 + a4: one launch per colour pass over every unconverged molecule
     const int p = ctx->sc.p, ncol = p * p * p;
     MolDesc* desc = reinterpret_cast<MolDesc*>(ctx->hstage + S.fdesc);

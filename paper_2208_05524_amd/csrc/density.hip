@@ -411,18 +411,18 @@ struct PTypes<double> {
     static __device__ double rsq(double x) { return sqrt(1.0 / x); }
 };
 
+// Block (bx, sl) of a far-field evaluation: nodes bx * PWG ..., atom slice sl.
 template <typename T>
-__global__ __launch_bounds__(PWG) void density_points_part(const double4* pts, int64_t np,
-                                                           Atoms a, Physics ph, int64_t chunk,
-                                                           int nsplit, double* part) {
+__device__ __forceinline__ void points_part_block(const double4* pts, int64_t np, const Atoms& a,
+                                                  const Physics& ph, int64_t chunk, int nsplit,
+                                                  double* part, int64_t bx, int sl) {
     using T4 = typename PTypes<T>::T4;
     __shared__ T4 spos[TILE];
     __shared__ T4 sprm[TILE];
     const int t = threadIdx.x;
-    const int sl = blockIdx.y;
     const int64_t lo = (int64_t)sl * chunk;
     const int64_t hi = (lo + chunk < a.n) ? lo + chunk : a.n;
-    const int64_t p0 = (int64_t)blockIdx.x * PWG;
+    const int64_t p0 = bx * PWG;
     const int64_t pi = p0 + t;
     const double4 o = pts[p0];
     const double4 me = pts[pi < np ? pi : p0];
@@ -477,10 +477,47 @@ __global__ __launch_bounds__(PWG) void density_points_part(const double4* pts, i
     part[3 * stride + at] = dEz;
 }
 
+template <typename T>
+__global__ __launch_bounds__(PWG) void density_points_part(const double4* pts, int64_t np,
+                                                           Atoms a, Physics ph, int64_t chunk,
+                                                           int nsplit, double* part) {
+    points_part_block<T>(pts, np, a, ph, chunk, nsplit, part, blockIdx.x, blockIdx.y);
+}
+
+// Batched: block b works on block b - block0 of molecule block_mol[b], laid
+// out as in the single-molecule launch (node block fastest, then slice).
+__global__ __launch_bounds__(PWG) void density_points_part_batch(const FarDesc* d,
+                                                                 const int* block_mol) {
+    const FarDesc& D = d[block_mol[blockIdx.x]];
+    const int64_t local = (int64_t)blockIdx.x - D.block0;
+    const int64_t nbx = (D.np + PWG - 1) / PWG;
+    points_part_block<float>(D.pts, D.np, D.a, D.ph, D.chunk, D.nsplit, D.part, local % nbx,
+                             (int)(local / nbx));
+}
+
+__device__ __forceinline__ void combine_point(int64_t p, int64_t np, int nsplit, const double* part,
+                                              double ccfa, double* ulj, double* ucfa, double* ex,
+                                              double* ey, double* ez);
+
 __global__ void points_combine(int64_t np, int nsplit, const double* part, double ccfa,
                                double* ulj, double* ucfa, double* ex, double* ey, double* ez) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
+    combine_point(p, np, nsplit, part, ccfa, ulj, ucfa, ex, ey, ez);
+}
+
+// Batched: block (x, k) combines nodes x * 256 ... of molecule k.
+__global__ void points_combine_batch(const FarDesc* d) {
+    const FarDesc& D = d[blockIdx.y];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= D.np) return;
+    combine_point(p, D.np, D.nsplit, D.part, D.ph.ccfa, D.ulj, D.ucfa, D.ex, D.ey, D.ez);
+}
+
+// The slices of node p added in order; the field squared.
+__device__ __forceinline__ void combine_point(int64_t p, int64_t np, int nsplit, const double* part,
+                                              double ccfa, double* ulj, double* ucfa, double* ex,
+                                              double* ey, double* ez) {
     const int64_t stride = (int64_t)nsplit * np;
     double lj = 0, x = 0, y = 0, z = 0;
     for (int s = 0; s < nsplit; ++s) {
@@ -497,14 +534,14 @@ __global__ void points_combine(int64_t np, int nsplit, const double* part, doubl
     ez[p] = z;
 }
 
-// Deterministic two-level sum of w_p a_p and w_p b_p (w = pts[p].w).
-__global__ __launch_bounds__(RED_WG) void wsum2_stage1(const double4* pts, const double* a,
-                                                       const double* b, int64_t np,
-                                                       double* partial) {
+// Deterministic two-level sum of w_p a_p and w_p b_p (w = pts[p].w): block
+// blk of nblk takes nodes blk * RED_WG + i * nblk * RED_WG.
+__device__ __forceinline__ void wsum2_block(const double4* pts, const double* a, const double* b,
+                                            int64_t np, double* partial, int blk, int nblk) {
     __shared__ double sh[RED_WG];
     double sa = 0.0, sb = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * RED_WG;
-    for (int64_t p = (int64_t)blockIdx.x * RED_WG + threadIdx.x; p < np; p += stride) {
+    const int64_t stride = (int64_t)nblk * RED_WG;
+    for (int64_t p = (int64_t)blk * RED_WG + threadIdx.x; p < np; p += stride) {
         const double w = pts[p].w;
         sa += w * a[p];
         sb += w * b[p];
@@ -512,9 +549,42 @@ __global__ __launch_bounds__(RED_WG) void wsum2_stage1(const double4* pts, const
     sa = block_sum(sa, sh);
     sb = block_sum(sb, sh);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = sa;
-        partial[2 * blockIdx.x + 1] = sb;
+        partial[2 * blk] = sa;
+        partial[2 * blk + 1] = sb;
     }
+}
+
+__global__ __launch_bounds__(RED_WG) void wsum2_stage1(const double4* pts, const double* a,
+                                                       const double* b, int64_t np,
+                                                       double* partial) {
+    wsum2_block(pts, a, b, np, partial, blockIdx.x, gridDim.x);
+}
+
+// Batched: block (blk, k) of molecule k's far-field sums; then one block per
+// molecule adds its partials as reduce_partials<double, 2> does.
+__global__ __launch_bounds__(RED_WG) void wsum2_stage1_batch(const FarDesc* d) {
+    const FarDesc& D = d[blockIdx.y];
+    wsum2_block(D.pts, D.ulj, D.ucfa, D.np, D.partial, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(RED_WG) void wsum2_stage2_batch(const FarDesc* d, int nblk) {
+    __shared__ double sh[RED_WG];
+    const FarDesc& D = d[blockIdx.x];
+    for (int k = 0; k < 2; ++k) {
+        double s = 0;
+        for (int i = threadIdx.x; i < nblk; i += RED_WG) s += D.partial[(int64_t)i * 2 + k];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) D.out[k] = s;
+    }
+}
+
+// Batched: the FP64 near-tie cache of every molecule set to NaN.
+__global__ void far_fill_nan_batch(const FarDesc* d) {
+    const FarDesc& D = d[blockIdx.y];
+    const int64_t n = 2 * D.ncell;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        D.u64cache[i] = __builtin_nan("");
 }
 
 }  // namespace
@@ -549,6 +619,7 @@ hipError_t launch_density_batch(const MolDesc* desc, const int* block_mol, int64
 }
 
 int points_split(int64_t np, int64_t natoms) {
+    if (np <= 0) return 1;
     const int64_t nblk = (np + PWG - 1) / PWG;
     int64_t s = (2048 + nblk - 1) / nblk;
     s = s < 1 ? 1 : (s > POINT_SPLITS_MAX ? POINT_SPLITS_MAX : s);
@@ -572,6 +643,28 @@ hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a,
                            chunk, nsplit, part);
     hipLaunchKernelGGL(points_combine, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np,
                        nsplit, part, ph.ccfa, ulj, ucfa, ex, ey, ez);
+    return hipGetLastError();
+}
+
+int64_t points_blocks(int64_t np, int64_t natoms) {
+    if (np <= 0) return 0;
+    return (np + PWG - 1) / PWG * points_split(np, natoms);
+}
+
+hipError_t launch_far_batch(const FarDesc* d, const int* block_mol, int m, int64_t nblocks,
+                            int64_t max_np, int64_t max_ncell, int nred, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const unsigned fx = (unsigned)std::min<int64_t>((2 * max_ncell + 1023) / 1024, 4096);
+    hipLaunchKernelGGL(far_fill_nan_batch, dim3(fx, (unsigned)m), dim3(256), 0, st, d);
+    if (nblocks > 0 && max_np > 0) {
+        hipLaunchKernelGGL(density_points_part_batch, dim3((unsigned)nblocks), dim3(PWG), 0, st, d,
+                           block_mol);
+        hipLaunchKernelGGL(points_combine_batch, dim3((unsigned)((max_np + 255) / 256), (unsigned)m),
+                           dim3(256), 0, st, d);
+    }
+    hipLaunchKernelGGL(wsum2_stage1_batch, dim3((unsigned)nred, (unsigned)m), dim3(RED_WG), 0, st,
+                       d);
+    hipLaunchKernelGGL(wsum2_stage2_batch, dim3((unsigned)m), dim3(RED_WG), 0, st, d, nred);
     return hipGetLastError();
 }
 

@@ -103,6 +103,38 @@ hipError_t launch_density_points(const double4* pts, int64_t np, const Atoms& a,
 hipError_t launch_weighted_sum2(const double4* pts, const double* a, const double* b, int64_t np,
                                 double* partial, int nblocks, double* out, hipStream_t st);
 
+// One molecule of a batched far-field evaluation (FP32 point densities):
+// what launch_density_points, launch_weighted_sum2 and the NaN fill of the
+// near-tie cache take for it, its slices (nsplit, chunk) as there, and the
+// index of its first point block in the launch.
+struct FarDesc {
+    const double4* pts;
+    int64_t np;
+    Atoms a;
+    Physics ph;
+    int nsplit;
+    int64_t chunk;
+    double* part;
+    double* ulj;
+    double* ucfa;
+    double* ex;
+    double* ey;
+    double* ez;
+    double* partial;   // nred x 2
+    double* out;       // the two weighted sums
+    double* u64cache;  // 2 x ncell
+    int64_t ncell;
+    int64_t block0;
+};
+// Point blocks of one molecule's far-field launch (node blocks x slices).
+int64_t points_blocks(int64_t np, int64_t natoms);
+// NaN fill, point densities, combine and the two-level sums of m molecules
+// in five launches; the point blocks of molecule k are consecutive from
+// d[k].block0 (block_mol maps each to its molecule).  The results equal the
+// single-molecule launches' bit for bit.
+hipError_t launch_far_batch(const FarDesc* d, const int* block_mol, int m, int64_t nblocks,
+                            int64_t max_np, int64_t max_ncell, int nred, hipStream_t st);
+
 // Batched density (FP32): variant 0 = 2 cells per lane on 16 x 8 x 4 bricks,
 // 1 = 1 cell per lane on 16 x 8 x 2 bricks.  block_mol maps each block to its
 // molecule; a molecule's blocks are consecutive, from desc[m].brick0.

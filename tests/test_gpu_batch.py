@@ -65,6 +65,17 @@ def _check_batch(ws, variant):
         assert np.array_equal(single.labels(), lab)
         assert (sst["sweeps"], sst["flips"], sst["band"]) == (st["sweeps"], st["flips"],
                                                               st["band"])
+        # the batched far field computes what the single-molecule launches
+        # compute, in the same order: bit for bit; so does the batched
+        # density in variant 0, whose bricks (16 x 8 x 4) are the single
+        # kernel's (variant 1's 16 x 8 x 2 bricks split atoms into near and
+        # far differently, so its volume terms differ by FP32 rounding)
+        es = single.energy()
+        exact = ("vdw_far", "elec_far", "geom")
+        if variant == 0:
+            exact += ("vdw_in", "elec_in", "total")
+        for k in exact:
+            assert e[k] == es[k], (k, e[k], es[k])
 
 
 def test_batch_resumes_after_max_sweeps():
