@@ -280,10 +280,14 @@ vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* opts, vesis_mob
  * relaxed together: one density launch covers every molecule's cells and each
  * colour pass is one launch over every unconverged molecule's label words.
  * Per molecule the result is the one vesis_minimize_interface gives: the
- * same passes in the same order (the paper's Step 2, batched).  The calls
- * need a device buffer for the batch's own tables (descriptors, block maps):
- * vesis_batch_workspace_size gives its size; it must be 256-byte aligned.
- * Contexts must not be used concurrently with a batch call. */
+ * same passes in the same order (the paper's Step 2, batched), and the far
+ * field of all molecules is evaluated together with the same result as one
+ * at a time.  The calls need a device buffer for the batch's own tables
+ * (descriptors, block maps): vesis_batch_workspace_size gives its size; it
+ * must be 256-byte aligned.  The first context of a batch keeps a pinned
+ * host buffer for staging those tables (host memory, grown as needed, freed
+ * by vesis_destroy), so that no call waits for a copy to finish.  Contexts
+ * must not be used concurrently with a batch call. */
 vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_t* bytes);
 
 /* Time each density tiling variant (0: two cells per lane on 16x8x4
