@@ -34,6 +34,19 @@ def test_batch_colour_period_two():
     _check_batch(ws, 0)
 
 
+def test_batch_of_one_and_mixed_far_nodes():
+    """A batch of one molecule, and a batch whose molecules have different
+    far-field node counts (far_nf 32, 20 and 8; ntau 16, 12 and 4): every
+    result equals the single-molecule path's."""
+    ws = _molecules()
+    _check_batch(ws[:1], 0)
+    mixed = []
+    for w, (nf, nt) in zip(ws[1:4], [(32, 16), (20, 12), (8, 4)]):
+        mixed.append(dataclasses.replace(w, params=dataclasses.replace(w.params, far_nf=nf,
+                                                                      far_ntau=nt)))
+    _check_batch(mixed, 0)
+
+
 def _check_batch(ws, variant):
     from paper_2208_05524_amd import Batch
     ctxs = [gpu_context(w) for w in ws]
