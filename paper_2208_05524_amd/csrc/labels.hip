@@ -43,14 +43,6 @@ __device__ inline uint32_t valid_mask(int n, int x0) {
     return m >= 32 ? 0xffffffffu : ((1u << m) - 1u);
 }
 
-// bits b of the word starting at x0 with (x0 + b) mod p == a
-__device__ inline uint32_t colour_mask(int p, int a, int x0) {
-    uint32_t m = 0;
-    const int r = ((a - x0) % p + p) % p;
-    for (int b = r; b < 32; b += p) m |= 1u << b;
-    return m;
-}
-
 // Cell centre c - L + (i + 1/2) h per axis, the grid's definition, evaluated
 // without contraction so that label decisions on a sphere or a union of
 // spheres round exactly as the definition reads.
@@ -122,15 +114,6 @@ __global__ __launch_bounds__(256) void init_tight_kernel(Grid g, Atoms a, double
 }
 
 // ------------------------------------------------------------- stencil
-
-// 5-bit window of row `r` at x-2 .. x+2 (bit 0 = x-2, bit 2 = x).
-__device__ inline uint32_t window5(const uint32_t* r, int x) {
-    const int gbit = x + 30;  // word 0 covers x in [-32, 0)
-    const int lo = gbit >> 5, sh = gbit & 31;
-    uint32_t v = r[lo] >> sh;
-    if (sh > 27) v |= r[lo + 1] << (32 - sh);
-    return v & 31u;
-}
 
 // The 25 x-rows (y + dy, z + dz) with dy^2 + dz^2 <= 8 around a word, three
 // words each (left, own, right), loaded once per lane.
