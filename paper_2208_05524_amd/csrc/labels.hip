@@ -274,6 +274,9 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     constexpr int K = (32 + P - 1) / P;  // cells of one colour in a word
     __shared__ double s_red[4 * FWG];
     __shared__ double s_cs[K * FWG];     // c S_j of the near ties, slot-major
+    __shared__ int s_item[FWG / 64][64 * K];  // per wavefront: (owner lane << 5) | bit
+    __shared__ int s_wyz[3][FWG];        // each lane's word: w, y, z
+    __shared__ uint32_t s_fm[FWG], s_tm[FWG];  // flip and near-tie bits per owner
     __shared__ int s_leader;
     __shared__ int s_tie[4];
     if (BATCH) {
@@ -327,39 +330,72 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
         const uint32_t cmask = (P == 2 ? 0x55555555u : 0x49249249u) << (((ca - x0) % P + P) % P);
         cand = band & cmask & valid_mask(g.n, x0) & fresh;
     }
-    uint32_t flipmask = 0, tiemask = 0;
-    const int b0 = ((ca - x0) % P + P) % P;  // first bit of this colour in the word
+    // The candidate cells are shared out over the wavefront: a prefix sum of
+    // the lanes' counts lists them in LDS as (owner lane, bit), and the
+    // wavefront takes the list 64 cells at a time, each lane one cell with
+    // the owner word's rows (L2-resident), so that a lane with many
+    // candidates does not hold its wavefront for as many rounds.  The
+    // decisions go back to the owner's masks in LDS; a near tie also keeps
+    // c S_j there for the FP64 decision below.  Every cell is evaluated
+    // exactly as its owner would.
     const int t = threadIdx.x;
-    if (cand) {
-        // The 5-cell windows of the 25 rows are built once for all of the
-        // word's candidates (at most K = ceil(32 / P)), taken in bit order.
-        // A near tie keeps c S_j in LDS for the FP64 decision below.
-        const int64_t cw = (int64_t)x0 + (int64_t)g.n * (y + (int64_t)g.n * z);
-        Win25 Wn;
-        {
-            Rows25 R;
-            load_rows(g, bits, w, y, z, R);
-            make_windows(R, Wn);
-        }
+    const int lane = t & 63, wv = t >> 6;
+    s_fm[t] = 0u;
+    s_tm[t] = 0u;
+    s_wyz[0][t] = w;
+    s_wyz[1][t] = y;
+    s_wyz[2][t] = z;
+    const int nc = __popc(cand);
+    int incl = nc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    const int nitems = __shfl(incl, 63);
+    {
+        int k = incl - nc;
         uint32_t cm = cand;
         while (cm) {
             const int b = __ffs(cm) - 1;
             cm &= cm - 1;
-            const int64_t c = cw + b;
-            const double S = stencil_sum(sc, Wn, b);
-            const double phi = ((C >> b) & 1u) ? 1.0 : -1.0;
-            const double hU = ph.h3 * (ulj[c] + ucfa[c]);
-            const double cS = sc.c * S;
-            const double dE = phi * (cS - hU);
-            const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
-            if (!(fabs(dE) > tol)) {
-                tiemask |= 1u << b;
-                s_cs[((b - b0) / P) * FWG + t] = cS;
-            } else if (dE < 0.0) {
-                flipmask |= 1u << b;
-            }
+            s_item[wv][k++] = (lane << 5) | b;
         }
     }
+    __syncthreads();
+    for (int k0 = 0; k0 < nitems; k0 += 64) {
+        const int k = k0 + lane;
+        if (k >= nitems) continue;
+        const int it = s_item[wv][k];
+        const int b = it & 31;
+        const int to = wv * 64 + (it >> 5);
+        const int wo = s_wyz[0][to], yo = s_wyz[1][to], zo = s_wyz[2][to];
+        const int64_t c = (int64_t)(32 * wo + b) + (int64_t)g.n * (yo + (int64_t)g.n * zo);
+        Win25 Wn;
+        uint32_t Co;
+        {
+            Rows25 R;
+            load_rows(g, bits, wo, yo, zo, R);
+            Co = R.c[12];  // the owner's word (dy = dz = 0)
+            make_windows(R, Wn);
+        }
+        const double S = stencil_sum(sc, Wn, b);
+        const double phi = ((Co >> b) & 1u) ? 1.0 : -1.0;
+        const double hU = ph.h3 * (ulj[c] + ucfa[c]);
+        const double cS = sc.c * S;
+        const double dE = phi * (cS - hU);
+        const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
+        if (!(fabs(dE) > tol)) {
+            const int b0o = ((ca - 32 * wo) % P + P) % P;
+            s_cs[((b - b0o) / P) * FWG + to] = cS;
+            atomicOr(&s_tm[to], 1u << b);
+        } else if (dE < 0.0) {
+            atomicOr(&s_fm[to], 1u << b);
+        }
+    }
+    __syncthreads();
+    uint32_t flipmask = s_fm[t], tiemask = s_tm[t];
+    const int b0 = ((ca - x0) % P + P) % P;  // first bit of this colour in the word
     // near ties: the whole workgroup resolves them one at a time in FP64,
     // lowest thread first; each cell's FP64 parts are computed once per atom
     // configuration and cached (2 x ncell doubles: LJ, then CFA; NaN = none)
