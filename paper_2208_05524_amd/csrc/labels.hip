@@ -274,7 +274,8 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     constexpr int K = (32 + P - 1) / P;  // cells of one colour in a word
     __shared__ double s_red[4 * FWG];
     __shared__ double s_cs[K * FWG];     // c S_j of the near ties, slot-major
-    __shared__ int s_item[FWG / 64][64 * K];  // per wavefront: (owner lane << 5) | bit
+    __shared__ int s_item[FWG * K];      // the workgroup's candidates: (owner << 5) | bit
+    __shared__ int s_wsum[FWG / 64];     // candidates per wavefront
     __shared__ int s_wyz[3][FWG];        // each lane's word: w, y, z
     __shared__ uint32_t s_fm[FWG], s_tm[FWG];  // flip and near-tie bits per owner
     __shared__ int s_leader;
@@ -330,14 +331,14 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
         const uint32_t cmask = (P == 2 ? 0x55555555u : 0x49249249u) << (((ca - x0) % P + P) % P);
         cand = band & cmask & valid_mask(g.n, x0) & fresh;
     }
-    // The candidate cells are shared out over the wavefront: a prefix sum of
-    // the lanes' counts lists them in LDS as (owner lane, bit), and the
-    // wavefront takes the list 64 cells at a time, each lane one cell with
+    // The candidate cells are shared out over the workgroup: a prefix sum of
+    // the lanes' counts lists them in LDS as (owner thread, bit), and the
+    // workgroup takes the list FWG cells at a time, each thread one cell with
     // the owner word's rows (L2-resident), so that a lane with many
-    // candidates does not hold its wavefront for as many rounds.  The
-    // decisions go back to the owner's masks in LDS; a near tie also keeps
-    // c S_j there for the FP64 decision below.  Every cell is evaluated
-    // exactly as its owner would.
+    // candidates does not hold its wavefront, nor the workgroup, for as many
+    // rounds.  The decisions go back to the owner's masks in LDS; a near tie
+    // also keeps c S_j there for the FP64 decision below.  Every cell is
+    // evaluated exactly as its owner would.
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     s_fm[t] = 0u;
@@ -352,23 +353,30 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
         const int v = __shfl_up(incl, o);
         if (lane >= o) incl += v;
     }
-    const int nitems = __shfl(incl, 63);
+    if (lane == 63) s_wsum[wv] = incl;
+    __syncthreads();
+    int base = 0, nitems = 0;
+#pragma unroll
+    for (int v = 0; v < FWG / 64; ++v) {
+        base += v < wv ? s_wsum[v] : 0;
+        nitems += s_wsum[v];
+    }
     {
-        int k = incl - nc;
+        int k = base + incl - nc;
         uint32_t cm = cand;
         while (cm) {
             const int b = __ffs(cm) - 1;
             cm &= cm - 1;
-            s_item[wv][k++] = (lane << 5) | b;
+            s_item[k++] = (t << 5) | b;
         }
     }
     __syncthreads();
-    for (int k0 = 0; k0 < nitems; k0 += 64) {
-        const int k = k0 + lane;
+    for (int k0 = 0; k0 < nitems; k0 += FWG) {
+        const int k = k0 + t;
         if (k >= nitems) continue;
-        const int it = s_item[wv][k];
+        const int it = s_item[k];
         const int b = it & 31;
-        const int to = wv * 64 + (it >> 5);
+        const int to = it >> 5;
         const int wo = s_wyz[0][to], yo = s_wyz[1][to], zo = s_wyz[2][to];
         const int64_t c = (int64_t)(32 * wo + b) + (int64_t)g.n * (yo + (int64_t)g.n * zo);
         Win25 Wn;
