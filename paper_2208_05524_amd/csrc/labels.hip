@@ -5,8 +5,9 @@
 // only the x-rows with y = b (mod p), z = cc (mod p) hold candidates, and in
 // them the cells with x = a (mod p).  One lane owns one 32-cell word of such
 // a row: it forms the band mask of all 32 cells with a few shifts and XORs
-// (a cell is in the band when a face neighbour carries the other label),
-// keeps the colour-a cells, and for each candidate evaluates
+// (a cell is in the band when a face neighbour carries the other label) and
+// keeps the colour-a cells.  The workgroup lists its lanes' candidates and
+// shares them out, one per thread, and for each evaluates
 //     Delta E_j = phi_j (c S_j - h^3 U_j),  S_j = sum_{0<|o|<delta/h} phi_{j+o} K(|o|/rho_s)
 // (the two cases of the paper's flip energy in one expression).  S_j is
 // computed exactly as sum over squared offsets s of w_s * n_s with integer
