@@ -641,7 +641,8 @@ int64_t orc_colour_pass(const orc_sys* s, int8_t* phi, const double* u, int colo
                         double* tie_de, int64_t tie_cap, int64_t* ntie) {
     int64_t n = s->n, ncell = n * n * n;
     int p = (int)ceil(s->rho_s);
-    int64_t cap = ncell / (p * p * p) + 64, nc = 0;
+    int64_t cap = ((n + p - 1) / p) * ((n + p - 1) / p) * ((n + p - 1) / p), nc = 0;
+    /* cap: the cells of one colour, ceil(n / p) along each axis at most */
     int64_t* cand = malloc(sizeof(int64_t) * (size_t)cap);
     /* the cells of colour c are i = c mod p, j = (c / p) mod p, k = c / p^2,
      * each stepping by p */
