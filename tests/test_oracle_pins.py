@@ -331,6 +331,35 @@ def test_minimised_labels_are_a_local_minimum():
         assert s.energy(phi2, ulj, ucfa, far)["total"] >= e_fin - 1e-12 * abs(e_fin)
 
 
+@pytest.mark.parametrize("rho_s,n", [(3.0, 40), (3.0, 31), (2.0, 33)])
+def test_colour_pass_lists_every_band_cell_of_its_colour(rho_s, n):
+    """From random labels, where nearly every cell is in the band, each colour
+    pass's candidates are exactly the band cells of that colour, counted here
+    with numpy from the definitions (a face neighbour with the other label,
+    cells outside the box solvent; colour (x mod p, y mod p, z mod p)), also
+    on grids that p = ceil(rho_s) does not divide, where one colour holds
+    ceil(n / p)^3 cells."""
+    rng = np.random.default_rng(31)
+    params = dataclasses.replace(synth.Params(), rho_s=rho_s)
+    s = _sys(n, 0.1, rng.uniform(-0.3, 0.3, size=(3, 3)), [0.2, -0.1, -0.1],
+             [0.35, 0.3, 0.4], [0.3, 0.4, 0.5], params)
+    phi = np.where(rng.random(n ** 3) < 0.4, -1, 1).astype(np.int8)
+    u = np.zeros(n ** 3)
+    g = np.pad(phi.reshape(n, n, n), 1, constant_values=1)  # [z, y, x], solvent outside
+    c = g[1:-1, 1:-1, 1:-1]
+    band = np.zeros_like(c, dtype=bool)
+    for ax in range(3):
+        for sh in (-1, 1):
+            band |= np.roll(g, sh, axis=ax)[1:-1, 1:-1, 1:-1] != c
+    p = math.ceil(rho_s)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    colour = x % p + p * (y % p) + p * p * (z % p)
+    assert s.colours() == p ** 3
+    for col in range(p ** 3):
+        _, ncand, _ = s.colour_pass(phi.copy(), u, col)
+        assert ncand == int((band & (colour == col)).sum()), col
+
+
 def test_colour_pass_equals_a_serial_pass_in_reverse_order():
     """A colour pass (every band cell of one colour evaluated on the labels at
     the start of the pass, those with Delta E < 0 flipped) equals visiting the
