@@ -34,6 +34,39 @@ def _oracle_state(w, phi0=None, mode="tight", param=1.0, max_sweeps=100000):
     return s, phi, st, ties, e, (ulj, ucfa, far)
 
 
+def _oracle_relax_from(w, phi0):
+    """The oracle's colour schedule from labels phi0; every decision is
+    logged and those within 1e-9 |G| of the final G are counted (a start
+    with solvent inside atoms has an enormous G0, so the window is taken
+    against where the relaxation ends).  Returns (labels, stats, count,
+    energy parts)."""
+    import oracle
+    s = oracle.System.from_workload(w)
+    ulj, ucfa = s.density_grid()
+    far = s.far_field()
+    phi = phi0.copy()
+    _, ost, _, tde = s.minimize_colour(phi, ulj + ucfa, tie_tol=np.inf, tie_cap=1 << 22)
+    assert ost["ties"] <= 1 << 22
+    oe = s.energy(phi, ulj, ucfa, far)
+    near = int((np.abs(tde) <= 1e-9 * abs(oe["total"])).sum())
+    return phi, ost, near, oe
+
+
+def _check_relax_from(w, phi0, label):
+    ctx = gpu_context(w)
+    ctx.init_labels("user", user=phi0)
+    rc, gst = ctx.minimize()
+    ophi, ost, near, oe = _oracle_relax_from(w, phi0)
+    log(label, "gpu", gst, "oracle", ost, "decisions inside 1e-9 |G|:", near)
+    assert rc == 0 and gst["converged"] == 1
+    if near == 0:
+        assert np.array_equal(ctx.labels(), ophi)
+        assert (gst["sweeps"], gst["flips"], gst["band"]) == \
+            (ost["sweeps"], ost["flips"], ost["band"])
+    assert not energies_close(ctx.energy(), oe, 1e-6)
+    return gst
+
+
 # ------------------------------------------------------------------ density
 
 @pytest.mark.parametrize("n,natoms,seed", [(40, 300, 5), (37, 257, 6), (32, 1, 7)])
@@ -146,34 +179,30 @@ def test_minimize_from_random_labels(rho_s):
     """Random labels (40 % solute) put almost every cell in the band, so a
     workgroup's lanes hold far more candidates than it has threads and the
     shared candidate list takes many rounds; labels, sweeps, flips and band
-    size must still equal the oracle's colour schedule.  Such a start puts
-    solvent inside atoms (G0 ~ 1e20), so the near-tie window is taken
-    against the final G: the oracle logs every decision with the start's
-    window and the log is filtered afterwards."""
-    import oracle
+    size must still equal the oracle's colour schedule."""
     w = ragged_small(seed=14, n=40, natoms=200)
     w = dataclasses.replace(w, params=dataclasses.replace(w.params, rho_s=rho_s))
     rng = synth.SplitMix64(1400 + int(rho_s))
     phi0 = np.where(rng.uniform(w.n ** 3) < 0.4, -1, 1).astype(np.int8)
-    ctx = gpu_context(w)
-    ctx.init_labels("user", user=phi0)
-    rc, gst = ctx.minimize()
-    s = oracle.System.from_workload(w)
-    ulj, ucfa = s.density_grid()
-    far = s.far_field()
-    phi = phi0.copy()
-    e0 = s.energy(phi, ulj, ucfa, far)["total"]
-    _, ost, _, tde = s.minimize_colour(phi, ulj + ucfa, tie_tol=1e-9 * abs(e0), tie_cap=1 << 22)
-    assert ost["ties"] <= 1 << 22
-    oe = s.energy(phi, ulj, ucfa, far)
-    near = int((np.abs(tde) <= 1e-9 * abs(oe["total"])).sum())
-    log("random start", rho_s, "gpu", gst, "oracle", ost, "decisions inside 1e-9 |G|:", near)
-    assert rc == 0 and gst["converged"] == 1
-    if near == 0:
-        assert np.array_equal(ctx.labels(), phi)
-        assert (gst["sweeps"], gst["flips"], gst["band"]) == \
-            (ost["sweeps"], ost["flips"], ost["band"])
-    assert not energies_close(ctx.energy(), oe, 1e-6)
+    _check_relax_from(w, phi0, f"random start {rho_s}")
+
+
+@pytest.mark.parametrize("start", ["all_solvent", "all_solute", "one_solute_cell"])
+def test_minimize_degenerate_labels(start):
+    """Degenerate starts: every cell solvent (empty band: one sweep, no
+    flip), every cell solute (the band is the box's boundary shell, as cells
+    outside count as solvent) and a single solute cell off the atoms; each
+    relaxes exactly as the oracle's colour schedule does."""
+    w = ragged_small(seed=15, n=35, natoms=60)
+    n = w.n
+    phi0 = np.ones(n ** 3, np.int8)
+    if start == "all_solute":
+        phi0[:] = -1
+    elif start == "one_solute_cell":
+        phi0[3 + n * (4 + n * 5)] = -1
+    gst = _check_relax_from(w, phi0, start)
+    if start == "all_solvent":
+        assert (gst["sweeps"], gst["flips"], gst["band"]) == (1, 0, 0)
 
 
 def test_minimize_fp64_single_atom_64():
