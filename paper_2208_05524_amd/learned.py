@@ -49,7 +49,9 @@ class UNet:
     backward and Adam through the library's kernels."""
 
     def __init__(self, size: int, batch: int = 1, device: int = 0, seed: int = 0,
-                 weights=None):
+                 weights=None, train: bool = True):
+        """train=False: inference only (no gradients, optimiser state or
+        weight-gradient scratch)."""
         import torch
         if size % 8:
             raise ValueError("grid size must be a multiple of 8 (three poolings)")
@@ -68,16 +70,24 @@ class UNet:
                 w=torch.tensor(np.asarray(w, np.float32).reshape(27, cout, cin), **f32),
                 bias=torch.tensor(np.asarray(bias, np.float32), **f32),
                 wf=torch.empty(27 * cout * cin, dtype=torch.bfloat16, device=self.dev),
-                wb=torch.empty(27 * cout * cin, dtype=torch.bfloat16, device=self.dev),
-                gw=torch.zeros(27 * cout * cin, **f32), gb=torch.zeros(cout, **f32))
+                wb=torch.empty(27 * cout * cin, dtype=torch.bfloat16, device=self.dev))
+            if train:
+                self.p[name].update(gw=torch.zeros(27 * cout * cin, **f32),
+                                    gb=torch.zeros(cout, **f32))
         hw, hb = w0["head"]
         self.p["head"] = dict(w=torch.tensor(np.asarray(hw, np.float32), **f32),
-                              bias=torch.tensor(np.asarray(hb, np.float32), **f32),
-                              gw=torch.zeros(LEVELS[0], **f32), gb=torch.zeros(1, **f32))
+                              bias=torch.tensor(np.asarray(hb, np.float32), **f32))
+        self.step_count = 0
+        self.partial = torch.zeros(1024, dtype=torch.float64, device=self.dev)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        if not train:
+            self.adam, self.ws, self.ws_bytes = None, None, 0
+            self.prep()
+            return
+        self.p["head"].update(gw=torch.zeros(LEVELS[0], **f32), gb=torch.zeros(1, **f32))
         self.adam = {k: (torch.zeros_like(v["w"]), torch.zeros_like(v["w"]),
                          torch.zeros_like(v["bias"]), torch.zeros_like(v["bias"]))
                      for k, v in self.p.items()}
-        self.step_count = 0
         # weight-gradient scratch: the largest layer at its resolution
         need = 0
         for name, cin, cout in self.specs:
@@ -89,9 +99,18 @@ class UNet:
         need = max(need, 4 * LEVELS[0] * (batch * size ** 3 // 1024 + 1))  # head sums
         self.ws = torch.empty(need // 4 + 1, **f32)
         self.ws_bytes = need
-        self.partial = torch.zeros(1024, dtype=torch.float64, device=self.dev)
-        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
         self.prep()
+
+    def weights(self):
+        """The FP32 master weights, in the form the constructor takes."""
+        out = {}
+        for name, cin, cout in self.specs:
+            q = self.p[name]
+            out[name] = (q["w"].cpu().numpy().reshape(27, cout, cin).copy(),
+                         q["bias"].cpu().numpy().copy())
+        h = self.p["head"]
+        out["head"] = (h["w"].cpu().numpy().copy(), h["bias"].cpu().numpy().copy())
+        return out
 
     # ------------------------------------------------------------ helpers
     def _size_of(self, name):
@@ -477,9 +496,14 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
                          plain_flips=sp["flips"], learned_flips=sl["flips"],
                          plain_ms=1e3 * (tb - ta), learned_ms=1e3 * (td - tc),
                          G_plain=gp, G_learned=gl, label_agreement=agree))
-    # batched: every test molecule at once
+    # batched: every test molecule at once; the network's inference either
+    # one molecule at a time or as one batch of all of them (a copy of the
+    # trained weights in an inference-only model of that batch size)
     b = Batch(ctxs)
     times = {}
+    inf = UNet(128, batch=len(test_set), weights=model.weights(), train=False)
+    xb = inf._act(128, IN_C)
+    n3 = 128 ** 3
     for rep in range(2):
         for c, w in zip(ctxs, test_set):
             c.set_positions(w.xyz)
@@ -497,7 +521,21 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
             c.init_labels_logits(predict_logits(model, a[0], a[1], a[2], w.h, w.center))
         rc, stl = b.minimize()
         torch.cuda.synchronize()
+        times["learned_batched_serial_inference_ms"] = 1e3 * (time.perf_counter() - ta)
+        for c, w in zip(ctxs, test_set):
+            c.set_positions(w.xyz)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for i, (w, a) in enumerate(zip(test_set, arrays)):
+            inf.featurize(a[0], a[1], a[2], w.h, w.center, out=xb[i:i + 1])
+        logits = inf.forward(xb, keep=False)
+        for i, c in enumerate(ctxs):
+            c.init_labels_logits(logits[i * n3:(i + 1) * n3])
+        rc, stl2 = b.minimize()
+        torch.cuda.synchronize()
         times["learned_batched_ms"] = 1e3 * (time.perf_counter() - ta)
+        del logits
+        assert [s_["sweeps"] for s_ in stl2] == [s_["sweeps"] for s_ in stl]
     for c in ctxs:
         c.close()
     dG = [abs(r["G_learned"] - r["G_plain"]) / abs(r["G_plain"]) for r in rows]

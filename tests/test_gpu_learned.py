@@ -76,6 +76,26 @@ def test_inference_forward_equals_training_forward():
     assert torch.equal(l0, l1)
 
 
+def test_batched_inference_equals_one_molecule_at_a_time():
+    """An inference-only model of batch 3 built from another model's weights
+    gives, for each sample, the logits that model gives for it alone, bit for
+    bit (32^3: the decoder's 16^3 level reads its inputs in place)."""
+    import torch
+
+    from paper_2208_05524_amd.learned import IN_C, UNet
+    m = UNet(32, seed=4)
+    r = np.random.default_rng(8)
+    x = _dev_bf16(np.abs(r.standard_normal((3, 32, 32, 32, IN_C))))
+    one = [m.forward(x[i:i + 1].contiguous(), keep=False).clone() for i in range(3)]
+    inf = UNet(32, batch=3, weights=m.weights(), train=False)
+    assert inf.adam is None and "gw" not in inf.p["e1a"]
+    lb = inf.forward(x, keep=False)
+    torch.cuda.synchronize()
+    n3 = 32 ** 3
+    for i in range(3):
+        assert torch.equal(lb[i * n3:(i + 1) * n3], one[i]), i
+
+
 @pytest.mark.parametrize("n,cin,cout,relu", [(8, 32, 64, 1), (6, 16, 32, 0), (5, 96, 32, 1),
                                              (16, 32, 64, 1), (20, 32, 32, 1), (18, 16, 64, 0),
                                              (24, 96, 32, 1)])
