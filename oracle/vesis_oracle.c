@@ -639,7 +639,7 @@ int orc_colour_of(const orc_sys* s, int64_t idx) {
 int64_t orc_colour_pass(const orc_sys* s, int8_t* phi, const double* u, int colour,
                         double tie_tol, int64_t* ncand_out, double* de_sum, int64_t* tie_log,
                         double* tie_de, int64_t tie_cap, int64_t* ntie) {
-    int64_t n = s->n, ncell = n * n * n;
+    int64_t n = s->n;
     int p = (int)ceil(s->rho_s);
     int64_t cap = ((n + p - 1) / p) * ((n + p - 1) / p) * ((n + p - 1) / p), nc = 0;
     /* cap: the cells of one colour, ceil(n / p) along each axis at most */
