@@ -47,6 +47,39 @@ def test_batch_of_one_and_mixed_far_nodes():
     _check_batch(mixed, 0)
 
 
+def test_batch_recomputes_only_the_molecules_that_moved():
+    """After a batched relaxation, one molecule's atoms move: the next batch
+    call recomputes the density and far field of that molecule alone (the
+    others keep theirs) and ends where a fresh single context ends, bit for
+    bit; the others keep their labels and energies."""
+    from paper_2208_05524_amd import Batch
+    ws = _molecules()[:3]
+    ctxs = [gpu_context(w) for w in ws]
+    for c in ctxs:
+        c.init_labels("tight", 1.0)
+    b = Batch(ctxs)
+    assert b.minimize()[0] == 0
+    before = [(c.labels(), c.energy()) for c in ctxs]
+    moved = ws[1].xyz + np.array([0.013, -0.007, 0.011])
+    ctxs[1].set_positions(moved)
+    ctxs[1].init_labels("tight", 1.0)
+    rc, st = b.minimize()
+    assert rc == 0
+    for i in (0, 2):
+        assert np.array_equal(ctxs[i].labels(), before[i][0])
+        assert ctxs[i].energy() == before[i][1]
+    w1 = dataclasses.replace(ws[1], xyz=moved)
+    single = gpu_context(w1)
+    single.init_labels("tight", 1.0)
+    _, sst = single.minimize()
+    assert np.array_equal(single.labels(), ctxs[1].labels())
+    assert (sst["sweeps"], sst["flips"], sst["band"]) == (st[1]["sweeps"], st[1]["flips"],
+                                                          st[1]["band"])
+    e, es = ctxs[1].energy(), single.energy()
+    for k in ("vdw_in", "elec_in", "vdw_far", "elec_far", "geom", "total"):
+        assert e[k] == es[k], k
+
+
 def _check_batch(ws, variant):
     from paper_2208_05524_amd import Batch
     ctxs = [gpu_context(w) for w in ws]
