@@ -249,9 +249,19 @@ def cpu_baseline(w, budget_s: float = 12.0):
                 break
     except OSError:
         pass
+    # one thread, one z-plane
+    z = w.center[2] - L + (n // 2 + 0.5) * w.h
+    pts = np.stack([X.ravel(), Y.ravel(), np.full(n * n, z)], axis=1)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    s.density_points(pts)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    single = {"value": n * n * w.natoms / dt1, "unit": "atom·gridpt/s", "cores": 1,
+              "sample": f"one z-plane ({n * n} cells) x {w.natoms} atoms, {dt1:.1f} s"}
     chain = cpu_chain_equilibrium()
     return {"value": pairs / dt, "unit": "atom·gridpt/s", "cores": cores, "kind": "oracle",
-            "chain_1000_128": chain,
+            "single_thread": single, "chain_1000_128": chain,
             "sample": f"FP64 oracle density over {planes} z-planes ({planes * n * n} cells) of "
                       f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s on {cores} threads of "
                       f"{model}; the GPU value is a whole hot-path step, whose density work "

@@ -107,6 +107,11 @@ def default_mobility(dt: float = 0.1) -> Mobility:
                     N_cnt=0, N_cnt_max=5, k=0, max_retries=200)
 
 
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops (timing only)."""
+    lib().orc_set_threads(int(n))
+
+
 def lib():
     global _LIB
     if _LIB is None:

@@ -42,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -1210,4 +1213,14 @@ int orc_relax(const orc_sys* s0, double* xyz, int8_t* phi, const uint8_t* movabl
     rep->stop_reason = reason;
     free(ulj); free(ucfa); free(u); free(f);
     return reason == 3 ? 1 : 0;
+}
+
+/* Threads of the OpenMP loops (measurement only: no result depends on it,
+ * every parallel loop writing disjoint entries). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
