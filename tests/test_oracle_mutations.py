@@ -82,7 +82,14 @@ MUTATIONS = [
     ("pair_force_drops_coulomb", "*du = (4.0 * ep * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r - kq / r2) / r;",
      "*du = (4.0 * ep * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r) / r;",
      "test_oracle_solute.py::test_ss_forces_match_central_differences"),
-    ("total_forces_skip_solute", "        for (int64_t k = 0; k < 3 * s->na; ++k) f[k] -= g[k];\n", "",
+    ("subset_drops_far_field",
+     "            gx += fw[p] * g[0];\n            gy += fw[p] * g[1];\n"
+     "            gz += fw[p] * g[2];\n", "",
+     "test_forces_subset_equals_the_rows_of_the_full_forces"),
+    ("subset_bond_sign_on_j", "(r - r0[b]) / r * (i == a ? 1.0 : -1.0);",
+     "(r - r0[b]) / r * (i == a ? 1.0 : 1.0);",
+     "test_forces_subset_equals_the_rows_of_the_full_forces"),
+    ("total_forces_skip_solute","        for (int64_t k = 0; k < 3 * s->na; ++k) f[k] -= g[k];\n", "",
      "test_oracle_solute.py::test_total_forces_include_the_solute_terms"),
 ]
 

@@ -593,6 +593,32 @@ def test_forces_match_central_differences():
     np.testing.assert_allclose(f, fd, rtol=1e-5, atol=1e-6 * np.abs(f).max())
 
 
+def test_forces_subset_equals_the_rows_of_the_full_forces():
+    """The per-atom force sum used on large grids (field given per cell, its
+    own far-field, bond and solute-solute loops) equals the rows of the full
+    force sum, itself pinned by central differences, to 1e-12 relative.  A
+    charged, bonded chain with bending, torsion and non-bonded terms; the
+    sample lists atoms out of order and holds both chain ends and interior
+    atoms, so each atom is the first and the second atom of some bond."""
+    natoms = 8
+    xyz = synth.globule(natoms, seed=84) * 1.5
+    w = synth.random_small(16, natoms, seed=84, h=0.07)
+    top = synth.chain_topology([(0, natoms)], seed=84, exclude=1)
+    ss = oracle.SoluteTerms(top.angles, top.theta0, top.k_angle, top.torsions, top.c, top.psi,
+                            True, None, None, top.exclusions)
+    bonds, r0, kb = synth.chain_bonds(natoms)
+    s = oracle.System(w.n, w.h, w.center, xyz, w.q, w.sigma, w.eps, w.params, bonds, r0,
+                      kb * 1e-2, ss)
+    phi = s.init_tight()
+    assert 0 < np.count_nonzero(phi == -1) < phi.size
+    f = s.forces(phi)
+    _, _, e = s.density_grid(efield=True)
+    sel = np.array([natoms - 1, 3, 0, 5, 1])
+    fs = s.forces_subset(phi, e, sel)
+    scale = np.linalg.norm(f, axis=1).max()
+    assert np.abs(fs - f[sel]).max() <= 1e-12 * scale, np.abs(fs - f[sel]).max() / scale
+
+
 # ------------------------------------------------------------ atom step
 
 def test_adaptive_mobility_relaxes_a_bond_to_its_rest_length():
