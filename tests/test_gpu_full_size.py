@@ -5,8 +5,9 @@ apart on 256^3 cells of 0.05 nm, in the launch configuration bench.py times
 The oracle computes the whole grid here (density with field, initial
 labels, colour minimisation, energy) on the host cores, and forces on 64
 seeded atoms.  Every cell's density must lie inside the kernel's certified
-bound; labels, sweep and flip counts must match exactly when the oracle saw
-no decision inside 1e-9 |G|; energies within 1e-6 |G|; forces within 1e-4.
+bound; labels, sweep and flip counts must match exactly, except at cells
+whose oracle decision fell inside 1e-9 |G|; energies within 1e-6 |G|;
+forces within 1e-4.
 A last test checks the FP64 force adjoint at this size against
 Richardson-extrapolated central differences of the energy.
 """
@@ -16,9 +17,19 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import energies_close, force_close, gpu_context, log, oracle_system
+from helpers import check_labels, energies_close, force_close, gpu_context, log, oracle_system
 
 pytestmark = pytest.mark.gpu
+
+
+def _sample_atoms(natoms, seed, count=64):
+    """count distinct atoms in the order the generator draws them (so the
+    sample spans both globules and every atom workgroup of the adjoint)."""
+    v = (synth.SplitMix64(seed).uniform(4 * count) * natoms).astype(np.int64)
+    first = np.unique(v, return_index=True)[1]
+    sel = v[np.sort(first)][:count]
+    assert len(sel) == count
+    return sel
 
 
 @pytest.fixture(scope="module")
@@ -47,8 +58,8 @@ def full():
     e = s.energy(phi, oulj, oucfa, far)
     e["bond"] = s.bond_energy()
     e["total"] += e["bond"]
-    rng = synth.SplitMix64(3064)
-    sel = np.unique((rng.uniform(200) * w.natoms).astype(np.int64))[:64]
+    sel = _sample_atoms(w.natoms, 3064)
+    log("sampled atoms span", int(sel.min()), "to", int(sel.max()))
     out.update(s=s, o_ulj=oulj, o_ucfa=oucfa, o_lab=phi, o_st=ost, o_ties=ties, o_e=e, sel=sel,
                o_f=s.forces_subset(phi, oe, sel))
     log("oracle forces done", f"{time.time() - t0:.1f}s")
@@ -76,17 +87,8 @@ def test_full_size_labels_and_energy(full):
     gst, ost = full["gst"], full["o_st"]
     log("gpu", gst, "oracle", ost)
     assert full["rc"] == 0 and gst["converged"] == 1 and ost["converged"] == 1
-    same = np.array_equal(full["g_lab"], full["o_lab"])
-    log("labels identical:", same, "oracle decisions inside 1e-9 |G|:", len(full["o_ties"]))
-    if len(full["o_ties"]) == 0:
-        assert same
-    if same:
-        assert (gst["sweeps"], gst["flips"], gst["band"]) == \
-            (ost["sweeps"], ost["flips"], ost["band"])
-    else:
-        # only decisions inside the 1e-9 |G| window may differ: both results
-        # must still be local minima of (almost) the same energy
-        assert len(full["o_ties"]) > 0
+    assert full["o_st"]["ties"] == len(full["o_ties"])  # every near tie logged
+    check_labels(full["g_lab"], full["o_lab"], full["o_ties"], gst, ost, what="full size")
     bad = energies_close(full["g_e"], full["o_e"], 1e-6, keys=("geom", "vdw_in", "vdw_far",
                                                              "elec_in", "elec_far", "bond",
                                                              "total"))
@@ -101,10 +103,12 @@ def test_full_size_forces_on_sampled_atoms(full):
     assert ok.all()
 
 
-def test_full_size_forces_match_central_differences_fp64():
+@pytest.mark.parametrize("chunk", range(4))
+def test_full_size_forces_match_central_differences_fp64(chunk):
     """The force adjoint at the benchmark's full size against central
-    differences of the energy at fixed labels, with FP64 densities, on 12
-    seeded atoms x 3 directions; 1e-4 relative, as for the oracle comparison.
+    differences of the energy at fixed labels, with FP64 densities, on 64
+    seeded atoms (16 per chunk, drawn across both globules) x 3 directions;
+    1e-4 relative, as for the oracle comparison.
 
     At this size the central difference with step h = 1e-4 nm still carries
     its O(h^2) truncation error (up to ~5e-3 relative here: the difference
@@ -118,8 +122,7 @@ def test_full_size_forces_match_central_differences_fp64():
     ctx.init_labels("tight", 1.0)
     t0 = time.time()
     f = ctx.forces()
-    rng = synth.SplitMix64(3065)
-    sel = np.unique((rng.uniform(40) * w.natoms).astype(np.int64))[:12]
+    sel = _sample_atoms(w.natoms, 3065)[16 * chunk:16 * (chunk + 1)]
     hfd = 1e-4
 
     def central(a, d, step):
