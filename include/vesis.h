@@ -32,7 +32,8 @@
  *  - Call order: vesis_set_params, vesis_set_grid, vesis_set_atoms,
  *    vesis_set_workspace, vesis_init_labels; a call made before its inputs
  *    exist returns VESIS_E_STATE.  Changing the grid or the atom count
- *    invalidates the workspace and the labels.
+ *    invalidates the workspace and the labels; changing the precision
+ *    invalidates the workspace (its per-cell arrays change size).
  *  - One host thread per context at a time; separate contexts are independent.
  */
 #ifndef VESIS_H
@@ -314,9 +315,12 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* batch
 /* Copy the labels (n^3 int8, -1/+1) to host memory. */
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out);
 
-/* Copy the per-cell density parts U_LJ and U_CFA (n^3 FP64 each) and,
- * if bound != NULL, the per-cell bound on |U_computed - U_exact| used for
- * near-tie decisions (n^3 FP64). */
+/* Copy the per-cell density parts U_LJ and U_CFA (n^3 values each, x
+ * fastest, written as FP64) and, if bound != NULL, the per-cell bound on
+ * |U_stored - U_exact| used for near-tie decisions (n^3).  The library
+ * stores them in the precision of the density sums: with precision 32 as
+ * FP32 (widened here; the bound includes that storage rounding), with
+ * precision 64 as FP64. */
 vesis_status vesis_get_density(vesis_ctx* ctx, double* u_lj, double* u_cfa, double* bound);
 
 /* Kernel timing for measurement: enable != 0 records HIP events around

@@ -126,6 +126,7 @@ struct vesis_ctx {
     Layout lay{};
     int64_t lay_na = -1, lay_nb = -1, lay_nfar = -1;
     int64_t lay_nang = 0, lay_ntor = 0, lay_nxo = 0;
+    int lay_cell_bytes = 0;  // bytes per stored cell value of the planned layout
     bool lay_nonbonded = false;
     int lay_n = -1;
 
@@ -287,6 +288,10 @@ void compute_far_nodes(vesis_ctx* c) {
     c->far_uploaded = false;
 }
 
+// Bytes per stored per-cell density value: float with FP32 sums, double
+// with FP64 sums.
+int cell_bytes(const vesis_ctx* c) { return c->prm.precision == 64 ? 8 : 4; }
+
 Layout plan(const vesis_ctx* c) {
     Layout L{};
     size_t o = 0;
@@ -305,12 +310,14 @@ Layout plan(const vesis_ctx* c) {
     L.bother = take(4 * nbi);
     L.br0 = take(8 * nbi);
     L.bk = take(8 * nbi);
-    L.ulj = take(8 * ncell);
-    L.ucfa = take(8 * ncell);
-    L.ex = take(8 * ncell);
-    L.ey = take(8 * ncell);
-    L.ez = take(8 * ncell);
-    L.bound = take(8 * ncell);
+    // density outputs in the precision of the sums (float for FP32)
+    const int64_t cb = cell_bytes(c);
+    L.ulj = take(cb * ncell);
+    L.ucfa = take(cb * ncell);
+    L.ex = take(cb * ncell);
+    L.ey = take(cb * ncell);
+    L.ez = take(cb * ncell);
+    L.bound = take(cb * ncell);
     L.u64cache = take(16 * ncell);
     L.bits = take(4 * c->g.nwords());
     L.stamp = take(4 * c->g.nwords());
@@ -451,12 +458,13 @@ vesis_status density_tail(vesis_ctx* ctx);
 
 CellFields cell_fields(vesis_ctx* ctx) {
     CellFields cf;
-    cf.ulj = at<double>(ctx, ctx->lay.ulj);
-    cf.ucfa = at<double>(ctx, ctx->lay.ucfa);
-    cf.ex = at<double>(ctx, ctx->lay.ex);
-    cf.ey = at<double>(ctx, ctx->lay.ey);
-    cf.ez = at<double>(ctx, ctx->lay.ez);
-    cf.bound = at<double>(ctx, ctx->lay.bound);
+    cf.ulj = ctx->ws + ctx->lay.ulj;
+    cf.ucfa = ctx->ws + ctx->lay.ucfa;
+    cf.ex = ctx->ws + ctx->lay.ex;
+    cf.ey = ctx->ws + ctx->lay.ey;
+    cf.ez = ctx->ws + ctx->lay.ez;
+    cf.bound = ctx->ws + ctx->lay.bound;
+    cf.f32 = ctx->prm.precision == 64 ? 0 : 1;
     return cf;
 }
 
@@ -552,8 +560,7 @@ vesis_status compute_energy(vesis_ctx* ctx, vesis_energy_parts* out) {
     const uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
     {
         Timed t(ctx, K_ENERGY);
-        CK(launch_energy_volume(ctx->g, bits, at<double>(ctx, ctx->lay.ulj),
-                                at<double>(ctx, ctx->lay.ucfa), at<double>(ctx, ctx->lay.red_d),
+        CK(launch_energy_volume(ctx->g, bits, cell_fields(ctx), at<double>(ctx, ctx->lay.red_d),
                                 RED_BLOCKS, at<double>(ctx, ctx->lay.scal_d) + SD_VOL, st));
         CK(launch_geom_counts(ctx->g, bits, at<int64_t>(ctx, ctx->lay.red_i), RED_BLOCKS,
                               at<int64_t>(ctx, ctx->lay.scal_i) + SI_GEOM, st));
@@ -601,8 +608,8 @@ vesis_status compute_forces(vesis_ctx* ctx, double* f_host) {
     if (!ctx->forces_valid) {
         Timed t(ctx, K_FORCE);
         CK(launch_forces(ctx->g, dev_atoms(ctx), ph, ctx->prm.precision,
-                         at<uint32_t>(ctx, ctx->lay.bits), at<double>(ctx, ctx->lay.ex),
-                         at<double>(ctx, ctx->lay.ey), at<double>(ctx, ctx->lay.ez),
+                         at<uint32_t>(ctx, ctx->lay.bits), ctx->ws + ctx->lay.ex,
+                         ctx->ws + ctx->lay.ey, ctx->ws + ctx->lay.ez,
                          at<double4>(ctx, ctx->lay.far_pts), at<double>(ctx, ctx->lay.far_ex),
                          at<double>(ctx, ctx->lay.far_ey), at<double>(ctx, ctx->lay.far_ez),
                          ctx->nfar, dev_bonds(ctx),
@@ -729,6 +736,8 @@ vesis_status vesis_set_params(vesis_ctx* ctx, const vesis_params* p) {
     const bool rho_changed = !ctx->has_params || p->rho_w != ctx->prm.rho_w;
     ctx->prm = *p;
     ctx->has_params = true;
+    // the stored densities change size with the precision
+    if (ctx->has_ws && ctx->lay_cell_bytes != cell_bytes(ctx)) ctx->has_ws = false;
     ctx->dens_valid = false;
     ctx->ss_valid = false;
     ctx->forces_valid = false;
@@ -1042,6 +1051,7 @@ vesis_status vesis_set_workspace(vesis_ctx* ctx, void* device_ptr, size_t bytes)
     ctx->lay_nxo = (int64_t)ctx->x_other.size();
     ctx->lay_nonbonded = ctx->nonbonded;
     ctx->lay_nfar = ctx->nfar;
+    ctx->lay_cell_bytes = cell_bytes(ctx);
     ctx->lay_n = ctx->g.n;
     ctx->has_ws = true;
     ctx->atoms_uploaded = false;
@@ -1125,6 +1135,7 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
     hipStream_t st = ctx->stream;
     const Atoms a = dev_atoms(ctx);
     const Physics ph = dev_physics(ctx);
+    const CellFields cf = cell_fields(ctx);
     const int ncol = ctx->sc.p * ctx->sc.p * ctx->sc.p;
     uint32_t* bits = at<uint32_t>(ctx, ctx->lay.bits);
     int* flips = at<int>(ctx, ctx->lay.sweep_flips);
@@ -1144,10 +1155,8 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
             for (int sw = 0; sw < nb; ++sw)
                 for (int c = 0; c < ncol; ++c)
                     CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw, (sweeps + sw) * ncol + c,
-                                        bits, stamp, at<double>(ctx, ctx->lay.ulj),
-                                        at<double>(ctx, ctx->lay.ucfa),
-                                        at<double>(ctx, ctx->lay.bound),
-                                        at<double>(ctx, ctx->lay.u64cache), flips, counters, st));
+                                        bits, stamp, cf, at<double>(ctx, ctx->lay.u64cache), flips,
+                                        counters, st));
         }
         int hf[SWEEP_BATCH];
         CK(hipMemcpyAsync(hf, flips, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
@@ -1802,11 +1811,28 @@ vesis_status vesis_get_density(vesis_ctx* ctx, double* u_lj, double* u_cfa, doub
     if (s != VESIS_OK) return s;
     s = ensure_density(ctx);
     if (s != VESIS_OK) return s;
-    const size_t nb = 8 * (size_t)ctx->g.ncell();
-    CK(hipMemcpyAsync(u_lj, ctx->ws + ctx->lay.ulj, nb, hipMemcpyDeviceToHost, ctx->stream));
-    CK(hipMemcpyAsync(u_cfa, ctx->ws + ctx->lay.ucfa, nb, hipMemcpyDeviceToHost, ctx->stream));
-    if (bound) CK(hipMemcpyAsync(bound, ctx->ws + ctx->lay.bound, nb, hipMemcpyDeviceToHost, ctx->stream));
-    CK(hipStreamSynchronize(ctx->stream));
+    const size_t ncell = (size_t)ctx->g.ncell();
+    if (ctx->prm.precision == 64) {
+        const size_t nb = 8 * ncell;
+        CK(hipMemcpyAsync(u_lj, ctx->ws + ctx->lay.ulj, nb, hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipMemcpyAsync(u_cfa, ctx->ws + ctx->lay.ucfa, nb, hipMemcpyDeviceToHost, ctx->stream));
+        if (bound)
+            CK(hipMemcpyAsync(bound, ctx->ws + ctx->lay.bound, nb, hipMemcpyDeviceToHost,
+                              ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        return VESIS_OK;
+    }
+    // FP32 storage: copied as stored, widened on the host
+    std::vector<float> tmp(ncell);
+    double* dst[3] = {u_lj, u_cfa, bound};
+    const size_t off[3] = {ctx->lay.ulj, ctx->lay.ucfa, ctx->lay.bound};
+    for (int k = 0; k < 3; ++k) {
+        if (!dst[k]) continue;
+        CK(hipMemcpyAsync(tmp.data(), ctx->ws + off[k], 4 * ncell, hipMemcpyDeviceToHost,
+                          ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        for (size_t c = 0; c < ncell; ++c) dst[k][c] = (double)tmp[c];
+    }
     return VESIS_OK;
 }
 

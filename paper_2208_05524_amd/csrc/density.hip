@@ -19,10 +19,14 @@
 //    4 rho_w eps sigma^6 and 4 rho_w eps sigma^12;
 //  * FP32 partial sums over 32 atoms are summed over the 256-atom tile in
 //    FP32 and folded into FP64 once per tile;
+//  * atoms within 16 cells of the brick centre are summed in FP64 (they
+//    carry most of a cell's U, and with it most of the FP32 rounding);
 //  * beside U the kernel keeps the absolute sum sum 4 eps (s^6 + s^3) per
 //    cell and, per atom tile, a brick-wide bound on sum |Q|/r^2, from which
-//    the epilogue writes a bound on |U_fp32 - U_exact| per cell; flip
-//    decisions inside that bound are redone in FP64.
+//    the epilogue writes a bound on |U_stored - U_exact| per cell; flip
+//    decisions inside that bound are redone in FP64;
+//  * U_LJ, U_CFA, the field E and the bound are stored as float (24 bytes
+//    per cell); the FP64 kernel stores doubles.
 #include "internal.h"
 #include "reduce.h"
 
@@ -39,10 +43,11 @@ constexpr int DWG = 256;
 constexpr int BX = 16, BY = 8, BZ = 4, KC = 2;
 constexpr int TILE = 256;
 
-// Error bound of the FP32 path.  Atoms within 12h of the brick centre are
-// summed in FP64; the others are at r >= 12h - |c| >= 3.6h from every cell
-// of the 16 x 8 x 4 brick (|c| <= 8.4h), so |c|/r <= 2.4 and, with
-// u = 2^-24:
+// Error bound of the FP32 path.  Atoms within NEAR_CELLS = 16 cells of the
+// brick centre are summed in FP64; the others are at r >= 16h - |c| >= 7.6h
+// from every cell of the 16 x 8 x 4 brick (|c| <= 8.4h).  The bound below is
+// derived for |c|/r <= 2.4 (which held for a radius of 12 cells) and so holds
+// with margin; with u = 2^-24:
 //  * coordinates: d = fl(c - fl(r_i - O)) has |d_err| <= u (|a| + |c| + r)
 //    <= u (2|c| + 2r), so rel(r^2) <= 4u(|c|/r + 1) + 2u <= 16u;
 //  * rsqrt (1 ulp): rel(1/r) <= 9u; r^-2: 18.5u; r^-3 = r^-2 r^-1: 28.5u;
@@ -65,6 +70,17 @@ constexpr double KAPPA_LJ = 192.0;
 constexpr double KAPPA_E = 96.0;
 constexpr double NEAR_REL = 1.0e-9;
 constexpr int SUB = 32;                           // atoms per FP32 partial
+// FP64 radius in cells.  The FP32 terms carry rounding that does not average
+// out over a cell's sum: v_rsq_f32 returns the value one ulp below the
+// correctly rounded one for about one input in ten (mean relative error
+// -0.12 u over all inputs), which the power chain scales by 6 and 12 on the
+// LJ terms, and each far atom's coordinates are rounded once per brick.  Both
+// weigh by the size of the term, i.e. by the nearest far atoms (r^-6 for
+// the attractive LJ term): moving the FP64 radius from 12 to 16 cells cuts
+// the FP32 share of U_LJ at a far atom's closest approach by (3.6/7.6)^6 and
+// the summed rounding of a small molecule's volume energy several-fold, for
+// about 2 % more work on a 10^4-atom globule.
+constexpr double NEAR_CELLS = 16.0;
 
 // Bound on |U - U_exact| from a bound on the LJ part (errLJ) and a per-
 // component bound on the field (errE): |E'|^2 - |E|^2 <= 2|E'| d + d^2 with
@@ -114,10 +130,10 @@ __device__ __forceinline__ void density_brick_f32(const Grid& g, const Atoms& a,
         cz[k] = (float)((tz * KCV + k - 0.5 * (BZV - 1)) * g.h);
         z64[k] = g.z0 + (k0 + k) * g.h;
     }
-    // atoms within 12h of the brick centre are "near": they are summed in
-    // FP64; every other atom is at least 12h - 8.4h > 3h from every cell
-    // (and beyond the r2_min floor)
-    const double rnear = 12.0 * g.h + 4.0 * sqrt(ph.r2min);
+    // atoms within NEAR_CELLS cells of the brick centre are "near": they are
+    // summed in FP64; every other atom is at least (NEAR_CELLS - 8.4) h from
+    // every cell (and beyond the r2_min floor)
+    const double rnear = NEAR_CELLS * g.h + 4.0 * sqrt(ph.r2min);
     const float rnear2 = (float)(rnear * rnear);
     // half extents of the box spanned by the brick's cell centres
     const double hxe = 0.5 * (BX - 1) * g.h, hye = 0.5 * (BY - 1) * g.h, hze = 0.5 * (BZV - 1) * g.h;
@@ -270,20 +286,31 @@ __device__ __forceinline__ void density_brick_f32(const Grid& g, const Atoms& a,
     }
 
     if (i >= g.n || j >= g.n) return;
+    float* o_lj = static_cast<float*>(out.ulj);
+    float* o_cfa = static_cast<float*>(out.ucfa);
+    float* o_ex = static_cast<float*>(out.ex);
+    float* o_ey = static_cast<float*>(out.ey);
+    float* o_ez = static_cast<float*>(out.ez);
+    float* o_b = static_cast<float*>(out.bound);
 #pragma unroll
     for (int k = 0; k < KCV; ++k) {
         const int kk = k0 + k;
         if (kk >= g.n) continue;
         const int64_t c = (int64_t)i + (int64_t)g.n * (j + (int64_t)g.n * kk);
         const double e2 = dEx[k] * dEx[k] + dEy[k] * dEy[k] + dEz[k] * dEz[k];
-        out.ulj[c] = dP[k] - dQ[k];
-        out.ucfa[c] = ph.ccfa * e2;
-        out.ex[c] = dEx[k];
-        out.ey[c] = dEy[k];
-        out.ez[c] = dEz[k];
-        out.bound[c] = cell_bound(KAPPA_LJ * U32 * dMag[k] + NEAR_REL * nMag[k],
-                                  KAPPA_E * U32 * dAE[k] + NEAR_REL * nAE[k], dEx[k], dEy[k],
-                                  dEz[k], ph.ccfa);
+        const double ulj = dP[k] - dQ[k], ucfa = ph.ccfa * e2;
+        // FP32 storage: the bound adds the rounding of both parts to float
+        // (u each) and is itself rounded up
+        const double b = cell_bound(KAPPA_LJ * U32 * dMag[k] + NEAR_REL * nMag[k],
+                                    KAPPA_E * U32 * dAE[k] + NEAR_REL * nAE[k], dEx[k], dEy[k],
+                                    dEz[k], ph.ccfa) +
+                         U32 * (fabs(ulj) + fabs(ucfa));
+        o_lj[c] = (float)ulj;
+        o_cfa[c] = (float)ucfa;
+        o_ex[c] = (float)dEx[k];
+        o_ey[c] = (float)dEy[k];
+        o_ez[c] = (float)dEz[k];
+        o_b[c] = (float)(b * (1.0 + 0x1p-22));
     }
 }
 
@@ -370,18 +397,23 @@ __global__ __launch_bounds__(DWG) void density_grid_f64(Grid g, Atoms a, Physics
     // FP64: one sequential sum over all atoms; coordinates are not rebased,
     // so allow 1e7 u of relative error per term (|x| / r up to ~1e5)
     const double kappa = ((double)a.n + 1.0e7) * U64;
+    double* o_lj = static_cast<double*>(out.ulj);
+    double* o_cfa = static_cast<double*>(out.ucfa);
+    double* o_ex = static_cast<double*>(out.ex);
+    double* o_ey = static_cast<double*>(out.ey);
+    double* o_ez = static_cast<double*>(out.ez);
+    double* o_b = static_cast<double*>(out.bound);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int kk = k0 + k;
         if (kk >= g.n) continue;
         const int64_t c = (int64_t)i + (int64_t)g.n * (j + (int64_t)g.n * kk);
-        out.ulj[c] = P[k] - Q[k];
-        out.ucfa[c] = ph.ccfa * (Ex[k] * Ex[k] + Ey[k] * Ey[k] + Ez[k] * Ez[k]);
-        out.ex[c] = Ex[k];
-        out.ey[c] = Ey[k];
-        out.ez[c] = Ez[k];
-        out.bound[c] = cell_bound(kappa * (P[k] + Q[k]), kappa * AE[k], Ex[k], Ey[k], Ez[k],
-                                  ph.ccfa);
+        o_lj[c] = P[k] - Q[k];
+        o_cfa[c] = ph.ccfa * (Ex[k] * Ex[k] + Ey[k] * Ey[k] + Ez[k] * Ez[k]);
+        o_ex[c] = Ex[k];
+        o_ey[c] = Ey[k];
+        o_ez[c] = Ez[k];
+        o_b[c] = cell_bound(kappa * (P[k] + Q[k]), kappa * AE[k], Ex[k], Ey[k], Ez[k], ph.ccfa);
     }
 }
 
@@ -400,7 +432,16 @@ template <>
 struct PTypes<float> {
     using T4 = float4;
     static __device__ float4 mk(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
-    static __device__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    // the hardware estimate refined by one Newton step on the residual
+    // t = 1 - x y^2 (small, so an FMA keeps its relative accuracy): the
+    // estimate's bias (one ulp low for about one input in ten) is removed,
+    // which matters here because every node's sum is a sum of terms of one
+    // sign; the grid kernel bounds this error by its FP64 radius instead
+    static __device__ float rsq(float x) {
+        const float y = __builtin_amdgcn_rsqf(x);
+        const float t = fmaf(-x, y * y, 1.0f);
+        return fmaf(0.5f * y, t, y);
+    }
 };
 template <>
 struct PTypes<double> {

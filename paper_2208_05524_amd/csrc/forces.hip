@@ -68,9 +68,9 @@ struct ForceArgs {
     Atoms a;
     Physics ph;
     const uint32_t* bits;
-    const double* ex;
-    const double* ey;
-    const double* ez;
+    const void* ex;       // cell field, stored as T
+    const void* ey;
+    const void* ez;
     const double4* far_pts;
     const double* far_ex;
     const double* far_ey;
@@ -164,7 +164,8 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
                         const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
                         a = mk4((T)((lx - 0.5 * (CB - 1)) * g.h), (T)((ly - 0.5 * (CB - 1)) * g.h),
                                 (T)((lz - 0.5 * (CB - 1)) * g.h), (T)1);
-                        b = mk4((T)f.ex[c], (T)f.ey[c], (T)f.ez[c], (T)0);
+                        b = mk4(static_cast<const T*>(f.ex)[c], static_cast<const T*>(f.ey)[c],
+                                static_cast<const T*>(f.ez)[c], (T)0);
                         keep = true;
                     }
                 }
@@ -462,8 +463,8 @@ ForceSizes force_sizes(const Grid& g, int64_t natoms, int64_t nfar) {
 }
 
 hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int precision,
-                         const uint32_t* bits, const double* ex, const double* ey,
-                         const double* ez, const double4* far_pts, const double* far_ex,
+                         const uint32_t* bits, const void* ex, const void* ey,
+                         const void* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
                          const Bonds& bonds, const double* g_extra, const ForceScratch& scr,
                          double* f_out, hipStream_t st) {

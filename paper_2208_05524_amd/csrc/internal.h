@@ -56,15 +56,25 @@ struct Physics {
     double h3;       // cell volume
 };
 
-// Per-cell outputs of the density kernel.
+// Per-cell outputs of the density kernel, ncell values each (x fastest), in
+// the precision of the density sums: float with FP32 sums (f32 != 0), double
+// with FP64 sums.  bound bounds |U_stored - U_exact| in U units, where
+// U_stored = U_LJ + U_CFA as stored (for float storage it includes the
+// rounding of both to float, and is itself rounded up).
 struct CellFields {
-    double* ulj;
-    double* ucfa;
-    double* ex;
-    double* ey;
-    double* ez;
-    double* bound;   // bound on |U - U_exact| (U units)
+    void* ulj;
+    void* ucfa;
+    void* ex;
+    void* ey;
+    void* ez;
+    void* bound;
+    int f32;
 };
+
+// Value c of a per-cell array stored as float (f32 != 0) or double.
+__host__ __device__ inline double cell_value(const void* a, int f32, int64_t c) {
+    return f32 ? (double)static_cast<const float*>(a)[c] : static_cast<const double*>(a)[c];
+}
 
 enum KernelKind {
     K_DENSITY = 0, K_FAR = 1, K_INIT = 2, K_FLIP = 3, K_ENERGY = 4, K_FORCE = 5, K_OTHER = 6,
@@ -158,8 +168,8 @@ hipError_t launch_labels_from_logits(const Grid& g, const float* logits, uint32_
 // stamp: one int per label word, filled with a value < -p^3 before the call.
 hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
                             int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
-                            const double* ulj, const double* ucfa, const double* bound,
-                            double* u64cache, int* sweep_flips, int64_t* counters, hipStream_t st);
+                            const CellFields& f, double* u64cache, int* sweep_flips,
+                            int64_t* counters, hipStream_t st);
 // Batched colour pass: flip_slots(g, p) thread slots per molecule (a multiple
 // of the workgroup size), a molecule's blocks consecutive from slot0.
 constexpr int FLIP_WG = 256;
@@ -178,9 +188,8 @@ hipError_t launch_batch_clear_flips(const MolDesc* descs, int m, int nsweeps, hi
 hipError_t launch_batch_prepare(const MolDesc* descs, int m, int64_t max_words, hipStream_t st);
 hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int* out,
                                      hipStream_t st);
-hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
-                                const double* ucfa, double* partial, int nblocks, double* out,
-                                hipStream_t st);
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const CellFields& f,
+                                double* partial, int nblocks, double* out, hipStream_t st);
 hipError_t launch_geom_counts(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
                               int64_t* out, hipStream_t st);
 hipError_t launch_band_count(const Grid& g, const uint32_t* bits, int64_t* partial, int nblocks,
@@ -210,9 +219,11 @@ struct ForceScratch {
     int64_t counts;
 };
 ForceSizes force_sizes(const Grid& g, int64_t natoms, int64_t nfar);
+// ex, ey, ez: the cell field as stored by the density kernel of the same
+// precision (float for 32, double for 64).
 hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int precision,
-                         const uint32_t* bits, const double* ex, const double* ey,
-                         const double* ez, const double4* far_pts, const double* far_ex,
+                         const uint32_t* bits, const void* ex, const void* ey,
+                         const void* ez, const double4* far_pts, const double* far_ex,
                          const double* far_ey, const double* far_ez, int64_t nfar,
                          const Bonds& bonds, const double* g_extra, const ForceScratch& scr,
                          double* f_out, hipStream_t st);

@@ -292,9 +292,7 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
     const Physics& ph = D.ph;
     uint32_t* bits = D.bits;
     int* stamp = D.stamp;
-    const double* ulj = D.f.ulj;
-    const double* ucfa = D.f.ucfa;
-    const double* bound = D.f.bound;
+    const CellFields& cf = D.f;
     double* u64cache = D.u64cache;
     int* sweep_flips = D.sweep_flips;
     int64_t* counters = D.counters;
@@ -390,10 +388,11 @@ __global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDe
         }
         const double S = stencil_sum(sc, Wn, b);
         const double phi = ((Co >> b) & 1u) ? 1.0 : -1.0;
-        const double hU = ph.h3 * (ulj[c] + ucfa[c]);
+        const double hU =
+            ph.h3 * (cell_value(cf.ulj, cf.f32, c) + cell_value(cf.ucfa, cf.f32, c));
         const double cS = sc.c * S;
         const double dE = phi * (cS - hU);
-        const double tol = ph.h3 * bound[c] + 4.0e-16 * (fabs(cS) + fabs(hU));
+        const double tol = ph.h3 * cell_value(cf.bound, cf.f32, c) + 4.0e-16 * (fabs(cS) + fabs(hU));
         if (!(fabs(dE) > tol)) {
             const int b0o = ((ca - 32 * wo) % P + P) % P;
             s_cs[((b - b0o) / P) * FWG + to] = cS;
@@ -518,15 +517,15 @@ __global__ void batch_gather_flips(const MolDesc* descs, int m, int nsweeps, int
 
 // ------------------------------------------------------------ reductions
 
-// h^3-less sums of U_LJ and U_CFA over solvent cells (FP64).
-// Sums of U_LJ and U_CFA over solvent cells.  A wavefront takes whole
-// x-rows, two at a time (lanes along x: each load instruction reads 512
-// contiguous bytes), rows strided over the grid; U is loaded for every cell
+// Sums (without the h^3 weight) of U_LJ and U_CFA over solvent cells, from
+// U stored as T (float or double).  A wavefront takes whole x-rows, two at a
+// time (lanes along x: each load instruction reads 64 consecutive values),
+// rows strided over the grid; U is loaded for every cell
 // and selected by its label bit, so the loads do not wait for the labels.
 // Per-lane FP64 sums in a fixed order, then a fixed tree per workgroup.
+template <typename T>
 __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uint32_t* bits,
-                                                               const double* ulj,
-                                                               const double* ucfa,
+                                                               const T* ulj, const T* ucfa,
                                                                double* partial) {
     __shared__ double sh[RED_WG];
     double sa = 0.0, sb = 0.0;
@@ -540,11 +539,11 @@ __global__ __launch_bounds__(RED_WG) void energy_volume_kernel(Grid g, const uin
             if (r >= nrows) break;
             const int y = r % n, z = r / n;
             const uint32_t* wrow = bits + g.row(y, z) + 1;
-            const double* a = ulj + (int64_t)r * n;
-            const double* b = ucfa + (int64_t)r * n;
+            const T* a = ulj + (int64_t)r * n;
+            const T* b = ucfa + (int64_t)r * n;
 #pragma unroll 4
             for (int x = lane; x < n; x += 64) {
-                const double va = a[x], vb = b[x];
+                const double va = (double)a[x], vb = (double)b[x];
                 const bool solvent = (wrow[x >> 5] >> (x & 31)) & 1u;
                 sa += solvent ? va : 0.0;
                 sb += solvent ? vb : 0.0;
@@ -670,8 +669,8 @@ hipError_t launch_init_tight(const Grid& g, const Atoms& a, double scale, double
 
 hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
                             int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
-                            const double* ulj, const double* ucfa, const double* bound,
-                            double* u64cache, int* sweep_flips, int64_t* counters, hipStream_t st) {
+                            const CellFields& f, double* u64cache, int* sweep_flips,
+                            int64_t* counters, hipStream_t st) {
     const int p = sc.p;
     const int cb = (colour / p) % p, cc = colour / (p * p);
     const int64_t ny = (g.n - cb + p - 1) / p, nz = (g.n - cc + p - 1) / p;
@@ -682,9 +681,7 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     d.sc = sc;
     d.a = a;
     d.ph = ph;
-    d.f.ulj = const_cast<double*>(ulj);
-    d.f.ucfa = const_cast<double*>(ucfa);
-    d.f.bound = const_cast<double*>(bound);
+    d.f = f;
     d.bits = bits;
     d.stamp = stamp;
     d.u64cache = u64cache;
@@ -760,11 +757,16 @@ hipError_t launch_batch_gather_flips(const MolDesc* descs, int m, int nsweeps, i
     return hipGetLastError();
 }
 
-hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const double* ulj,
-                                const double* ucfa, double* partial, int nblocks, double* out,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(energy_volume_kernel, dim3(nblocks), dim3(RED_WG), 0, st, g, bits, ulj,
-                       ucfa, partial);
+hipError_t launch_energy_volume(const Grid& g, const uint32_t* bits, const CellFields& f,
+                                double* partial, int nblocks, double* out, hipStream_t st) {
+    if (f.f32)
+        hipLaunchKernelGGL(energy_volume_kernel<float>, dim3(nblocks), dim3(RED_WG), 0, st, g,
+                           bits, static_cast<const float*>(f.ulj),
+                           static_cast<const float*>(f.ucfa), partial);
+    else
+        hipLaunchKernelGGL(energy_volume_kernel<double>, dim3(nblocks), dim3(RED_WG), 0, st, g,
+                           bits, static_cast<const double*>(f.ulj),
+                           static_cast<const double*>(f.ucfa), partial);
     hipLaunchKernelGGL((reduce_partials<double, 2>), dim3(1), dim3(RED_WG), 0, st, partial,
                        nblocks, out);
     return hipGetLastError();

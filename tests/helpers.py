@@ -37,14 +37,9 @@ def oracle_density(key, w_factory):
 
 
 def energies_close(a: dict, b: dict, rel: float, keys=("geom", "vdw_in", "vdw_far", "elec_in",
-                                                       "elec_far", "total"), volume_scale=False):
-    """Keys whose difference exceeds rel * |G|.  volume_scale: rel * max(|G|,
-    |vdw_in| + |elec_in| of b) instead; for FP32 densities, whose rounding
-    error is relative to the volume sums rather than to their sum G (a small
-    molecule's G can cancel to a few percent of them)."""
+                                                       "elec_far", "total")):
+    """Keys whose difference exceeds rel * |G| (G = a's total)."""
     scale = max(abs(a["total"]), 1e-30)
-    if volume_scale:
-        scale = max(scale, abs(b["vdw_in"]) + abs(b["elec_in"]))
     bad = {k: (a[k], b[k]) for k in keys if abs(a[k] - b[k]) > rel * scale}
     return bad
 
