@@ -228,3 +228,44 @@ def test_batch_graph_replays_match_eager():
         for ce, cg, a, b in zip(eager, graph, se, sg):
             assert np.array_equal(ce.labels(), cg.labels())
             assert a == b
+
+
+def test_full_batch_64_molecules_matches_oracle():
+    """The 64-molecule batch against the oracle's colour schedule, molecule by
+    molecule: labels (differences only at cells whose oracle decision fell
+    inside 1e-9 |G|), sweep, flip and band counts, and every energy part
+    within 1e-6 |G|.  Covers the large uneven shapes (up to 160^3 cells and
+    3,000 atoms) that the small-molecule batch tests do not reach; the
+    oracle's densities take about a minute on the host cores."""
+    import time
+
+    from paper_2208_05524_amd import Batch
+    ws = synth.batch_conformations()
+    ctxs = [gpu_context(w) for w in ws]
+    for c in ctxs:
+        c.init_labels("tight", 1.0)
+    rc, bst = Batch(ctxs).minimize()
+    assert rc == 0
+    got = [(c.labels(), c.energy()) for c in ctxs]
+    for c in ctxs:
+        c.close()
+    t0 = time.time()
+    worst = 0.0
+    for w, st, (lab, e) in zip(ws, bst, got):
+        s = oracle_system(w)
+        ulj, ucfa = s.density_grid()
+        far = s.far_field()
+        phi = s.init_tight()
+        e0 = s.energy(phi, ulj, ucfa, far)["total"]
+        _, ost, ties, _ = s.minimize_colour(phi, ulj + ucfa, tie_tol=1e-9 * abs(e0))
+        assert ost["ties"] == len(ties)
+        ref = s.energy(phi, ulj, ucfa, far)
+        rel = max(abs(e[k] - ref[k]) for k in ("geom", "vdw_in", "vdw_far", "elec_in",
+                                               "elec_far", "total")) / abs(ref["total"])
+        worst = max(worst, rel)
+        log(f"{w.name} n={w.n} atoms={w.natoms} sweeps {st['sweeps']}/{ost['sweeps']} "
+            f"max |dE|/|G| {rel:.2e} ties {len(ties)} ({time.time() - t0:.0f}s)")
+        check_labels(lab, phi, ties, st, ost, what=w.name)
+        bad = energies_close(e, ref, 1e-6)
+        assert not bad, (w.name, bad)
+    log("64 molecules: largest energy difference / |G|", worst)
