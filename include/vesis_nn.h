@@ -28,6 +28,7 @@ extern "C" {
 
 #define VESIS_NN_E_ARG (-1)
 #define VESIS_NN_E_DEVICE (-6)
+#define VESIS_NN_E_SCRATCH (-7)
 
 /* y = [relu](conv3x3x3(x, w) + bias), zero padding, stride 1: an implicit
  * GEMM on the BF16 matrix cores with FP32 accumulation.  x: (n,d,h,w,cin)
@@ -99,6 +100,20 @@ int vesis_nn_head_fwd(void* stream, const void* x, const float* w, const float* 
                       int64_t p, int c);
 int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const float* w, void* dx,
                       float* dw, float* db, float* ws, size_t ws_bytes, int64_t p, int c);
+
+/* vesis_nn_head_bwd without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the channel partials go to a static
+ * device array of the library (1 MiB per GPU, kept until the process ends),
+ * so nothing is allocated.  Same kernels and summation order as
+ * vesis_nn_head_bwd, hence the same results bit for bit.  Limit:
+ * c * ceil(p / 1024) <= 262144 (e.g. c = 32 and p up to 8,388,608
+ * positions), else VESIS_NN_E_SCRATCH and nothing is launched.  `stream`
+ * must belong to the current device.  Calls that overlap on one GPU share
+ * the array and race; every call overwrites the partials it reads, so no
+ * state carries from one call to the next. */
+int vesis_nn_head_bwd_noalloc(void* stream, const float* dlogit, const void* x, const float* w,
+                              void* dx, float* dw, float* db, int64_t p, int c);
 
 /* Mean binary cross-entropy of logits against labels (int8 per cell, -1 =
  * solute = target 1, +1 = solvent = target 0), solute cells weighted by

@@ -765,9 +765,19 @@ inline unsigned nblk(int64_t n, int wg) { return (unsigned)((n + wg - 1) / wg); 
 
 // ------------------------------------------------------------------ C ABI
 
+#include <mutex>
+
 #include "vesis_nn.h"
 
 using namespace vesis::nn;
+
+// Scratch of the allocation-free head gradient (vesis_nn_head_bwd_noalloc):
+// the per-chunk channel partial sums, one float per (chunk of 1024
+// positions, channel), at most HEAD_SCRATCH_FLOATS of them (1 MiB).  Each GPU
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the device address looked up per device below.
+constexpr int64_t HEAD_SCRATCH_FLOATS = 262144;
+static __device__ __align__(256) float scratch[HEAD_SCRATCH_FLOATS];
 
 namespace {
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -775,6 +785,40 @@ inline int status(hipError_t e) { return e == hipSuccess ? 0 : VESIS_NN_E_DEVICE
 inline const __bf16* B(const void* p) { return static_cast<const __bf16*>(p); }
 inline __bf16* Bm(void* p) { return static_cast<__bf16*>(p); }
 bool dims_ok(int N, int D, int H, int W) { return N > 0 && D > 0 && H > 0 && W > 0; }
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_ptr[SCRATCH_DEVICES] = {};
+
+int head_scratch(float** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES)
+        return VESIS_NN_E_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return VESIS_NN_E_DEVICE;
+        scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return 0;
+}
+
+// The head's adjoint with its channel partials in ws (at least
+// channel_sums_bytes(p, c) bytes): dx, then dw, then db (which reuses ws
+// after the dw sums have read it: same stream).
+int head_bwd(hipStream_t st, const float* dlogit, const void* x, const float* w, void* dx,
+             float* dw, float* db, float* ws, int64_t p, int c) {
+    hipLaunchKernelGGL(head_bwd_x_kernel, dim3(nblk(p * c, 256)), dim3(256), 0, st, dlogit, w,
+                       Bm(dx), p, c);
+    if (channel_sums(B(x), dlogit, p, c, ws, dw, st) != hipSuccess ||
+        channel_sums(nullptr, dlogit, p, 1, ws, db, st) != hipSuccess)
+        return VESIS_NN_E_DEVICE;
+    return status(hipGetLastError());
+}
 
 // LDS-staged tiles of 4 x-rows (y) x MT z-layers x 32 positions, one tile of
 // 32 output channels per workgroup.  Layers with at least as many such
@@ -947,11 +991,18 @@ int vesis_nn_head_bwd(void* stream, const float* dlogit, const void* x, const fl
                       float* dw, float* db, float* ws, size_t ws_bytes, int64_t p, int c) {
     if (!dlogit || !x || !w || !dx || !dw || !db || !ws || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
     if (ws_bytes < channel_sums_bytes(p, c)) return VESIS_NN_E_ARG;
-    hipLaunchKernelGGL(head_bwd_x_kernel, dim3(nblk(p * c, 256)), dim3(256), 0, S(stream), dlogit, w, Bm(dx), p, c);
-    if (channel_sums(B(x), dlogit, p, c, ws, dw, S(stream)) != hipSuccess ||
-        channel_sums(nullptr, dlogit, p, 1, ws, db, S(stream)) != hipSuccess)
-        return VESIS_NN_E_DEVICE;
-    return status(hipGetLastError());
+    return head_bwd(S(stream), dlogit, x, w, dx, dw, db, ws, p, c);
+}
+
+int vesis_nn_head_bwd_noalloc(void* stream, const float* dlogit, const void* x, const float* w,
+                              void* dx, float* dw, float* db, int64_t p, int c) {
+    if (!dlogit || !x || !w || !dx || !dw || !db || p <= 0 || c <= 0) return VESIS_NN_E_ARG;
+    if (channel_sums_bytes(p, c) > sizeof(float) * (size_t)HEAD_SCRATCH_FLOATS)
+        return VESIS_NN_E_SCRATCH;
+    float* ws = nullptr;
+    const int rc = head_scratch(&ws);
+    if (rc != 0) return rc;
+    return head_bwd(S(stream), dlogit, x, w, dx, dw, db, ws, p, c);
 }
 
 int vesis_nn_bce(void* stream, const float* logits, const int8_t* labels, int64_t p,

@@ -12,7 +12,7 @@ from . import _lib
 NN_EXPORTS = ["vesis_nn_conv3_fwd", "vesis_nn_conv3_fwd_upcat", "vesis_nn_wgrad_workspace", "vesis_nn_conv3_wgrad",
               "vesis_nn_prep_weights", "vesis_nn_relu_bwd", "vesis_nn_pool2", "vesis_nn_up2",
               "vesis_nn_concat", "vesis_nn_split", "vesis_nn_add", "vesis_nn_head_fwd",
-              "vesis_nn_head_bwd",
+              "vesis_nn_head_bwd", "vesis_nn_head_bwd_noalloc",
               "vesis_nn_bce", "vesis_nn_adam", "vesis_nn_featurize"]
 
 _NN = None
@@ -40,6 +40,7 @@ def lib():
         L.vesis_nn_add.argtypes = [P, P, P, P, I64]
         L.vesis_nn_head_fwd.argtypes = [P, P, P, P, P, I64, I]
         L.vesis_nn_head_bwd.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, I64, I]
+        L.vesis_nn_head_bwd_noalloc.argtypes = [P, P, P, P, P, P, P, I64, I]
         L.vesis_nn_bce.argtypes = [P, P, P, I64, F, P, P, I, P]
         L.vesis_nn_adam.argtypes = [P, P, P, P, P, I64, F, F, F, F, I]
         L.vesis_nn_featurize.argtypes = [P, P, P, P, I64, I, D, P, I, P]
