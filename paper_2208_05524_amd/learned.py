@@ -78,6 +78,7 @@ class UNet:
         self.p["head"] = dict(w=torch.tensor(np.asarray(hw, np.float32), **f32),
                               bias=torch.tensor(np.asarray(hb, np.float32), **f32))
         self.step_count = 0
+        self.record = None  # a dict: backward() keeps every intermediate gradient there
         self.partial = torch.zeros(1024, dtype=torch.float64, device=self.dev)
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
         if not train:
@@ -254,11 +255,15 @@ class UNet:
                                             N.ptr(q["gb"]), N.ptr(self.ws), self.ws_bytes, self.b,
                                             s, s, s, q["cin"], q["cout"]), "wgrad " + name)
         if not need_dx:
+            if self.record is not None:
+                self.record[name] = (dy, None)
             return None
         dx = self._act(s, q["cin"])
         N.check(self.L.vesis_nn_conv3_fwd(self._s(), N.ptr(g), N.ptr(q["wb"]), None, N.ptr(dx),
                                           self.b, s, s, s, q["cout"], q["cin"], 0),
                 "dgrad " + name)
+        if self.record is not None:
+            self.record[name] = (dy, dx)
         return dx
 
     def _split(self, dcat, ca):
@@ -274,11 +279,15 @@ class UNet:
         dx = self._act(s // 2, c)
         N.check(self.L.vesis_nn_up2(self._s(), N.ptr(dy), N.ptr(dx), self.b, s, s, s, c, 1),
                 "up_bwd")
+        if self.record is not None:
+            self.record["up", s] = (dy, dx)
         return dx
 
     def _pool_bwd_add(self, dp, dskip):
         """dskip + the adjoint of pooling applied to dp (in place on dskip)."""
         s, c = dskip.shape[1], dskip.shape[4]
+        if self.record is not None:
+            self.record["pool", s] = (dp, dskip.clone(), dskip)
         t = self._act(s, c)
         N.check(self.L.vesis_nn_pool2(self._s(), N.ptr(dp), N.ptr(t), self.b, s, s, s, c, 1),
                 "pool_bwd")
@@ -296,6 +305,8 @@ class UNet:
                                          N.ptr(db7), N.ptr(h["gw"]), N.ptr(h["gb"]),
                                          N.ptr(self.ws), self.ws_bytes, P, LEVELS[0]),
                 "head_bwd")
+        if self.record is not None:
+            self.record["head"] = (dlogit, db7)
         c1, c2, c3, _ = LEVELS
         da7 = self._conv_bwd("d1b", a["a7"], a["b7"], db7)
         dc1 = self._conv_bwd("d1a", a["c1"], a["a7"], da7)

@@ -312,3 +312,285 @@ def test_training_lowers_the_loss_and_the_warm_start_is_relaxed_exactly():
     check_labels(ctx.labels(), phi, ties, st, ost, what="warm start")
     e = ctx.energy()["total"]
     assert abs(e - s.energy(phi, ulj, ucfa, far)["total"]) <= 1e-6 * abs(e)
+
+
+def _stored_close(got, ref, what, max_frac=2e-3):
+    """A BF16 tensor the GPU stored against the reference layer's stored
+    value from the same inputs: equal except where the FP32 and FP64 sums
+    fall on different sides of a BF16 rounding boundary (a small fraction),
+    and there by at most one BF16 step."""
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    d = got != ref
+    frac = float(d.mean())
+    # one BF16 step of the value, or (a ReLU whose input sits at zero within
+    # the sums' rounding) a difference negligible against the tensor
+    floor = 1e-6 * np.abs(ref).max()
+    step = np.abs(got[d] - ref[d]) / np.maximum(np.abs(ref[d]), floor / 2.0 ** -7 + 1e-300)
+    log(f"{what}: {d.sum()} of {d.size} differ, largest {step.max() if d.any() else 0.0:.2e}")
+    assert frac <= max_frac, (what, frac)
+    assert not d.any() or step.max() <= 2.0 ** -7, (what, step.max())
+
+
+def test_network_layers_match_the_bf16_storage_reference():
+    """Every layer of the whole U-Net (16^3, random input and labels), forward
+    and backward, against the reference layer of oracle/unet.py's BF16-storage
+    mode fed with the GPU's own inputs to that layer: stored BF16 tensors
+    equal up to rare one-step rounding differences, logits within 1e-6,
+    weight and bias gradients within 1e-5 (relative L2).  End to end the
+    two networks drift apart by about 1 % (each rare one-step difference
+    shifts later sums across other rounding boundaries), which the
+    comparison with the FP64 network above bounds."""
+    import torch
+
+    from oracle import unet
+    from paper_2208_05524_amd.learned import UNet, init_weights
+    n = 16
+    w = init_weights(seed=3)
+    r = np.random.default_rng(5)
+    x = _bf(np.abs(r.standard_normal((1, n, n, n, 32))))
+    lab = np.where(r.random(n ** 3) < 0.25, -1, 1).astype(np.int8)
+    m = UNet(n, weights=w)
+    m.record = {}
+    xd = _dev_bf16(x)
+    labd = torch.tensor(lab, device="cuda")
+    logits = m.forward(xd)
+    loss, dlogit = m.loss(logits, labd, 2.0)
+    m.backward(dlogit)
+    g = m.grads()
+
+    def T(t):  # device channels-last -> float64 (b, c, z, y, x)
+        return torch.as_tensor(t.double().cpu().numpy()).permute(0, 4, 1, 2, 3).contiguous()
+
+    A = {k: T(v) for k, v in m.acts.items()}
+    W = {name: (unet.bf16(unet.to_torch_weight(w[name][0])),
+                torch.as_tensor(np.asarray(w[name][1], np.float64))) for name, _, _ in unet.SPECS}
+    hw = torch.as_tensor(np.asarray(w["head"][0], np.float64))
+    hb = torch.as_tensor(np.asarray(w["head"][1], np.float64))
+    fwd = [("a1", "e1a", "x"), ("s1", "e1b", "a1"), ("a2", "e2a", "p1"), ("s2", "e2b", "a2"),
+           ("a3", "e3a", "p2"), ("s3", "e3b", "a3"), ("a4", "e4a", "p3"), ("b4", "e4b", "a4"),
+           ("a5", "d3a", "c3"), ("b5", "d3b", "a5"), ("a6", "d2a", "c2"), ("b6", "d2b", "a6"),
+           ("a7", "d1a", "c1"), ("b7", "d1b", "a7")]
+    for out, name, inp in fwd:
+        _stored_close(A[out], unet.conv_layer(A[inp], *W[name]), f"forward {name}")
+    for out, inp in (("p1", "s1"), ("p2", "s2"), ("p3", "s3")):
+        _stored_close(A[out], unet.pool_layer(A[inp]), f"pool {out}")
+    for cat, up, skip in (("c3", "b4", "s3"), ("c2", "b5", "s2"), ("c1", "b6", "s1")):
+        assert torch.equal(A[cat], torch.cat([unet.upsample(A[up]), A[skip]], dim=1)), cat
+    lg = logits.double().cpu().numpy()
+    assert _rel(lg, unet.head_layer(A["b7"], hw, hb).reshape(-1).numpy()) < 1e-6
+    t = (lab < 0).astype(np.float64)
+    wt = np.where(t > 0, 2.0, 1.0)
+    lg64 = lg.astype(np.float64)
+    want_loss = np.mean(wt * (np.log1p(np.exp(-np.abs(lg64))) + np.maximum(lg64, 0) - lg64 * t))
+    assert abs(float(loss) - want_loss) <= 1e-6 * want_loss
+
+    rec = m.record
+    dl, db7 = rec["head"]
+    dlt = torch.as_tensor(dl.double().cpu().numpy()).reshape(1, n, n, n)
+    ref_db7, hgw, hgb = unet.head_adjoint(dlt, A["b7"], hw)
+    _stored_close(T(db7), ref_db7, "head adjoint")
+    assert _rel(g["head"][0], hgw.numpy()) < 1e-5 and _rel(g["head"][1], hgb.numpy()) < 1e-5
+    bwd = [("d1b", "a7", "b7"), ("d1a", "c1", "a7"), ("d2b", "a6", "b6"), ("d2a", "c2", "a6"),
+           ("d3b", "a5", "b5"), ("d3a", "c3", "a5"), ("e4b", "a4", "b4"), ("e4a", "p3", "a4"),
+           ("e3b", "a3", "s3"), ("e3a", "p2", "a3"), ("e2b", "a2", "s2"), ("e2a", "p1", "a2"),
+           ("e1b", "a1", "s1"), ("e1a", "x", "a1")]
+    for name, xin, y in bwd:
+        dy, dx = rec[name]
+        rdx, gw, gb = unet.conv_adjoint(A[xin], A[y], T(dy), W[name][0], need_dx=dx is not None)
+        if dx is not None:
+            _stored_close(T(dx), rdx, f"data gradient {name}")
+        ew = _rel(g[name][0], unet.from_torch_weight(gw))
+        eb = _rel(g[name][1], gb.numpy()) if gb.abs().max() > 0 else 0.0
+        log(f"weight gradient {name}: {ew:.2e}, bias {eb:.2e}")
+        assert ew < 1e-5 and eb < 1e-5, name
+    for key, v in rec.items():
+        if isinstance(key, tuple) and key[0] == "up":
+            _stored_close(T(v[1]), unet.upsample_adjoint(T(v[0])), f"upsample adjoint {key[1]}")
+        elif isinstance(key, tuple) and key[0] == "pool":
+            dp, before, after = v
+            _stored_close(T(after), unet.pool_adjoint_add(T(dp), T(before)),
+                          f"pool adjoint {key[1]}")
+    assert sum(isinstance(k, tuple) for k in rec) == 6
+
+
+def _bf16_grid(shape, seed, lo=-1.0, hi=1.0):
+    """Values on a 2^-8 grid in [lo, hi] (exact in BF16, and their sums of
+    eight exact in FP32)."""
+    v = np.round(np.random.default_rng(seed).uniform(lo, hi, shape) * 256.0) / 256.0
+    return v.astype(np.float32)
+
+
+def test_pool_and_upsample_adjoints_are_their_definitions():
+    """Backward of 2x2x2 average pooling: each cell gets 1/8 of its parent's
+    gradient; backward of nearest upsampling: each half-size cell gets the
+    sum of its 8 children's gradients (both rounded to BF16; exact here)."""
+    import torch
+
+    from paper_2208_05524_amd import nn
+    L = nn.lib()
+    b, d, h, w, c = 2, 6, 4, 10, 24
+    dy_small = _bf16_grid((b, d // 2, h // 2, w // 2, c), 11)
+    dx = torch.empty((b, d, h, w, c), dtype=torch.bfloat16, device="cuda")
+    dys = _dev_bf16(dy_small)
+    nn.check(L.vesis_nn_pool2(_stream(), nn.ptr(dys), nn.ptr(dx), b, d, h, w, c, 1), "pool bwd")
+    zi, yi, xi = np.meshgrid(np.arange(d) // 2, np.arange(h) // 2, np.arange(w) // 2,
+                             indexing="ij")
+    want = 0.125 * dy_small[:, zi, yi, xi, :]
+    assert np.array_equal(dx.float().cpu().numpy(), want.astype(np.float32))
+    dy_full = _bf16_grid((b, d, h, w, c), 12)
+    ds = torch.empty((b, d // 2, h // 2, w // 2, c), dtype=torch.bfloat16, device="cuda")
+    dyf = _dev_bf16(dy_full)
+    nn.check(L.vesis_nn_up2(_stream(), nn.ptr(dyf), nn.ptr(ds), b, d, h, w, c, 1), "up bwd")
+    want = dy_full.reshape(b, d // 2, 2, h // 2, 2, w // 2, 2, c).astype(np.float64).sum(
+        axis=(2, 4, 6))
+    assert np.array_equal(ds.float().cpu().numpy().astype(np.float64), _bf(want))
+
+
+def test_relu_adjoint_and_head_are_their_definitions():
+    """ReLU adjoint: dy where y > 0; head: logit = b + sum_c w_c x_c, its
+    input gradient dlogit w_c (rounded to BF16), dw = sum_p dlogit x,
+    db = sum_p dlogit."""
+    import ctypes
+
+    import torch
+
+    from paper_2208_05524_amd import nn
+    L = nn.lib()
+    p, c = 3001, 32
+    r = np.random.default_rng(13)
+    y = _bf(r.standard_normal(p * c))
+    dy = _bf(r.standard_normal(p * c))
+    g = torch.empty(p * c, dtype=torch.bfloat16, device="cuda")
+    yd, dyd = _dev_bf16(y), _dev_bf16(dy)
+    nn.check(L.vesis_nn_relu_bwd(_stream(), nn.ptr(yd), nn.ptr(dyd), nn.ptr(g), p * c),
+             "relu bwd")
+    assert np.array_equal(g.double().cpu().numpy(), np.where(y > 0, dy, 0.0))
+    x = _bf(np.abs(r.standard_normal((p, c))))
+    hw = r.uniform(-1, 1, c).astype(np.float32)
+    hb = np.array([0.3], np.float32)
+    xd = _dev_bf16(x)
+    wt, bt = torch.tensor(hw, device="cuda"), torch.tensor(hb, device="cuda")
+    logits = torch.empty(p, dtype=torch.float32, device="cuda")
+    nn.check(L.vesis_nn_head_fwd(_stream(), nn.ptr(xd), nn.ptr(wt), nn.ptr(bt), nn.ptr(logits),
+                                 p, c), "head fwd")
+    want = hb[0] + x @ hw.astype(np.float64)
+    np.testing.assert_allclose(logits.cpu().numpy(), want, rtol=1e-5, atol=1e-6 * np.abs(want).max())
+    dl = r.uniform(-1e-3, 1e-3, p).astype(np.float32)
+    dlt = torch.tensor(dl, device="cuda")
+    dx = torch.empty((p, c), dtype=torch.bfloat16, device="cuda")
+    dw = torch.empty(c, dtype=torch.float32, device="cuda")
+    db = torch.empty(1, dtype=torch.float32, device="cuda")
+    wsb = 4 * c * ((p + 1023) // 1024)
+    ws = torch.empty(wsb // 4, dtype=torch.float32, device="cuda")
+    nn.check(L.vesis_nn_head_bwd(_stream(), nn.ptr(dlt), nn.ptr(xd), nn.ptr(wt), nn.ptr(dx),
+                                 nn.ptr(dw), nn.ptr(db), nn.ptr(ws), ctypes.c_size_t(wsb), p, c),
+             "head bwd")
+    prod = (dl.astype(np.float64)[:, None] * hw.astype(np.float64)[None, :]).astype(np.float32)
+    assert np.array_equal(dx.double().cpu().numpy(), _bf(prod))
+    np.testing.assert_allclose(dw.cpu().numpy(), dl.astype(np.float64) @ x, rtol=1e-5,
+                               atol=1e-6 * np.abs(dl).sum() * np.abs(x).max())
+    assert abs(float(db.item()) - dl.astype(np.float64).sum()) <= 1e-5 * np.abs(dl).sum()
+
+
+def test_bce_is_its_definition():
+    """Mean weighted binary cross-entropy with logits (target 1 where the
+    label is -1, weight pos_weight there) and its gradient w (sigmoid(l) - t) / P."""
+    import torch
+
+    from paper_2208_05524_amd import nn
+    L = nn.lib()
+    p = 50001
+    r = np.random.default_rng(14)
+    lg = r.uniform(-12, 12, p).astype(np.float32)
+    lab = np.where(r.random(p) < 0.3, -1, 1).astype(np.int8)
+    pw = 2.5
+    dl = torch.empty(p, dtype=torch.float32, device="cuda")
+    part = torch.empty(333, dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    lgd, labd = torch.tensor(lg, device="cuda"), torch.tensor(lab, device="cuda")
+    nn.check(L.vesis_nn_bce(_stream(), nn.ptr(lgd), nn.ptr(labd), p, pw, nn.ptr(dl),
+                            nn.ptr(part), 333, nn.ptr(loss)), "bce")
+    l64 = lg.astype(np.float64)
+    t = (lab < 0).astype(np.float64)
+    wt = np.where(t > 0, pw, 1.0)
+    want = np.mean(wt * (np.log1p(np.exp(-np.abs(l64))) + np.maximum(l64, 0) - l64 * t))
+    assert abs(float(loss.item()) - want) <= 1e-6 * want
+    gwant = wt * (1.0 / (1.0 + np.exp(-l64)) - t) / p
+    np.testing.assert_allclose(dl.cpu().numpy(), gwant, rtol=1e-5, atol=1e-6 * np.abs(gwant).max())
+
+
+def test_adam_is_the_published_update():
+    """Three Adam steps (Kingma & Ba: m <- b1 m + (1 - b1) g, v <- b2 v +
+    (1 - b2) g^2, w <- w - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps))
+    against that update in FP64."""
+    import torch
+
+    from paper_2208_05524_amd import nn
+    L = nn.lib()
+    n = 10007
+    r = np.random.default_rng(15)
+    w = r.standard_normal(n).astype(np.float32)
+    # the kernel takes FP32 hyper-parameters: the reference uses those values
+    lr, b1, b2, eps = (float(np.float32(v)) for v in (1e-3, 0.9, 0.999, 1e-8))
+    wd = torch.tensor(w, device="cuda")
+    md = torch.zeros(n, dtype=torch.float32, device="cuda")
+    vd = torch.zeros(n, dtype=torch.float32, device="cuda")
+    w64, m64, v64 = w.astype(np.float64), np.zeros(n), np.zeros(n)
+    mabs = np.zeros(n)   # the same recursion on |g|: the scale of m's rounding
+    for step in range(1, 4):
+        g = (r.standard_normal(n) * 10.0 ** r.uniform(-4, 0, n)).astype(np.float32)
+        gd = torch.tensor(g, device="cuda")
+        nn.check(L.vesis_nn_adam(_stream(), nn.ptr(wd), nn.ptr(gd), nn.ptr(md), nn.ptr(vd), n,
+                                 lr, b1, b2, eps, step), "adam")
+        g64 = g.astype(np.float64)
+        m64 = b1 * m64 + (1 - b1) * g64
+        mabs = b1 * mabs + (1 - b1) * np.abs(g64)
+        v64 = b2 * v64 + (1 - b2) * g64 * g64
+        w64 = w64 - lr * (m64 / (1 - b1 ** step)) / (np.sqrt(v64 / (1 - b2 ** step)) + eps)
+    # FP32 recursions: a few ulps of the magnitudes they add (m's terms can
+    # cancel, v's cannot)
+    assert np.all(np.abs(md.cpu().numpy() - m64) <= 1e-6 * mabs)
+    np.testing.assert_allclose(vd.cpu().numpy(), v64, rtol=1e-5, atol=0)
+    step_sizes = np.abs(w64 - w.astype(np.float64))
+    err = np.abs(wd.cpu().numpy().astype(np.float64) - w64)
+    # FP32 arithmetic: the weight carries its own rounding (ulp of |w|) plus a
+    # small relative error on the step
+    assert np.all(err <= 1e-4 * step_sizes + 2.0 * np.spacing(np.abs(w).astype(np.float32)))
+
+
+def test_trained_network_start_needs_fewer_sweeps():
+    """What the network gains: trained on the relaxed labels of 160
+    molecules (300 to 1,500 atoms, 64^3 cells of 0.1 nm), its labels start
+    the relaxation of 16 held-out molecules closer to equilibrium than the
+    tight start: fewer colour sweeps in total, and every relaxation from it
+    still ends at a local minimum (zero-flip sweep)."""
+    import torch
+
+    from helpers import gpu_context
+    from paper_2208_05524_amd.learned import (Sample, UNet, molecule_arrays, predict_logits,
+                                              relaxed_labels, train)
+    dev = torch.device("cuda")
+    train_set = synth.warm_start_set(160, n=64, h=0.1, seed0=5000)
+    test_set = synth.warm_start_set(16, n=64, h=0.1, seed0=9000)
+    labels, _ = relaxed_labels(train_set)
+    samples = [Sample(w, lab, dev) for w, lab in zip(train_set, labels)]
+    m = UNet(64, seed=2)
+    losses = train(m, samples, steps=4 * len(samples), lr=2e-3)
+    log("training loss first/last", np.mean(losses[:20]), np.mean(losses[-20:]))
+    tight, learned = [], []
+    for w in test_set:
+        c = gpu_context(w)
+        c.init_labels("tight", 1.0)
+        rc, st = c.minimize()
+        assert rc == 0
+        tight.append(st["sweeps"])
+        pos4, sig, q = molecule_arrays(w, dev)
+        c.init_labels_logits(predict_logits(m, pos4, sig, q, w.h, w.center))
+        rc, st = c.minimize()
+        assert rc == 0 and st["converged"] == 1
+        learned.append(st["sweeps"])
+        c.close()
+    log("sweeps to equilibrium, tight start", tight, "learned start", learned)
+    log(f"mean {np.mean(tight):.2f} -> {np.mean(learned):.2f}")
+    assert sum(learned) < sum(tight)

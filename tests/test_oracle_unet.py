@@ -75,3 +75,45 @@ def test_oracle_gradients_match_central_differences():
         fd = (unet.forward(wp, x, lab, 2.0)["loss"] - unet.forward(wm, x, lab, 2.0)["loss"]) / (2 * eps)
         an = g[name][0][idx]
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-4), (name, idx, fd, an)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    """The BF16-storage mode's rounding: 8 significant bits, halfway cases to
+    the even neighbour, other values to the nearest, signs symmetric."""
+    import torch
+    v = torch.tensor([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, 1 + 2 ** -9,
+                      -(1 + 3 * 2 ** -8), 3.0 * 2 ** -100, 255.5, 257.0], dtype=torch.float64)
+    want = [1.0, 1 + 2 ** -6, 1 + 2 ** -7, 1.0, -(1 + 2 ** -6), 3.0 * 2 ** -100, 256.0, 256.0]
+    assert unet.bf16(v).tolist() == want
+
+
+def test_written_out_backward_equals_autograd_without_rounding():
+    """The BF16-storage mode's layer-by-layer backward pass, with rounding
+    off, equals autograd's gradients of the plain float64 network (and the
+    same logits and loss): the chain rule is written out correctly."""
+    r = _rng(4)
+    w = synth.conv_weights(unet.SPECS, 32, seed=9)
+    x = r.standard_normal((1, 8, 8, 8, 32))
+    lab = np.where(r.random(8 ** 3) < 0.3, -1, 1).astype(np.int8)
+    ref = unet.forward(w, x, lab, pos_weight=2.0, grads=True)
+    got = unet.forward_backward_bf16(w, x, lab, pos_weight=2.0, rounding=False)
+    np.testing.assert_allclose(got["logits"], ref["logits"], rtol=1e-12, atol=1e-12)
+    assert abs(got["loss"] - ref["loss"]) <= 1e-12 * abs(ref["loss"])
+    for k, (gw, gb) in ref["grads"].items():
+        sw = np.abs(gw).max()
+        np.testing.assert_allclose(got["grads"][k][0], gw, rtol=1e-9, atol=1e-11 * sw, err_msg=k)
+        np.testing.assert_allclose(got["grads"][k][1], gb, rtol=1e-9,
+                                   atol=1e-11 * max(np.abs(gb).max(), 1e-300), err_msg=k)
+
+
+def test_bf16_storage_mode_rounds_what_it_stores():
+    """With rounding on, the stored tensors are BF16 values and the result
+    differs from the unrounded network by BF16-sized amounts only."""
+    r = _rng(6)
+    w = synth.conv_weights(unet.SPECS, 32, seed=10)
+    x = unet.bf16(__import__("torch").as_tensor(np.abs(r.standard_normal((1, 8, 8, 8, 32))))).numpy()
+    lab = np.where(r.random(8 ** 3) < 0.3, -1, 1).astype(np.int8)
+    exact = unet.forward_backward_bf16(w, x, lab, 2.0, rounding=False)
+    rnd = unet.forward_backward_bf16(w, x, lab, 2.0, rounding=True)
+    rel = np.linalg.norm(rnd["logits"] - exact["logits"]) / np.linalg.norm(exact["logits"])
+    assert 1e-5 < rel < 5e-2
