@@ -220,9 +220,60 @@ def cpu_chain_equilibrium():
             "start": "tight"}
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
-    """Oracle density (FP64, OpenMP) over whole z-planes of the same grid
-    until about budget_s seconds of work; returns atom-gridpoint pairs/s."""
+def cpu_single_atom():
+    """The oracle's full run on the single LJ atom (64^3 cells, FP64, loose
+    sphere of 1.2 nm): density, far field, colour sweeps to equilibrium."""
+    import oracle
+    import synth
+    w = synth.single_atom()
+    s = oracle.System.from_workload(w)
+    t0 = time.perf_counter()
+    ulj, ucfa = s.density_grid()
+    far = s.far_field()
+    phi = s.init_loose(1.2)
+    rc, st, _, _ = s.minimize_colour(phi, ulj + ucfa)
+    e = s.energy(phi, ulj, ucfa, far)
+    return {"time_to_equilibrium_s": time.perf_counter() - t0, "sweeps": st["sweeps"],
+            "G": e["total"], "start": "loose sphere, R0 = 1.2 nm"}
+
+
+def cpu_full_two_globules(w):
+    """The oracle's full interface relaxation at the benchmark's size: FP64
+    density over every cell, far field, tight start, colour sweeps to
+    equilibrium (about a minute on 16 host threads; --cpu-full only)."""
+    import oracle
+    s = oracle.System.from_workload(w)
+    t0 = time.perf_counter()
+    ulj, ucfa = s.density_grid()
+    t1 = time.perf_counter()
+    s.far_field()
+    phi = s.init_tight()
+    rc, st, _, _ = s.minimize_colour(phi, ulj + ucfa)
+    t2 = time.perf_counter()
+    return {"density_s": t1 - t0, "far_field_and_sweeps_s": t2 - t1,
+            "time_to_equilibrium_s": t2 - t0, "sweeps": st["sweeps"], "flips": st["flips"]}
+
+
+def host_cpu():
+    """CPU model name of the host (from /proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def cpu_baseline(w, budget_s: float = 12.0, full: bool = False, relax=None):
+    """The FP64 oracle on the host cores, as written (not tuned).  value: its
+    density (OpenMP over cells) over whole z-planes of the same grid until
+    about budget_s seconds of work, in atom-gridpoint pairs/s; beside it the
+    same on one thread (one z-plane), the whole-grid density time both
+    imply (extrapolated), full runs of the single-atom and 1,000-atom
+    workloads, optionally (full) the full relaxation at this size, and the
+    200-iteration alternation extrapolated from the density evaluations the
+    GPU run of it made."""
     import numpy as np
 
     import oracle
@@ -240,15 +291,9 @@ def cpu_baseline(w, budget_s: float = 12.0):
         planes += 1
     dt = time.perf_counter() - t0
     pairs = planes * n * n * w.natoms
+    rate = pairs / dt
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    model = "unknown CPU"
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    model = host_cpu()
     # one thread, one z-plane
     z = w.center[2] - L + (n // 2 + 0.5) * w.h
     pts = np.stack([X.ravel(), Y.ravel(), np.full(n * n, z)], axis=1)
@@ -257,15 +302,33 @@ def cpu_baseline(w, budget_s: float = 12.0):
     s.density_points(pts)
     dt1 = time.perf_counter() - t1
     oracle.set_threads(cores)
-    single = {"value": n * n * w.natoms / dt1, "unit": "atom·gridpt/s", "cores": 1,
+    rate1 = n * n * w.natoms / dt1
+    grid_pairs = float(n) ** 3 * w.natoms
+    single = {"value": rate1, "unit": "atom·gridpt/s", "cores": 1,
               "sample": f"one z-plane ({n * n} cells) x {w.natoms} atoms, {dt1:.1f} s"}
-    chain = cpu_chain_equilibrium()
-    return {"value": pairs / dt, "unit": "atom·gridpt/s", "cores": cores, "kind": "oracle",
-            "single_thread": single, "chain_1000_128": chain,
-            "sample": f"FP64 oracle density over {planes} z-planes ({planes * n * n} cells) of "
-                      f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s on {cores} threads of "
-                      f"{model}; the GPU value is a whole hot-path step, whose density work "
-                      f"alone is >= 2 such evaluations"}
+    out = {"value": rate, "unit": "atom·gridpt/s", "cores": cores, "kind": "oracle",
+           "host": {"cpu": model, "threads": cores},
+           "single_thread": single,
+           "density_whole_grid_s_extrapolated": {
+               "all_threads": grid_pairs / rate, "one_thread": grid_pairs / rate1,
+               "note": "extrapolated from the measured samples (pairs / rate)"},
+           "single_atom_64": cpu_single_atom(),
+           "chain_1000_128": cpu_chain_equilibrium(),
+           "sample": f"FP64 oracle density over {planes} z-planes ({planes * n * n} cells) of "
+                     f"the {n}^3 grid x {w.natoms} atoms, {dt:.1f} s on {cores} threads of "
+                     f"{model}; the GPU value is a whole hot-path step, whose density work "
+                     f"alone is >= 2 such evaluations"}
+    if relax is not None:
+        evals = relax["iters"] + relax["retries"]
+        out["relax_extrapolated_s"] = {
+            "all_threads": evals * grid_pairs / rate,
+            "note": f"extrapolated: {evals} whole-grid density evaluations (one per outer "
+                    f"iteration and per rejected trial of the GPU run of "
+                    f"{relax['iters']} iterations) at the measured oracle rate; forces and "
+                    f"sweeps not counted"}
+    if full:
+        out["two_globules_full"] = cpu_full_two_globules(w)
+    return out
 
 
 def main():
@@ -275,6 +338,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle's full relaxation at the benchmark's size "
+                         "(about a minute on 16 host threads)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-molecule batched-vs-one-at-a-time comparison")
     ap.add_argument("--learned-train", type=int, default=2000,
@@ -433,7 +499,8 @@ def main():
         log(f"relax: {out['relax']}")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, full=args.cpu_full,
+                                           relax=out.get("relax"))
     print(json.dumps(out), flush=True)
 
 
