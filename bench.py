@@ -64,6 +64,32 @@ def measured_traffic(kernel: str = "density_grid_f32"):
     return None
 
 
+def measured_flip_traffic():
+    """HBM traffic of the batched colour pass on the 64-molecule workload
+    from the committed PMC summary: bytes per dispatch, average dispatch
+    time and their ratio against 8 TB/s, or None when the colour-pass source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_batch64_flip.md")
+    src = os.path.join(ROOT, "paper_2208_05524_amd", "csrc", "labels.hip")
+    try:
+        lines = open(path).read().splitlines()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for ln in lines:
+        f = ln.split()
+        if len(f) > 2 and f[0] == "traffic" and f[1] == "flip_pass_batch":
+            kv = dict(x.split("=", 1) for x in f[2:])
+            if kv.get("source_sha256") != sha:
+                return None
+            b, us = float(kv["bytes_per_dispatch"]), float(kv["avg_us"])
+            gbs = b / (us * 1e-6) / 1e9
+            return {"bytes_per_dispatch": b, "avg_us": us, "GB_per_s": gbs,
+                    "frac_of_8TBs": gbs / 8000.0}
+    return None
+
+
 def batch_comparison(rounds: int = 2):
     """Time to equilibrium of 64 molecules (atom counts log-uniform in [200,
     3000], grids 64^3 to 160^3 at 0.05 nm): each molecule on its own (tight
@@ -91,6 +117,8 @@ def batch_comparison(rounds: int = 2):
             c.set_positions(w.xyz)  # marks the density stale
         torch.cuda.synchronize()
 
+    for c in ctxs:
+        c.init_labels("tight", 1.0)  # the tuner times colour passes from these labels
     best, tune_ms = b.tune()
     plain_ms, batch_ms, eager_ms = [], [], []
     for r in range(rounds + 1):
@@ -136,7 +164,11 @@ def batch_comparison(rounds: int = 2):
            "batched_without_graph_ms": min(eager_ms),
            "speedup": min(plain_ms) / min(batch_ms),
            "batched_atom_gridpt_per_s": pairs / (min(batch_ms) / 1e3),
-           "density_variant": best, "tune_ms": tune_ms,
+           "variant": {"code": best, "density_tiling": best % Batch.DENSITY_VARIANTS,
+                       "colour_pass": best // Batch.DENSITY_VARIANTS},
+           "tune_ms": {"density_tilings": tune_ms[:Batch.DENSITY_VARIANTS],
+                       "one_sweep_per_colour_pass_variant": tune_ms[Batch.DENSITY_VARIANTS:]},
+           "flip_pass_hbm": measured_flip_traffic(),
            "sweeps_max": max(x["sweeps"] for x in st), "converged": rc == 0,
            "labels_identical": bool(same), "max_rel_dG": rel}
     for c in ctxs:

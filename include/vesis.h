@@ -291,18 +291,29 @@ vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* opts, vesis_mob
  * must not be used concurrently with a batch call. */
 vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_t* bytes);
 
-/* Time each density tiling variant (0: two cells per lane on 16x8x4
- * bricks; 1: one cell per lane on 16x8x2 bricks) on the batch, return the
- * fastest in *best and the times in ms[variant] (ms may be NULL).  Needs no
- * labels; leaves the densities marked stale. */
+/* Autotune the batch's launch shapes.  Times each density tiling d (0: two
+ * cells per lane on 16x8x4 bricks; 1: one cell per lane on 16x8x2 bricks;
+ * 2: four cells per lane on 16x8x8 bricks) on the batch, and, when every
+ * molecule has labels, one sweep of colour passes with each register
+ * variant f (0: the compiler's allocation; 1: capped for four wavefronts
+ * per SIMD) from the current labels, which are put back afterwards.
+ * *best = d + 3 f of the fastest of each (f = 0 when not timed), the value
+ * vesis_minimize_batch takes as `variant`; ms (may be NULL, 5 entries)
+ * receives the density times (ms[d]) and the sweep times (ms[3 + f], -1
+ * when not timed).  Every variant computes the same labels; the density
+ * tilings round differently in FP32.  Leaves the densities marked stale. */
 vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* batch_ws, size_t bytes,
                               int32_t* best, double* ms);
 
 /* Relax the interfaces of m molecules (Step 2 for each), recomputing the
- * density of those whose atoms changed with density variant `variant`.
+ * density of those whose atoms changed; variant = d + 3 f selects the
+ * density tiling d and the colour-pass variant f (see vesis_batch_tune).
  * Sweeps run in groups of 8; a full group is captured once as a HIP graph
- * (on a private stream) and replayed on the context stream, unless flags
- * holds VESIS_BATCH_EAGER.
+ * (on a private stream; kept by the first context for later calls with the
+ * same batch workspace, molecule count, pass grid, colour period and f) and
+ * replayed on the context stream, unless flags holds VESIS_BATCH_EAGER.
+ * While many molecules are still relaxing, the next group is queued before
+ * the host reads the current one's flip counts. 
  * out (m entries, may be NULL) receives each molecule's statistics.
  * Returns VESIS_OK when every molecule converged within max_sweeps,
  * VESIS_NOT_CONVERGED otherwise (the others keep their state and a new call

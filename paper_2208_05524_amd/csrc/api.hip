@@ -140,6 +140,15 @@ struct vesis_ctx {
     bool forces_valid = false;
 
     hipStream_t capture = nullptr;  // private stream for graph capture (made on first use)
+    // the captured group of batched sweeps, kept across calls while the
+    // batch workspace, molecule count, pass grid, colour period and flip
+    // variant stay the same
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    const void* bkey_ws = nullptr;
+    int bkey_m = 0, bkey_p = 0, bkey_fv = 0;
+    int64_t bkey_nblocks = 0;
+    hipEvent_t bev[2] = {nullptr, nullptr};  // completion of the two groups in flight
     // pinned host staging of the batch calls' tables (descriptors, block
     // maps, read-backs), so that their copies need not be waited for
     char* hstage = nullptr;
@@ -712,6 +721,10 @@ vesis_status vesis_create(int32_t device, void* stream, vesis_ctx** out) {
 void vesis_destroy(vesis_ctx* ctx) {
     if (!ctx) return;
     if (!ctx->pending.empty()) drain_events(ctx);
+    if (ctx->bexec) (void)hipGraphExecDestroy(ctx->bexec);
+    if (ctx->bgraph) (void)hipGraphDestroy(ctx->bgraph);
+    for (hipEvent_t e : ctx->bev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->hstage) (void)hipHostFree(ctx->hstage);
     delete ctx;
@@ -1368,11 +1381,12 @@ BatchLayout batch_layout(int m, int64_t dens_blocks, int64_t flip_blocks, int64_
 
 // Host staging of a batch call (in the first context's pinned buffer):
 // density descriptors and brick map, colour-pass descriptors and block map,
-// and three int64 read-backs per molecule.  The regions are disjoint, so a
+// three int64 read-backs per molecule, and two slots of per-sweep flip
+// counts (one per group of sweeps in flight).  The regions are disjoint, so a
 // call never overwrites a table whose copy may still be pending; every call
 // ends synchronised, so the next one may reuse them.
 struct StageLayout {
-    size_t ddesc, dmap, fdesc, fmap, far, farmap, stats, total;
+    size_t ddesc, dmap, fdesc, fmap, far, farmap, stats, flips2, total;
 };
 
 StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks, int64_t far_blocks) {
@@ -1390,6 +1404,7 @@ StageLayout stage_layout(int m, int64_t dens_blocks, int64_t flip_blocks, int64_
     S.far = take(sizeof(FarDesc) * (size_t)m);
     S.farmap = take(4 * (size_t)far_blocks);
     S.stats = take(8 * 3 * (size_t)m);
+    S.flips2 = take(2 * 4 * (size_t)m * SWEEP_BATCH);
     S.total = o;
     return S;
 }
@@ -1589,6 +1604,30 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
     return VESIS_OK;
 }
 
+// The colour-pass tables of a batch call: descriptors and the block map,
+// staged and copied to the batch workspace; returns the pass grid.
+int64_t batch_pass_tables(vesis_ctx* ctx, vesis_ctx* const* ctxs, int m, char* b,
+                          const BatchLayout& L, const StageLayout& S, int64_t& max_words,
+                          MolDesc*& desc) {
+    const int p = ctx->sc.p;
+    desc = reinterpret_cast<MolDesc*>(ctx->hstage + S.fdesc);
+    int* map = reinterpret_cast<int*>(ctx->hstage + S.fmap);
+    int64_t nmap = 0;
+    max_words = 0;
+    for (int i = 0; i < m; ++i) {
+        desc[i] = mol_desc(ctxs[i]);
+        desc[i].slot0 = nmap * FLIP_WG;
+        const int64_t nb = flip_slots(ctxs[i]->g, p) / FLIP_WG;
+        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = i;
+        nmap += nb;
+        max_words = std::max(max_words, ctxs[i]->g.nwords());
+    }
+    ctx->hstage_busy = true;
+    (void)hipMemcpyAsync(b + L.desc, desc, sizeof(MolDesc) * m, hipMemcpyHostToDevice, ctx->stream);
+    (void)hipMemcpyAsync(b + L.fmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, ctx->stream);
+    return nmap;
+}
+
 vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
                               int32_t* best, double* ms) {
     BatchLayout L;
@@ -1598,34 +1637,92 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
     if (!best) return fail(ctxs[0], VESIS_E_ARG, "null argument");
     vesis_ctx* ctx = ctxs[0];
     hipStream_t st = ctx->stream;
+    char* b = static_cast<char*>(bws);
     std::vector<int> all(m);
     for (int i = 0; i < m; ++i) all[i] = i;
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
+    auto elapsed = [&](float& t) -> hipError_t {
+        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        return e;
+    };
+    // density tilings
+    int dbest = 0;
     double tbest = 0.0;
-    for (int v = 0; v < DENSITY_VARIANTS; ++v) {
+    for (int v = 0; v < DENSITY_VARIANTS && s == VESIS_OK; ++v) {
         double tv = 1e300;
         for (int rep = 0; rep < 2; ++rep) {  // the first run also warms the caches
             CK(hipEventRecord(e0, st));
-            s = batch_density(ctx, ctxs, all, static_cast<char*>(bws), L, S, v);
+            s = batch_density(ctx, ctxs, all, b, L, S, v);
             if (s != VESIS_OK) break;
             CK(hipEventRecord(e1, st));
-            CK(hipEventSynchronize(e1));
-            ctx->hstage_busy = false;
             float t = 0.f;
-            CK(hipEventElapsedTime(&t, e0, e1));
+            CK(elapsed(t));
+            ctx->hstage_busy = false;
             tv = std::min(tv, (double)t);
         }
         if (s != VESIS_OK) break;
         if (ms) ms[v] = tv;
         if (v == 0 || tv < tbest) {
             tbest = tv;
-            *best = v;
+            dbest = v;
         }
+    }
+    // colour-pass register variants: one sweep of every colour over the
+    // batch from its current labels, which are saved first and put back
+    // after each run (in each molecule's force staging scratch, which no
+    // result depends on between calls).  Needs labels on every molecule.
+    bool labelled = s == VESIS_OK;
+    for (int i = 0; i < m && labelled; ++i) labelled = ctxs[i]->has_labels;
+    int fbest = 0;
+    for (int v = 0; v < FLIP_VARIANTS && ms; ++v) ms[DENSITY_VARIANTS + v] = -1.0;
+    if (labelled) {
+        const int p = ctx->sc.p, ncol = p * p * p;
+        int64_t max_words = 0;
+        MolDesc* desc = nullptr;
+        const int64_t nblocks = batch_pass_tables(ctx, ctxs, m, b, L, S, max_words, desc);
+        const MolDesc* ddesc = reinterpret_cast<const MolDesc*>(b + L.desc);
+        const int* dmap = reinterpret_cast<const int*>(b + L.fmap);
+        int* ddone = reinterpret_cast<int*>(b + L.done);
+        int* dpass = reinterpret_cast<int*>(b + L.pass);
+        for (int i = 0; i < m; ++i)
+            CK(hipMemcpyAsync(ctxs[i]->ws + ctxs[i]->lay.fstage, desc[i].bits,
+                              4 * (size_t)ctxs[i]->g.nwords(), hipMemcpyDeviceToDevice, st));
+        double fb = 0.0;
+        for (int v = 0; v < FLIP_VARIANTS; ++v) {
+            double tv = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                CK(launch_batch_prepare(ddesc, m, max_words, st));
+                CK(launch_fill_u32(reinterpret_cast<uint32_t*>(ddone), m, 0u, st));
+                CK(launch_fill_u32(reinterpret_cast<uint32_t*>(dpass), 1, 0u, st));
+                CK(launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, st));
+                CK(hipEventRecord(e0, st));
+                for (int c = 0; c < ncol; ++c)
+                    CK(launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, 0, c, v,
+                                              st));
+                CK(hipEventRecord(e1, st));
+                float t = 0.f;
+                CK(elapsed(t));
+                tv = std::min(tv, (double)t);
+                for (int i = 0; i < m; ++i)
+                    CK(hipMemcpyAsync(desc[i].bits, ctxs[i]->ws + ctxs[i]->lay.fstage,
+                                      4 * (size_t)ctxs[i]->g.nwords(), hipMemcpyDeviceToDevice,
+                                      st));
+            }
+            if (ms) ms[DENSITY_VARIANTS + v] = tv;
+            if (v == 0 || tv < fb) {
+                fb = tv;
+                fbest = v;
+            }
+        }
+        CK(hipStreamSynchronize(st));
+        ctx->hstage_busy = false;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    *best = dbest + DENSITY_VARIANTS * fbest;
     // the densities now come from the last variant tried: recompute on use
     for (int i = 0; i < m; ++i) {
         ctxs[i]->dens_valid = false;
@@ -1633,6 +1730,13 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
         ctxs[i]->forces_valid = false;
     }
     return s;
+}
+
+void release_batch_graph(vesis_ctx* c) {
+    if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
+    if (c->bgraph) (void)hipGraphDestroy(c->bgraph);
+    c->bexec = nullptr;
+    c->bgraph = nullptr;
 }
 
 vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
@@ -1644,44 +1748,33 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     if (s != VESIS_OK) return s;
     vesis_ctx* ctx = ctxs[0];
     if (max_sweeps < 1) return fail(ctx, VESIS_E_ARG, "max_sweeps must be >= 1");
-    if (variant < 0 || variant >= DENSITY_VARIANTS)
-        return fail(ctx, VESIS_E_ARG, "density variant out of range");
+    if (variant < 0 || variant >= DENSITY_VARIANTS * FLIP_VARIANTS)
+        return fail(ctx, VESIS_E_ARG, "batch variant out of range");
+    const int dvar = variant % DENSITY_VARIANTS, fvar = variant / DENSITY_VARIANTS;
     hipStream_t st = ctx->stream;
     char* b = static_cast<char*>(bws);
     // a1 + a2: one density launch over every molecule whose atoms changed
     std::vector<int> stale;
     for (int i = 0; i < m; ++i)
         if (!ctxs[i]->dens_valid) stale.push_back(i);
-    s = batch_density(ctx, ctxs, stale, b, L, S, variant);
+    s = batch_density(ctx, ctxs, stale, b, L, S, dvar);
     if (s != VESIS_OK) return s;
     s = batch_far(ctx, ctxs, stale, b, L, S);
     if (s != VESIS_OK) return s;
     // a3 + a4: one launch per colour pass over every unconverged molecule
     const int p = ctx->sc.p, ncol = p * p * p;
-    MolDesc* desc = reinterpret_cast<MolDesc*>(ctx->hstage + S.fdesc);
-    int* map = reinterpret_cast<int*>(ctx->hstage + S.fmap);
-    int64_t nmap = 0, max_words = 0;
-    for (int i = 0; i < m; ++i) {
-        desc[i] = mol_desc(ctxs[i]);
-        desc[i].slot0 = nmap * FLIP_WG;
-        const int64_t nb = flip_slots(ctxs[i]->g, p) / FLIP_WG;
-        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = i;
-        nmap += nb;
-        max_words = std::max(max_words, ctxs[i]->g.nwords());
-    }
+    int64_t max_words = 0;
+    MolDesc* desc = nullptr;
+    const int64_t nblocks = batch_pass_tables(ctx, ctxs, m, b, L, S, max_words, desc);
     std::vector<char> done(m, 0);
     std::vector<int> msweeps(m, 0);
     std::vector<int64_t> mflips(m, 0);
-    std::vector<int> hf((size_t)m * SWEEP_BATCH);
     const MolDesc* ddesc = reinterpret_cast<const MolDesc*>(b + L.desc);
     const int* dmap = reinterpret_cast<const int*>(b + L.fmap);
     int* ddone = reinterpret_cast<int*>(b + L.done);
     int* dpass = reinterpret_cast<int*>(b + L.pass);
     int* dflips = reinterpret_cast<int*>(b + L.flips);
-    const int64_t nblocks = nmap;
-    ctx->hstage_busy = true;
-    CK(hipMemcpyAsync(b + L.desc, desc, sizeof(MolDesc) * m, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(b + L.fmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, st));
+    int* hflips = reinterpret_cast<int*>(ctx->hstage + S.flips2);
     // every molecule's stamps older than any pass and its tie counters zero
     CK(launch_batch_prepare(ddesc, m, max_words, st));
     CK(launch_fill_u32(reinterpret_cast<uint32_t*>(ddone), m, 0u, st));
@@ -1693,28 +1786,22 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
         for (int sw = 0; sw < nb && e == hipSuccess; ++sw)
             for (int c = 0; c < ncol && e == hipSuccess; ++c)
                 e = launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, sw,
-                                           sw * ncol + c, s2);
+                                           sw * ncol + c, fvar, s2);
         if (e == hipSuccess) e = launch_batch_end_group(ddesc, m, nb, ncol, ddone, dpass, s2);
         if (e == hipSuccess) e = launch_batch_gather_flips(ddesc, m, SWEEP_BATCH, dflips, s2);
         return e;
     };
     const bool use_graph = !(flags & VESIS_BATCH_EAGER);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    auto release = [&]() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-    };
-    int sweeps = 0, active = m;
-    while (sweeps < max_sweeps && active > 0) {
-        const int nb = std::min(SWEEP_BATCH, max_sweeps - sweeps);
+    if (ctx->bexec && !(ctx->bkey_ws == bws && ctx->bkey_m == m && ctx->bkey_nblocks == nblocks &&
+                        ctx->bkey_p == p && ctx->bkey_fv == fvar))
+        release_batch_graph(ctx);
+    // a full group is the same sequence of launches every time: captured once
+    // on a private stream, replayed on the caller's stream (no memset nodes:
+    // counters are cleared by kernels)
+    auto launch_group = [&](int nb) -> hipError_t {
         hipError_t e = hipSuccess;
         if (use_graph && nb == SWEEP_BATCH) {
-            if (!exec) {
-                // the same group of launches every time: capture it once on a
-                // private stream, replay it on the caller's stream
+            if (!ctx->bexec) {
                 if (!ctx->capture) {
                     e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
                     if (e != hipSuccess) ctx->capture = nullptr;
@@ -1722,29 +1809,65 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
                 if (e == hipSuccess) e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed);
                 if (e == hipSuccess) {
                     const hipError_t e1 = enqueue_group(ctx->capture, nb);
-                    const hipError_t e2 = hipStreamEndCapture(ctx->capture, &graph);
+                    const hipError_t e2 = hipStreamEndCapture(ctx->capture, &ctx->bgraph);
                     e = e1 != hipSuccess ? e1 : e2;
                 }
-                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (e == hipSuccess) e = hipGraphInstantiate(&ctx->bexec, ctx->bgraph, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    release_batch_graph(ctx);
+                    return e;
+                }
+                ctx->bkey_ws = bws;
+                ctx->bkey_m = m;
+                ctx->bkey_nblocks = nblocks;
+                ctx->bkey_p = p;
+                ctx->bkey_fv = fvar;
             }
-            if (e == hipSuccess) {
-                Timed t(ctx, K_FLIP);
-                e = hipGraphLaunch(exec, st);
-            }
-        } else {
             Timed t(ctx, K_FLIP);
-            e = enqueue_group(st, nb);
+            return hipGraphLaunch(ctx->bexec, st);
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), dflips, 4 * hf.size(), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e == hipSuccess) ctx->hstage_busy = false;
-        if (e != hipSuccess) {
-            release();
-            return fail(ctx, VESIS_E_DEVICE, std::string("batched sweeps: ") + hipGetErrorString(e));
+        Timed t(ctx, K_FLIP);
+        return enqueue_group(st, nb);
+    };
+    for (int k = 0; k < 2; ++k)
+        if (!ctx->bev[k]) CK(hipEventCreateWithFlags(&ctx->bev[k], hipEventDisableTiming));
+    // Groups are issued ahead of the host: while more than an eighth of the
+    // molecules are still relaxing, the next group is queued before the
+    // host waits for the current one's flip counts, so the device does not
+    // idle through the round trip; near the end, when a queued group would
+    // mostly find every molecule done, the host waits first.  At most two
+    // groups are in flight (two host slots for their counts).
+    struct Inflight { int slot, nb; };
+    Inflight q[2];
+    int nq = 0, next_slot = 0, enq = 0, sweeps = 0, active = m;
+    auto issue = [&]() -> hipError_t {
+        const int nb = std::min(SWEEP_BATCH, max_sweeps - enq);
+        hipError_t e = launch_group(nb);
+        const int slot = next_slot;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hflips + (size_t)slot * m * SWEEP_BATCH, dflips,
+                               4 * (size_t)m * SWEEP_BATCH, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(ctx->bev[slot], st);
+        if (e == hipSuccess) {
+            q[nq++] = Inflight{slot, nb};
+            next_slot ^= 1;
+            enq += nb;
         }
+        return e;
+    };
+    hipError_t e = issue();
+    while (e == hipSuccess && nq > 0) {
+        if (nq == 1 && enq < max_sweeps && active > std::max(1, m / 8)) e = issue();
+        if (e != hipSuccess) break;
+        const Inflight g = q[0];
+        q[0] = q[1];
+        --nq;
+        e = hipEventSynchronize(ctx->bev[g.slot]);
+        if (e != hipSuccess) break;
+        const int* hf = hflips + (size_t)g.slot * m * SWEEP_BATCH;
         for (int i = 0; i < m; ++i) {
             if (done[i]) continue;
-            for (int sw = 0; sw < nb; ++sw) {
+            for (int sw = 0; sw < g.nb; ++sw) {
                 const int f = hf[(size_t)i * SWEEP_BATCH + sw];
                 mflips[i] += f;
                 ++msweeps[i];
@@ -1755,9 +1878,16 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
                 }
             }
         }
-        sweeps += nb;
+        sweeps += g.nb;
+        if (active == 0) break;  // a group still queued finds every molecule done
+        if (nq == 0 && enq < max_sweeps) e = issue();
     }
-    release();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    ctx->hstage_busy = false;
+    if (e != hipSuccess) {
+        release_batch_graph(ctx);
+        return fail(ctx, VESIS_E_DEVICE, std::string("batched sweeps: ") + hipGetErrorString(e));
+    }
     for (int i = 0; i < m; ++i)
         if (mflips[i] > 0) ctxs[i]->forces_valid = false;
     if (out) {
@@ -1785,6 +1915,7 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
         }
     }
     ctx->err.clear();
+    (void)sweeps;
     return active == 0 ? VESIS_OK : VESIS_NOT_CONVERGED;
 }
 

@@ -322,9 +322,10 @@ __global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     density_brick_f32<KC, BZ>(g, a, ph, out, blockIdx.x);
 }
 
-// Batched: block b works on brick b - brick0 of molecule block_mol[b].
+// Batched: block b works on brick b - brick0 of molecule block_mol[b].  Four
+// cells per lane hold twice the accumulators: two wavefronts per SIMD.
 template <int KCV, int BZV>
-__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void density_batch_f32(
+__global__ __launch_bounds__(DWG) __attribute__((amdgpu_waves_per_eu(KCV >= 4 ? 2 : 4, 8))) void density_batch_f32(
     const MolDesc* desc, const int* block_mol) {
     const MolDesc& d = desc[block_mol[blockIdx.x]];
     density_brick_f32<KCV, BZV>(d.g, d.a, d.ph, d.f, (int64_t)blockIdx.x - d.brick0);
@@ -642,7 +643,7 @@ hipError_t launch_density_grid(const Grid& g, const Atoms& a, const Physics& ph,
 }
 
 int64_t density_bricks(const Grid& g, int variant) {
-    const int bz = variant == 1 ? 2 : BZ;
+    const int bz = variant == 1 ? 2 : (variant == 2 ? 8 : BZ);
     const int64_t nbx = (g.n + BX - 1) / BX, nby = (g.n + BY - 1) / BY, nbz = (g.n + bz - 1) / bz;
     return nbx * nby * nbz;
 }
@@ -652,6 +653,9 @@ hipError_t launch_density_batch(const MolDesc* desc, const int* block_mol, int64
     if (nblocks <= 0) return hipSuccess;
     if (variant == 1)
         hipLaunchKernelGGL((density_batch_f32<1, 2>), dim3((unsigned)nblocks), dim3(DWG), 0, st,
+                           desc, block_mol);
+    else if (variant == 2)
+        hipLaunchKernelGGL((density_batch_f32<4, 8>), dim3((unsigned)nblocks), dim3(DWG), 0, st,
                            desc, block_mol);
     else
         hipLaunchKernelGGL((density_batch_f32<KC, BZ>), dim3((unsigned)nblocks), dim3(DWG), 0, st,

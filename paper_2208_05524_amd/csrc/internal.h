@@ -146,9 +146,10 @@ hipError_t launch_far_batch(const FarDesc* d, const int* block_mol, int m, int64
                             int64_t max_np, int64_t max_ncell, int nred, hipStream_t st);
 
 // Batched density (FP32): variant 0 = 2 cells per lane on 16 x 8 x 4 bricks,
-// 1 = 1 cell per lane on 16 x 8 x 2 bricks.  block_mol maps each block to its
-// molecule; a molecule's blocks are consecutive, from desc[m].brick0.
-constexpr int DENSITY_VARIANTS = 2;
+// 1 = 1 cell per lane on 16 x 8 x 2 bricks, 2 = 4 cells per lane on 16 x 8 x 8
+// bricks.  block_mol maps each block to its molecule; a molecule's blocks are
+// consecutive, from desc[m].brick0.
+constexpr int DENSITY_VARIANTS = 3;
 int64_t density_bricks(const Grid& g, int variant);
 hipError_t launch_density_batch(const MolDesc* desc, const int* block_mol, int64_t nblocks,
                                 int variant, hipStream_t st);
@@ -175,9 +176,12 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
 constexpr int FLIP_WG = 256;
 int64_t flip_slots(const Grid& g, int p);
 // done[k] != 0 skips molecule k; the pass index is *pass_base + gpass_off.
+// variant: 0 = registers at the compiler's choice, 1 = capped for four
+// wavefronts per SIMD (the same arithmetic, so the same labels).
+constexpr int FLIP_VARIANTS = 2;
 hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
                                   const int* pass_base, int64_t nblocks, int p, int colour,
-                                  int sweep, int gpass_off, hipStream_t st);
+                                  int sweep, int gpass_off, int variant, hipStream_t st);
 // End of a group of nsweeps sweeps: flag molecules that had a sweep without
 // flips, advance *pass_base by nsweeps * ncol.
 hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,

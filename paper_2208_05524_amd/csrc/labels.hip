@@ -267,8 +267,11 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
 // In a batch, molecules flagged in `done` are skipped and the pass index is
 // *pass_base + gpass, so that one captured sequence of passes can be
 // replayed.
-template <bool BATCH, int P>
-__global__ __launch_bounds__(FWG) void flip_pass_kernel(MolDesc one, const MolDesc* descs,
+// W: the fewest wavefronts per SIMD the register allocation must allow (1:
+// the compiler's choice; 4 caps the kernel at 128 VGPRs).
+template <bool BATCH, int P, int W>
+__global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) void flip_pass_kernel(
+    MolDesc one, const MolDesc* descs,
                                                         const int* block_mol, const int* done,
                                                         const int* pass_base, int colour,
                                                         int sweep, int gpass, int ncol) {
@@ -688,10 +691,10 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     d.sweep_flips = sweep_flips;
     d.counters = counters;
     if (p == 2)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 2>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
+        hipLaunchKernelGGL((flip_pass_kernel<false, 2, 1>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
                            d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 8);
     else if (p == 3)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 3>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
+        hipLaunchKernelGGL((flip_pass_kernel<false, 3, 1>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
                            d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 27);
     else
         return hipErrorInvalidValue;
@@ -716,15 +719,22 @@ int64_t flip_slots(const Grid& g, int p) {
 
 hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
                                   const int* pass_base, int64_t nblocks, int p, int colour,
-                                  int sweep, int gpass_off, hipStream_t st) {
+                                  int sweep, int gpass_off, int variant, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     MolDesc unused{};
-    if (p == 2)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 2>), dim3((unsigned)nblocks), dim3(FWG), 0, st,
-                           unused, descs, block_mol, done, pass_base, colour, sweep, gpass_off, 8);
-    else if (p == 3)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 3>), dim3((unsigned)nblocks), dim3(FWG), 0, st,
-                           unused, descs, block_mol, done, pass_base, colour, sweep, gpass_off, 27);
+    const dim3 grid((unsigned)nblocks);
+    if (p == 2 && variant == 0)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 2, 1>), grid, dim3(FWG), 0, st, unused, descs,
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 8);
+    else if (p == 2 && variant == 1)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 2, 4>), grid, dim3(FWG), 0, st, unused, descs,
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 8);
+    else if (p == 3 && variant == 0)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 3, 1>), grid, dim3(FWG), 0, st, unused, descs,
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 27);
+    else if (p == 3 && variant == 1)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 3, 4>), grid, dim3(FWG), 0, st, unused, descs,
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 27);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -263,15 +263,22 @@ class Batch:
             raise VesisError(rc, msg.decode() if msg else "")
         return rc
 
+    DENSITY_VARIANTS = 3
+    FLIP_VARIANTS = 2
+
     def tune(self):
-        """Time the density variants on this batch and keep the fastest."""
+        """Time the density tilings and (when every molecule has labels) the
+        colour-pass variants on this batch and keep the fastest of each:
+        returns (variant, ms), ms = the density tilings' times then one
+        sweep's time per colour-pass variant (-1: not timed)."""
         best = C.c_int32()
-        ms = (C.c_double * 2)()
+        nv = self.DENSITY_VARIANTS + self.FLIP_VARIANTS
+        ms = (C.c_double * nv)()
         self._check(self.lib.vesis_batch_tune(self._arr, len(self.contexts),
                                               C.c_void_p(self._ptr), self.nbytes,
                                               C.byref(best), ms))
         self.variant = int(best.value)
-        return self.variant, [ms[0], ms[1]]
+        return self.variant, [ms[k] for k in range(nv)]
 
     def minimize(self, max_sweeps: int = 20000, variant=None, graph: bool = True):
         m = len(self.contexts)

@@ -148,9 +148,12 @@ def test_batch_tune_and_errors():
     for c in ctxs:
         c.init_labels("tight", 1.0)
     b = Batch(ctxs)
+    before = [c.labels() for c in ctxs]
     best, ms = b.tune()
     log("tune", best, ms)
-    assert best in (0, 1) and all(t > 0 for t in ms)
+    assert 0 <= best < Batch.DENSITY_VARIANTS * Batch.FLIP_VARIANTS and all(t > 0 for t in ms)
+    # the colour-pass timing ran from the labels and put them back
+    assert all(np.array_equal(a, c.labels()) for a, c in zip(before, ctxs))
     rc, _ = b.minimize()
     assert rc == 0
     # FP64 members are refused
@@ -269,3 +272,35 @@ def test_full_batch_64_molecules_matches_oracle():
         bad = energies_close(e, ref, 1e-6)
         assert not bad, (w.name, bad)
     log("64 molecules: largest energy difference / |G|", worst)
+
+
+def test_every_batch_variant_reaches_the_single_molecule_result():
+    """Each density tiling and colour-pass register variant the tuner picks
+    among ends in the single-molecule path's labels, sweep, flip and band
+    counts (decisions are exact whatever the FP32 rounding), with energies
+    within 1e-6 |G|; twice in a row per variant, the second call replaying
+    the graph kept from the first."""
+    from paper_2208_05524_amd import Batch
+    ws = _molecules()
+    single = []
+    for w in ws:
+        c = gpu_context(w)
+        c.init_labels("tight", 1.0)
+        _, st = c.minimize()
+        single.append((c.labels(), st, c.energy()))
+    ctxs = [gpu_context(w) for w in ws]
+    b = Batch(ctxs)
+    for v in range(Batch.DENSITY_VARIANTS * Batch.FLIP_VARIANTS):
+        for rep in range(2):
+            for c, w in zip(ctxs, ws):
+                c.set_positions(w.xyz)
+                c.init_labels("tight", 1.0)
+            rc, st = b.minimize(variant=v)
+            assert rc == 0
+            for c, (lab, sst, es), bst in zip(ctxs, single, st):
+                assert np.array_equal(c.labels(), lab), (v, rep)
+                assert (sst["sweeps"], sst["flips"], sst["band"]) == \
+                    (bst["sweeps"], bst["flips"], bst["band"]), (v, rep)
+                e = c.energy()
+                assert abs(e["total"] - es["total"]) <= 1e-6 * abs(es["total"]), (v, rep)
+        log("variant", v, "ok")
