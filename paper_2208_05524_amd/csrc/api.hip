@@ -1353,7 +1353,8 @@ vesis_status vesis_relax(vesis_ctx* ctx, const vesis_relax_opts* o, vesis_mobili
 
 namespace {
 
-constexpr int BATCH_MAX = 4096;
+constexpr int BATCH_MAX = BATCH_MOLS;
+constexpr int NXCD_BATCH = 8;  // dies (XCDs) of the chip, each with its own L2
 
 struct BatchLayout {
     size_t desc, dmap, fmap, flips, done, pass, far, farmap, total;
@@ -1441,7 +1442,16 @@ void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip, int6
         for (int i = 0; i < m; ++i) s += density_bricks(c[i]->g, v);
         dens = std::max(dens, s);
     }
-    for (int i = 0; i < m; ++i) flip += flip_slots(c[i]->g, c[i]->sc.p) / FLIP_WG;
+    // the colour passes' block map: every molecule's blocks, dealt to the
+    // dies, padded to the longest die's list (at most one molecule longer
+    // than the even share)
+    int64_t most = 0;
+    for (int i = 0; i < m; ++i) {
+        const int64_t nb = flip_slots(c[i]->g, c[i]->sc.p) / FLIP_WG;
+        flip += nb;
+        most = std::max(most, nb);
+    }
+    flip = NXCD_BATCH * ((flip + NXCD_BATCH - 1) / NXCD_BATCH + most);
 }
 
 MolDesc mol_desc(vesis_ctx* c) {
@@ -1612,16 +1622,33 @@ int64_t batch_pass_tables(vesis_ctx* ctx, vesis_ctx* const* ctxs, int m, char* b
     const int p = ctx->sc.p;
     desc = reinterpret_cast<MolDesc*>(ctx->hstage + S.fdesc);
     int* map = reinterpret_cast<int*>(ctx->hstage + S.fmap);
-    int64_t nmap = 0;
     max_words = 0;
+    // Each molecule's blocks go to one die (its labels then stay in that
+    // die's L2 for the pass), largest molecules first, each to the die with
+    // the fewest blocks so far; workgroup NXCD j + x runs entry j of die x.
+    std::vector<int64_t> nbm(m);
+    std::vector<int> order(m);
     for (int i = 0; i < m; ++i) {
         desc[i] = mol_desc(ctxs[i]);
-        desc[i].slot0 = nmap * FLIP_WG;
-        const int64_t nb = flip_slots(ctxs[i]->g, p) / FLIP_WG;
-        for (int64_t j = 0; j < nb; ++j) map[nmap + j] = i;
-        nmap += nb;
+        desc[i].slot0 = 0;
+        nbm[i] = flip_slots(ctxs[i]->g, p) / FLIP_WG;
+        order[i] = i;
         max_words = std::max(max_words, ctxs[i]->g.nwords());
     }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return nbm[a] > nbm[b2]; });
+    std::vector<std::vector<int>> lists(NXCD_BATCH);
+    std::vector<int64_t> load(NXCD_BATCH, 0);
+    for (int i : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int64_t j = 0; j < nbm[i]; ++j) lists[x].push_back(i | (int)(j << BATCH_MOL_BITS));
+        load[x] += nbm[i];
+    }
+    int64_t longest = 0;
+    for (const auto& l : lists) longest = std::max<int64_t>(longest, (int64_t)l.size());
+    const int64_t nmap = NXCD_BATCH * longest;
+    for (int64_t j = 0; j < longest; ++j)
+        for (int x = 0; x < NXCD_BATCH; ++x)
+            map[NXCD_BATCH * j + x] = j < (int64_t)lists[x].size() ? lists[x][j] : -1;
     ctx->hstage_busy = true;
     (void)hipMemcpyAsync(b + L.desc, desc, sizeof(MolDesc) * m, hipMemcpyHostToDevice, ctx->stream);
     (void)hipMemcpyAsync(b + L.fmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, ctx->stream);

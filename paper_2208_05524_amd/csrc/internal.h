@@ -172,8 +172,11 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                             const CellFields& f, double* u64cache, int* sweep_flips,
                             int64_t* counters, hipStream_t st);
 // Batched colour pass: flip_slots(g, p) thread slots per molecule (a multiple
-// of the workgroup size), a molecule's blocks consecutive from slot0.
+// of the workgroup size).  Entry b of the block map is molecule |
+// (logical block << BATCH_MOL_BITS), or -1 for an idle workgroup.
 constexpr int FLIP_WG = 256;
+constexpr int BATCH_MOL_BITS = 12;
+constexpr int BATCH_MOLS = 1 << BATCH_MOL_BITS;  // molecules a batch may hold
 int64_t flip_slots(const Grid& g, int p);
 // done[k] != 0 skips molecule k; the pass index is *pass_base + gpass_off.
 // variant: 0 = registers at the compiler's choice, 1 = capped for four

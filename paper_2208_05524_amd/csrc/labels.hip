@@ -261,20 +261,32 @@ __device__ inline void block_density_f64(const Grid& g, const Atoms& a, const Ph
 // pass q - ncol; if its stamp is older than that, nothing in its cells'
 // neighbourhoods changed since then, every decision would repeat (no flip),
 // and the word is skipped.  The first sweep of a call evaluates every word.
-// One colour pass of colour period P (2 or 3).  BATCH = false: one molecule, described by `one`; BATCH =
-// true: block b works on molecule block_mol[b] of `descs` (a molecule's
-// blocks are consecutive from slot0 / FWG, so a block never spans two).
-// In a batch, molecules flagged in `done` are skipped and the pass index is
-// *pass_base + gpass, so that one captured sequence of passes can be
-// replayed.
+// XCD-aware block order.  The chip hands consecutive workgroups of a launch
+// to its NXCD dies in turn, and each die has its own L2.  A pass's logical
+// blocks run along x, then the colour's rows along y, then z, and each block
+// reads the label rows two either side of its own; so the logical blocks are
+// dealt out in contiguous runs, one run per die (workgroup b takes logical
+// block (b mod NXCD) xcd_blocks + b / NXCD), and each die's L2 serves a slab
+// of rows instead of every die fetching rows from all over the grid.
+// xcd_blocks = 0 keeps the launch order.
+constexpr int NXCD = 8;
+__device__ inline int64_t flip_block_of(unsigned b, int64_t xcd_blocks) {
+    return xcd_blocks > 0 ? (int64_t)(b % NXCD) * xcd_blocks + b / NXCD : (int64_t)b;
+}
+
+// One colour pass of colour period P (2 or 3).  BATCH = false: one molecule,
+// described by `one`, its logical blocks from flip_block_of; BATCH = true:
+// workgroup b takes entry block_mol[b] = molecule | (logical block <<
+// BATCH_MOL_BITS) of `descs` (-1: none), so a block never spans two molecules
+// and the host chooses which die runs which molecule.  In a batch, molecules
+// flagged in `done` are skipped and the pass index is *pass_base + gpass, so
+// that one captured sequence of passes can be replayed.
 // W: the fewest wavefronts per SIMD the register allocation must allow (1:
 // the compiler's choice; 4 caps the kernel at 128 VGPRs).
 template <bool BATCH, int P, int W>
 __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) void flip_pass_kernel(
-    MolDesc one, const MolDesc* descs,
-                                                        const int* block_mol, const int* done,
-                                                        const int* pass_base, int colour,
-                                                        int sweep, int gpass, int ncol) {
+    MolDesc one, const MolDesc* descs, const int* block_mol, const int* done,
+    const int* pass_base, int colour, int sweep, int gpass, int ncol, int64_t xcd_blocks) {
     constexpr int K = (32 + P - 1) / P;  // cells of one colour in a word
     __shared__ double s_red[4 * FWG];
     __shared__ double s_cs[K * FWG];     // c S_j of the near ties, slot-major
@@ -284,11 +296,18 @@ __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     __shared__ uint32_t s_fm[FWG], s_tm[FWG];  // flip and near-tie bits per owner
     __shared__ int s_leader;
     __shared__ int s_tie[4];
+    // the logical block this workgroup takes (see flip_block_of)
+    int mol = 0;
+    int64_t lblock = flip_block_of(blockIdx.x, xcd_blocks);
     if (BATCH) {
-        if (done[block_mol[blockIdx.x]]) return;
+        const int ent = block_mol[blockIdx.x];
+        if (ent < 0) return;  // padding at the end of a shorter XCD's list
+        mol = ent & (BATCH_MOLS - 1);
+        lblock = ent >> BATCH_MOL_BITS;
+        if (done[mol]) return;
         gpass += *pass_base;
     }
-    const MolDesc& D = BATCH ? descs[block_mol[blockIdx.x]] : one;
+    const MolDesc& D = BATCH ? descs[mol] : one;
     const Grid& g = D.g;
     const Stencil& sc = D.sc;
     const Atoms& a = D.a;
@@ -304,7 +323,7 @@ __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     const int ca = colour % P, cb = (colour / P) % P, cc = colour / (P * P);
     const int ny = (g.n - cb + P - 1) / P, nz = (g.n - cc + P - 1) / P;
     const int64_t total = (int64_t)g.nwin * ny * nz;
-    const int64_t tid = (int64_t)blockIdx.x * FWG - (BATCH ? D.slot0 : 0) + threadIdx.x;
+    const int64_t tid = lblock * FWG + threadIdx.x;
     const bool active = tid < total;
     int w = 0, y = 0, z = 0;
     if (active) {
@@ -690,12 +709,14 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     d.u64cache = u64cache;
     d.sweep_flips = sweep_flips;
     d.counters = counters;
+    const int64_t xb = (nblk(total, FWG) + NXCD - 1) / NXCD;  // logical blocks per die
+    const dim3 grid((unsigned)(xb * NXCD));
     if (p == 2)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 2, 1>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
-                           d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 8);
+        hipLaunchKernelGGL((flip_pass_kernel<false, 2, 1>), grid, dim3(FWG), 0, st, d, nullptr,
+                           nullptr, nullptr, nullptr, colour, sweep, gpass, 8, xb);
     else if (p == 3)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 3, 1>), dim3(nblk(total, FWG)), dim3(FWG), 0, st,
-                           d, nullptr, nullptr, nullptr, nullptr, colour, sweep, gpass, 27);
+        hipLaunchKernelGGL((flip_pass_kernel<false, 3, 1>), grid, dim3(FWG), 0, st, d, nullptr,
+                           nullptr, nullptr, nullptr, colour, sweep, gpass, 27, xb);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -725,16 +746,16 @@ hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, co
     const dim3 grid((unsigned)nblocks);
     if (p == 2 && variant == 0)
         hipLaunchKernelGGL((flip_pass_kernel<true, 2, 1>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 8);
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 8, (int64_t)0);
     else if (p == 2 && variant == 1)
         hipLaunchKernelGGL((flip_pass_kernel<true, 2, 4>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 8);
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 8, (int64_t)0);
     else if (p == 3 && variant == 0)
         hipLaunchKernelGGL((flip_pass_kernel<true, 3, 1>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 27);
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 27, (int64_t)0);
     else if (p == 3 && variant == 1)
         hipLaunchKernelGGL((flip_pass_kernel<true, 3, 4>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 27);
+                           block_mol, done, pass_base, colour, sweep, gpass_off, 27, (int64_t)0);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
