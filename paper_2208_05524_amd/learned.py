@@ -566,17 +566,59 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
         **times, "rows": rows}
 
 
+def conv_flops(n: int, batch: int = 1) -> float:
+    """Multiply-add work (2 flops each) of the network's 3x3x3 convolutions at
+    grid n: 27 cin cout per position at each layer's resolution."""
+    total = 0.0
+    for name, cin, cout in layer_specs():
+        s = n >> (int(name[1]) - 1)
+        total += 2.0 * 27 * cin * cout * batch * s ** 3
+    return total
+
+
+def inference_timing(n: int = 128, batch: int = 16, reps: int = 5, seed: int = 0):
+    """Device time of the inference forward pass (keep=False) of an
+    inference-only network (initial weights) on random BF16 input of `batch`
+    grids of n^3 cells; returns ms per batch, ms per molecule and the
+    convolutions' TFLOP/s."""
+    import time
+
+    import torch
+    m = UNet(n, batch=batch, seed=seed, train=False)
+    x = m._act(n, IN_C)
+    g = torch.Generator(device=m.dev).manual_seed(seed)
+    x.copy_(torch.rand(x.shape, generator=g, device=m.dev).to(torch.bfloat16))
+    m.forward(x, keep=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m.forward(x, keep=False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    return {"grid": n, "batch": batch, "ms_per_batch": ms, "ms_per_molecule": ms / batch,
+            "conv_tflops": conv_flops(n, batch) / (ms * 1e-3) / 1e12,
+            "conv_flop_per_molecule": conv_flops(n)}
+
+
 if __name__ == "__main__":
     import argparse
     import json
     import sys
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
+    ap.add_argument("--infer-only", action="store_true",
+                    help="only time the inference forward pass (--grid, --batch, --reps)")
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.infer_only:
+        print(json.dumps(inference_timing(args.grid, args.batch, args.reps)), flush=True)
+        sys.exit(0)
     res = warm_start_experiment(args.train, args.test, args.epochs, args.lr,
                                 log=lambda *a: print(*a, file=sys.stderr, flush=True))
     text = json.dumps(res)
