@@ -219,6 +219,25 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
  * first if the atoms moved.  out may be NULL. */
 vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out);
 
+/* Relax the interface at fixed atoms by the paper's serial flipping process
+ * (Sec. "Flipping grid cells", Steps 2.1-2.3 of the algorithm): the energy
+ * change of every band cell goes into a min-heap keyed by (Delta E, cell
+ * index); while the smallest key is negative that one cell flips and the
+ * cells whose Delta E or band membership the flip changed (those within two
+ * cells along each axis) are re-evaluated and pushed, stale entries being
+ * dropped.  The density (computed on the device, recomputed if the atoms
+ * moved) is read back once; the heap and the flips run on the host, one flip
+ * at a time, and the final labels are written back to the device.  Each
+ * Delta E is decided as the colour passes decide it: from the stored U,
+ * unless it lies within the cell's error bound, then from U recomputed in
+ * FP64 on the device (once per cell).  A different schedule from
+ * vesis_minimize_interface, so it may end in a different local minimum; for
+ * checking and small grids, not for speed.  Stops with every band Delta E
+ * >= 0 (VESIS_OK) or after max_flips flips (VESIS_NOT_CONVERGED).  out (may
+ * be NULL) gets sweeps = 0, flips, converged, band_cells (after), near_ties
+ * and fp64_recomputes. */
+vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_stats* out);
+
 /* Discrete free energy of the current labels and atoms (Eq. "4flip" plus
  * the solute-solute terms that are set). */
 vesis_status vesis_energy(vesis_ctx* ctx, vesis_energy_parts* out);

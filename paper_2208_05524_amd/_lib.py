@@ -23,7 +23,7 @@ EXPORTS = ["vesis_create", "vesis_destroy", "vesis_last_error", "vesis_set_param
            "vesis_set_bonds", "vesis_set_angles", "vesis_set_torsions", "vesis_set_nonbonded",
            "vesis_workspace_size", "vesis_set_workspace", "vesis_init_labels",
            "vesis_init_labels_logits",
-           "vesis_minimize_interface", "vesis_energy", "vesis_forces", "vesis_atom_step",
+           "vesis_minimize_interface", "vesis_minimize_heap", "vesis_energy", "vesis_forces", "vesis_atom_step",
            "vesis_relax", "vesis_batch_workspace_size", "vesis_batch_tune", "vesis_minimize_batch",
            "vesis_get_labels", "vesis_get_density", "vesis_profile", "vesis_profile_read"]
 
@@ -109,6 +109,7 @@ def load():
     L.vesis_set_workspace.argtypes = [P, P, C.c_size_t]
     L.vesis_init_labels.argtypes = [P, I32, D, P]
     L.vesis_minimize_interface.argtypes = [P, I32, C.POINTER(MinStats)]
+    L.vesis_minimize_heap.argtypes = [P, I64, C.POINTER(MinStats)]
     L.vesis_energy.argtypes = [P, C.POINTER(EnergyParts)]
     L.vesis_forces.argtypes = [P, P]
     L.vesis_atom_step.argtypes = [P, C.POINTER(Mobility), C.POINTER(StepInfo)]

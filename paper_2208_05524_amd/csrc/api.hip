@@ -1946,6 +1946,161 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     return active == 0 ? VESIS_OK : VESIS_NOT_CONVERGED;
 }
 
+// ------------------------------------------------ serial (min-heap) schedule
+
+namespace {
+
+struct HeapItem {
+    double key;
+    int64_t idx;
+    int64_t ver;
+};
+// min-heap order on (Delta E, cell index): std::push_heap keeps the largest
+// first, so "less" means "later"
+struct HeapLater {
+    bool operator()(const HeapItem& a, const HeapItem& b) const {
+        return a.key != b.key ? a.key > b.key : a.idx > b.idx;
+    }
+};
+
+}  // namespace
+
+vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_stats* out) {
+    if (!ctx) return VESIS_E_ARG;
+    if (max_flips < 0) return fail(ctx, VESIS_E_ARG, "max_flips must be >= 0");
+    vesis_status s = need(ctx, true);
+    if (s != VESIS_OK) return s;
+    s = ensure_density(ctx);
+    if (s != VESIS_OK) return s;
+    hipStream_t st = ctx->stream;
+    const Grid& g = ctx->g;
+    const int n = g.n;
+    const int64_t ncell = g.ncell();
+    // the labels and the stored densities and bounds, on the host
+    std::vector<int8_t> phi(ncell);
+    s = vesis_get_labels(ctx, phi.data());
+    if (s != VESIS_OK) return s;
+    std::vector<double> U(ncell), B(ncell);
+    {
+        std::vector<double> lj(ncell), cfa(ncell);
+        s = vesis_get_density(ctx, lj.data(), cfa.data(), B.data());
+        if (s != VESIS_OK) return s;
+        for (int64_t c = 0; c < ncell; ++c) U[c] = lj[c] + cfa[c];
+    }
+    const double h3 = g.h * g.h * g.h, cc = ctx->sc.c;
+    const Atoms a = dev_atoms(ctx);
+    const Physics ph = dev_physics(ctx);
+    double* u64 = at<double>(ctx, ctx->lay.u64cache);
+    std::vector<double> exact(ncell, NAN);  // FP64 U of near-tie cells, once each
+    int64_t near_ties = 0, recomputes = 0;
+    auto label = [&](int x, int y, int z) -> int {
+        if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return 1;  // outside: solvent
+        return phi[x + (int64_t)n * (y + (int64_t)n * z)];
+    };
+    auto in_band = [&](int x, int y, int z) {
+        const int me = label(x, y, z);
+        return label(x - 1, y, z) != me || label(x + 1, y, z) != me || label(x, y - 1, z) != me ||
+               label(x, y + 1, z) != me || label(x, y, z - 1) != me || label(x, y, z + 1) != me;
+    };
+    hipError_t herr = hipSuccess;
+    // Delta E of cell (x, y, z), decided as a colour pass decides it: the
+    // stored U unless |Delta E| is within the cell's bound, then FP64 U
+    auto delta_e = [&](int x, int y, int z) -> double {
+        static const int NS[9] = {0, 6, 12, 8, 6, 24, 24, 0, 12};
+        int cnt[9] = {0};
+        for (int dz = -2; dz <= 2; ++dz)
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int q = dx * dx + dy * dy + dz * dz;
+                    if (q >= 1 && q <= 8) cnt[q] += label(x + dx, y + dy, z + dz) == 1;
+                }
+        double S = 0.0;
+        for (int q = 1; q <= 8; ++q) S += ctx->sc.w[q] * (double)(2 * cnt[q] - NS[q]);
+        const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
+        const double p = phi[c] == 1 ? 1.0 : -1.0;
+        const double cS = cc * S, hU = h3 * U[c];
+        const double dE = p * (cS - hU);
+        if (std::fabs(dE) > h3 * B[c] + 4.0e-16 * (std::fabs(cS) + std::fabs(hU))) return dE;
+        ++near_ties;
+        if (std::isnan(exact[c])) {
+            double two[2];
+            if (herr == hipSuccess) herr = launch_cell_density_f64(g, a, ph, x, y, z, u64, st);
+            if (herr == hipSuccess) herr = hipMemcpyAsync(&two[0], u64 + c, 8, hipMemcpyDeviceToHost, st);
+            if (herr == hipSuccess)
+                herr = hipMemcpyAsync(&two[1], u64 + ncell + c, 8, hipMemcpyDeviceToHost, st);
+            if (herr == hipSuccess) herr = hipStreamSynchronize(st);
+            if (herr != hipSuccess) return 0.0;
+            exact[c] = two[0] + two[1];
+            ++recomputes;
+        }
+        return p * (cS - h3 * exact[c]);
+    };
+    // the paper's flipping process: every band cell's Delta E in a min-heap;
+    // while the smallest is negative, flip that cell and re-evaluate the
+    // cells whose Delta E or band membership it changed (within two cells
+    // along each axis: the kernel's support); stale entries are dropped by a
+    // per-cell version
+    std::vector<int64_t> ver(ncell, 0);
+    std::vector<HeapItem> heap;
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x)
+                if (in_band(x, y, z))
+                    heap.push_back({delta_e(x, y, z), x + (int64_t)n * (y + (int64_t)n * z), 0});
+    std::make_heap(heap.begin(), heap.end(), HeapLater());
+    int64_t flips = 0;
+    bool converged = false;
+    while (herr == hipSuccess) {
+        if (heap.empty()) {
+            converged = true;
+            break;
+        }
+        std::pop_heap(heap.begin(), heap.end(), HeapLater());
+        const HeapItem it = heap.back();
+        heap.pop_back();
+        if (it.ver != ver[it.idx]) continue;
+        if (it.key >= 0.0) {
+            converged = true;
+            break;
+        }
+        if (flips == max_flips) break;
+        phi[it.idx] = (int8_t)(-phi[it.idx]);
+        ++flips;
+        const int x0 = (int)(it.idx % n), y0 = (int)((it.idx / n) % n), z0 = (int)(it.idx / ((int64_t)n * n));
+        for (int dz = -2; dz <= 2; ++dz)
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int x = x0 + dx, y = y0 + dy, z = z0 + dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) continue;
+                    const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
+                    ++ver[c];
+                    if (in_band(x, y, z)) {
+                        heap.push_back({delta_e(x, y, z), c, ver[c]});
+                        std::push_heap(heap.begin(), heap.end(), HeapLater());
+                    }
+                }
+    }
+    if (herr != hipSuccess)
+        return fail(ctx, VESIS_E_DEVICE, std::string("FP64 near-tie density: ") + hipGetErrorString(herr));
+    // the new labels back to the device
+    s = vesis_init_labels(ctx, 2, 0.0, phi.data());
+    if (s != VESIS_OK) return s;
+    if (out) {
+        int64_t band = 0;
+        for (int z = 0; z < n; ++z)
+            for (int y = 0; y < n; ++y)
+                for (int x = 0; x < n; ++x) band += in_band(x, y, z);
+        out->sweeps = 0;
+        out->converged = converged ? 1 : 0;
+        out->flips = flips;
+        out->band_cells = band;
+        out->near_ties = near_ties;
+        out->fp64_recomputes = recomputes;
+    }
+    ctx->err.clear();
+    return converged ? VESIS_OK : VESIS_NOT_CONVERGED;
+}
+
 vesis_status vesis_get_labels(vesis_ctx* ctx, int8_t* out) {
     if (!ctx || !out) return fail(ctx, VESIS_E_ARG, "null argument");
     vesis_status s = need(ctx, true);

@@ -171,6 +171,10 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                             int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
                             const CellFields& f, double* u64cache, int* sweep_flips,
                             int64_t* counters, hipStream_t st);
+// FP64 density parts of cell (x, y, z) into u64cache (LJ at c, CFA at
+// ncell + c), by one workgroup, as the colour passes compute near ties.
+hipError_t launch_cell_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x, int y,
+                                   int z, double* u64cache, hipStream_t st);
 // Batched colour pass: flip_slots(g, p) thread slots per molecule (a multiple
 // of the workgroup size).  Entry b of the block map is molecule |
 // (logical block << BATCH_MOL_BITS), or -1 for an idle workgroup.

@@ -481,6 +481,21 @@ __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     if ((t & 63) == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
 }
 
+// FP64 density parts of one cell into the near-tie cache (u64cache: LJ,
+// then CFA), by one workgroup: the value the colour passes compute for a
+// near tie, for the serial schedule's near ties.
+__global__ __launch_bounds__(FWG) void cell_density_f64_kernel(Grid g, Atoms a, Physics ph, int x,
+                                                               int y, int z, double* u64cache) {
+    __shared__ double s_red[4 * FWG];
+    double lj = 0.0, cfa = 0.0;
+    block_density_f64<8>(g, a, ph, x, y, z, s_red, lj, cfa);
+    if (threadIdx.x == 0) {
+        const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
+        u64cache[c] = lj;
+        u64cache[g.ncell() + c] = cfa;
+    }
+}
+
 // Labels from per-cell logits (FP32, x fastest): solute (bit 0) where the
 // logit is positive; padding bits stay solvent.
 __global__ void labels_from_logits_kernel(Grid g, const float* logits, uint32_t* bits) {
@@ -736,6 +751,14 @@ int64_t flip_slots(const Grid& g, int p) {
     const int64_t ny = (g.n + p - 1) / p;
     const int64_t slots = (int64_t)g.nwin * ny * ny;
     return (slots + FWG - 1) / FWG * FWG;
+}
+
+hipError_t launch_cell_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x, int y,
+                                   int z, double* u64cache, hipStream_t st) {
+    if (x < 0 || y < 0 || z < 0 || x >= g.n || y >= g.n || z >= g.n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cell_density_f64_kernel, dim3(1), dim3(FWG), 0, st, g, a, ph, x, y, z,
+                       u64cache);
+    return hipGetLastError();
 }
 
 hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,

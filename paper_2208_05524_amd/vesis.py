@@ -184,6 +184,14 @@ class Context:
                         band=st.band_cells, near_ties=st.near_ties,
                         fp64_recomputes=st.fp64_recomputes)
 
+    def minimize_heap(self, max_flips: int = 1 << 40):
+        """The serial min-heap flipping schedule (host heap, device density)."""
+        st = MinStats()
+        rc = self._check(self.lib.vesis_minimize_heap(self.h, int(max_flips), C.byref(st)),
+                         allow=(0, 1))
+        return rc, dict(converged=st.converged, flips=st.flips, band=st.band_cells,
+                        near_ties=st.near_ties, fp64_recomputes=st.fp64_recomputes)
+
     def energy(self) -> dict:
         e = EnergyParts()
         self._check(self.lib.vesis_energy(self.h, C.byref(e)))
