@@ -26,6 +26,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int CWG = 256;  // convolution workgroup: four wavefronts
 
@@ -123,8 +124,10 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_kernel(const __bf16* __restrict
 // tile of 4 MT x-rows of 32 positions (TY = 4 rows in y, TZ = MT in z) and
 // 32 NT output channels; per chunk of 16 input channels it stages the tile
 // with its one-cell halo (TZ+2) x 6 x 34 positions in LDS (16 channels =
-// 32 bytes per position, so the 32 rows of an operand are one contiguous
-// kilobyte: conflict-free 16-byte reads), then runs the 27 taps:
+// 32 bytes per position: the 32 rows of an operand are one contiguous
+// kilobyte, though eight lanes' 16-byte reads then fall on every other 16
+// bytes, a two-way bank conflict the z-reuse kernel below avoids), then
+// runs the 27 taps:
 // wavefront w takes y-row w of each of the MT z-layers of the tile (MT
 // operands of 32 positions) against NT output-channel tiles, the weights
 // read from global memory (shared by every workgroup, they stay in cache).
@@ -231,119 +234,163 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const ConvIn in,
     }
 }
 
-// Prefetching variant for the large layers (MT = 4 z-layers, one tile of
-// 32 output channels): per chunk of 16 input channels both the input tile
-// and the chunk's weights (27 taps x 32 output channels x 16 channels) are
-// staged in LDS, and the next chunk's are loaded into registers while the
-// current one is multiplied, so the matrix loop reads LDS only and the
-// global loads overlap it (loads issued inside the loop would have to wait
-// for the prefetch: they retire in order).  The products and their order
-// are those of conv3_fwd_lds_kernel<4, 1>, so the results are identical.
-template <bool RELU>
-__global__ __launch_bounds__(CWG) void conv3_fwd_pf_kernel(const ConvIn in,
+// The large layers: tile reuse along z, operands from LDS only.  A
+// workgroup owns TZ z-layers x 4 y-rows x 32 x-positions and 32 output
+// channels; wavefront w takes y-row w of every layer (TZ accumulators).  Per
+// chunk of 16 input channels the halo tile (TZ+2) x 6 x 34 and the chunk's
+// weights (27 taps x 32 output channels x 16 channels) sit in LDS, and the
+// next chunk's are loaded into registers (every load issued before any is
+// waited for) while the current one is multiplied.  The 27 taps run as 9
+// (dy, dx) pairs: the pair's three weight fragments (dz = 0, 1, 2) are read
+// once, and each staged operand of halo layer hz (32 positions of row wv +
+// dy, shifted by dx) is read once and multiplied into output layers hz - dz
+// for all three dz: per chunk 27 TZ matrix instructions against 9 (TZ + 2)
+// + 27 operand reads.  LDS holds each operand as two planes of 8 channels
+// (16 bytes per position), so the 16-byte reads of eight consecutive lanes
+// cover 128 contiguous bytes (no bank conflict); the second plane is offset
+// by 64 bytes so the staging writes, which alternate planes, do not
+// conflict either.  The staged pieces' element offsets are computed once per
+// workgroup (32-bit: the host checks that they fit).  Workgroups are dealt
+// to the chip's dies in contiguous runs of tiles (XCD-aware, as the colour
+// passes), so the halo rows neighbouring tiles share are served by one L2.
+constexpr int NXCD_CONV = 8;
+
+// One chunk's staged pieces into registers: input piece k from element
+// offset oa[k] (channels [0, ca), tensor A) or ob[k] (tensor B) plus the
+// chunk's first channel, zero where bit k of okm is clear; weight piece k
+// from ow[k] plus the chunk's first channel.  Every load is issued before
+// any result is used.
+template <int NA, int NW>
+__device__ __forceinline__ void conv_fetch(u32x4 (&pa)[NA], u32x4 (&pw)[NW], const int (&oa)[NA],
+                                           const int (&ob)[NA], uint32_t okm, const int (&ow)[NW],
+                                           const __bf16* abase, const __bf16* bbase,
+                                           const __bf16* Wt, int ca, int c0) {
+    const bool from_a = c0 < ca;  // uniform over the workgroup
+    const __bf16* base = from_a ? abase + c0 : bbase + (c0 - ca);
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(base + (from_a ? oa[k] : ob[k]));
+        pa[k] = (okm >> k) & 1u ? v : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) pw[k] = *reinterpret_cast<const u32x4*>(Wt + ow[k] + c0);
+}
+
+template <int TZ, bool RELU>
+__global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) void conv3_fwd_zp_kernel(const ConvIn in,
                                                            const __bf16* __restrict__ Wt,
                                                            const float* __restrict__ bias,
                                                            __bf16* __restrict__ Y, int N, int D,
-                                                           int H, int W, int Cin, int Cout) {
-    constexpr int MT = 4, TZ = MT, HZ = TZ + 2, HPOS = HZ * HY * HX;
-    constexpr int NA = (2 * HPOS + CWG - 1) / CWG;  // input 16-byte pieces per thread
-    constexpr int WQ = 27 * 32 * 2;                  // weight 16-byte pieces per chunk
+                                                           int H, int W, int Cin, int Cout,
+                                                           int64_t ntiles, int64_t per_die) {
+    constexpr int HZ = TZ + 2, HPOS = HZ * HY * HX;
+    constexpr int PT = HPOS * 8 + 32;       // elements per plane of the input tile
+    constexpr int PW = 27 * 32 * 8 + 32;    // elements per plane of the weights
+    constexpr int NA = (2 * HPOS + CWG - 1) / CWG;
+    constexpr int WQ = 27 * 32 * 2;
     constexpr int NW = (WQ + CWG - 1) / CWG;
-    __shared__ __attribute__((aligned(16))) __bf16 tile[HPOS * 16];
-    __shared__ __attribute__((aligned(16))) __bf16 wts[27 * 32 * 16];
+    __shared__ __attribute__((aligned(16))) __bf16 tile[2 * PT];
+    __shared__ __attribute__((aligned(16))) __bf16 wts[2 * PW];
+    const int64_t tid = (int64_t)(blockIdx.x % NXCD_CONV) * per_die + blockIdx.x / NXCD_CONV;
+    if (tid >= ntiles) return;  // whole workgroup: no barrier is skipped by part of it
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 31, half = lane >> 5;
     const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
-    const int x0 = (blockIdx.x % ntx) * TX;
-    const int y0 = ((int)(blockIdx.x / ntx) % nty) * TY;
-    const int co0 = blockIdx.y * 32;
-    const int z0 = ((int)blockIdx.z % ntz) * TZ;
-    const int nb = (int)blockIdx.z / ntz;
+    const int ncot = Cout / 32;
+    int64_t r = tid;
+    const int x0 = (int)(r % ntx) * TX;
+    r /= ntx;
+    const int y0 = (int)(r % nty) * TY;
+    r /= nty;
+    const int co0 = (int)(r % ncot) * 32;
+    r /= ncot;
+    const int z0 = (int)(r % ntz) * TZ;
+    const int nb = (int)(r / ntz);
     const int cb = Cin - in.ca;
     const int Da = in.up ? D / 2 : D, Ha = in.up ? H / 2 : H, Wa = in.up ? W / 2 : W;
-    f32x16 acc[MT];
+    const float bv = bias ? bias[co0 + row] : 0.f;  // loaded with the first chunk
+    f32x16 acc[TZ];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) acc[i] = f32x16{};
-    uint4 pa[NA], pw[NW];
-    auto fetch = [&](int c0) {
-        const bool from_a = c0 < in.ca;  // uniform over the workgroup
+    for (int i = 0; i < TZ; ++i) acc[i] = f32x16{};
+    // each thread's staged pieces as element offsets within this molecule's
+    // input (A and B) and within the weights, computed once: a chunk's fetch
+    // is then one add and one load per piece; pieces outside the volume load
+    // offset 0 and are replaced by zero
+    const __bf16* abase = in.a + (int64_t)nb * Da * Ha * Wa * in.ca;
+    const __bf16* bbase = cb > 0 ? in.b + (int64_t)nb * D * H * W * cb : abase;
+    int oa[NA], ob[NA];
+    uint32_t okm = 0;
 #pragma unroll
-        for (int k = 0; k < NA; ++k) {
-            const int e = threadIdx.x + k * CWG;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (e < 2 * HPOS) {
-                const int hp = e >> 1, hh = e & 1;
-                const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
-                const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
-                if (xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D) {
-                    const __bf16* src;
-                    if (from_a) {
-                        const int za = in.up ? zz >> 1 : zz, ya = in.up ? yy >> 1 : yy,
-                                  xa = in.up ? xx >> 1 : xx;
-                        src = in.a + ((((int64_t)nb * Da + za) * Ha + ya) * Wa + xa) * in.ca + c0;
-                    } else {
-                        src = in.b + ((((int64_t)nb * D + zz) * H + yy) * W + xx) * cb +
-                              (c0 - in.ca);
-                    }
-                    v = *reinterpret_cast<const uint4*>(src + 8 * hh);
-                }
-            }
-            pa[k] = v;
-        }
+    for (int k = 0; k < NA; ++k) {
+        const int e = threadIdx.x + k * CWG;
+        const int hp = e >> 1, hh = e & 1;
+        const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
+        const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+        const bool ok = e < 2 * HPOS && xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 &&
+                        zz < D;
+        const int za = in.up ? zz >> 1 : zz, ya = in.up ? yy >> 1 : yy, xa = in.up ? xx >> 1 : xx;
+        oa[k] = ok ? ((za * Ha + ya) * Wa + xa) * in.ca + 8 * hh : 0;
+        ob[k] = ok && cb > 0 ? ((zz * H + yy) * W + xx) * cb + 8 * hh : 0;
+        okm |= ok ? 1u << k : 0u;
+    }
+    int ow[NW];
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const int e = threadIdx.x + k * CWG;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (e < WQ) {
-                const int tap = e >> 6, co = (e >> 1) & 31, hh = e & 1;
-                v = *reinterpret_cast<const uint4*>(Wt + ((int64_t)tap * Cout + co0 + co) * Cin +
-                                                    c0 + 8 * hh);
-            }
-            pw[k] = v;
-        }
-    };
-    fetch(0);
+    for (int k = 0; k < NW; ++k) {
+        const int e = threadIdx.x + k * CWG;
+        const int tap = e >> 6, co = (e >> 1) & 31, hh = e & 1;
+        ow[k] = e < WQ ? (tap * Cout + co0 + co) * Cin + 8 * hh : 0;
+    }
+    u32x4 pa[NA], pw[NW];
+    conv_fetch(pa, pw, oa, ob, okm, ow, abase, bbase, Wt, in.ca, 0);
     for (int c0 = 0; c0 < Cin; c0 += 16) {
         __syncthreads();  // the previous chunk's LDS reads are done
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
             const int e = threadIdx.x + k * CWG;
-            if (e < 2 * HPOS) *reinterpret_cast<uint4*>(&tile[(e >> 1) * 16 + 8 * (e & 1)]) = pa[k];
+            if (e < 2 * HPOS) *reinterpret_cast<u32x4*>(&tile[(e & 1) * PT + (e >> 1) * 8]) = pa[k];
         }
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             const int e = threadIdx.x + k * CWG;
-            if (e < WQ) *reinterpret_cast<uint4*>(&wts[(e >> 1) * 16 + 8 * (e & 1)]) = pw[k];
+            if (e < WQ) *reinterpret_cast<u32x4*>(&wts[(e & 1) * PW + (e >> 1) * 8]) = pw[k];
         }
         __syncthreads();
-        if (c0 + 16 < Cin) fetch(c0 + 16);
-#pragma unroll 3
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // halo offsets 0..2
-            const bf16x8 b = load8(&wts[(tap * 32 + row) * 16 + 8 * half]);
+        if (c0 + 16 < Cin) conv_fetch(pa, pw, oa, ob, okm, ow, abase, bbase, Wt, in.ca, c0 + 16);
+        const __bf16* wl = &wts[half * PW + row * 8];
+        const __bf16* tl = &tile[half * PT + (wv * HX + row) * 8];
 #pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int hp = ((i + dz) * HY + (wv + dy)) * HX + (row + dx);
-                const bf16x8 a = load8(&tile[hp * 16 + 8 * half]);
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+        for (int yx = 0; yx < 9; ++yx) {
+            const int dy = yx / 3, dx = yx - 3 * dy;
+            bf16x8 b[3];
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) b[dz] = load8(wl + (dz * 9 + yx) * 32 * 8);
+#pragma unroll
+            for (int hz = 0; hz < HZ; ++hz) {
+                const bf16x8 a = load8(tl + ((hz * HY + dy) * HX + dx) * 8);
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz) {
+                    const int z = hz - dz;
+                    if (z >= 0 && z < TZ)
+                        acc[z] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[dz], acc[z], 0, 0, 0);
+                }
             }
         }
     }
-    // D[8 (r/4) + 4 half + r%4][row]: x = x0 + that, channel co0 + row
+    // D[8 (r/4) + 4 half + r%4][row]: x = x0 + that, channel co0 + row; a
+    // tile wholly inside the row stores at fixed offsets from one pointer
+    const bool full_x = x0 + TX <= W;
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
+    for (int i = 0; i < TZ; ++i) {
         const int z = z0 + i, y = y0 + wv;
         if (z >= D || y >= H) continue;
-        const int64_t rowbase = (((int64_t)nb * D + z) * H + y) * W;
-        const int co = co0 + row;
-        const float bv = bias ? bias[co] : 0.f;
+        __bf16* yr = Y + ((((int64_t)nb * D + z) * H + y) * W + x0 + 4 * half) * Cout + co0 + row;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int x = x0 + 8 * (r / 4) + 4 * half + (r % 4);
-            if (x >= W) continue;
-            float v = acc[i][r] + bv;
+        for (int q = 0; q < 16; ++q) {
+            const int dxq = 8 * (q / 4) + (q % 4);
+            if (!full_x && x0 + 4 * half + dxq >= W) continue;
+            float v = acc[i][q] + bv;
             if (RELU) v = v > 0.f ? v : 0.f;
-            Y[(rowbase + x) * Cout + co] = (__bf16)v;
+            yr[(int64_t)dxq * Cout] = (__bf16)v;
         }
     }
 }
@@ -820,35 +867,41 @@ int head_bwd(hipStream_t st, const float* dlogit, const void* x, const float* w,
     return status(hipGetLastError());
 }
 
-// LDS-staged tiles of 4 x-rows (y) x MT z-layers x 32 positions, one tile of
-// 32 output channels per workgroup.  Layers with at least as many such
-// workgroups (MT = 4) as CUs take the prefetching kernel when they have 64
-// or more output channels; with 32 (the finest level) the operand reads
-// from LDS bound the loop and the plain kernel, at twice the workgroups per
-// CU, is as fast.  The coarsest levels take MT = 1 (more, smaller
+// Layers with at least 256 workgroups of 4 z-layers take the z-reuse kernel
+// (when its 32-bit element offsets fit: the inputs of one molecule and the
+// weights each below 2^31 elements); smaller ones take
+// conv3_fwd_lds_kernel<1, 1> (one z-layer per workgroup: more, smaller
 // workgroups).
+template <int TZ>
+void launch_conv3_zp(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
+                     int n, int d, int h, int wd, int cin, int cout, int relu) {
+    const int64_t ntiles = (int64_t)((wd + TX - 1) / TX) * ((h + TY - 1) / TY) * (cout / 32) *
+                           ((d + TZ - 1) / TZ) * n;
+    const int64_t per = (ntiles + NXCD_CONV - 1) / NXCD_CONV;
+    const dim3 grid((unsigned)(per * NXCD_CONV));
+    if (relu)
+        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
+    else
+        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
+}
+
 void launch_conv3_lds(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
                       int n, int d, int h, int wd, int cin, int cout, int relu) {
     const unsigned nt_xy = (unsigned)(((wd + TX - 1) / TX) * ((h + TY - 1) / TY));
     const int64_t big = (int64_t)nt_xy * (cout / 32) * ((d + 3) / 4) * n;
-    const dim3 grid4(nt_xy, (unsigned)(cout / 32), (unsigned)(n * ((d + 3) / 4)));
-    if (big < 256) {
-        const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * d));
-        if (relu)
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-        else
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-    } else if (cout >= 64) {
-        if (relu)
-            hipLaunchKernelGGL((conv3_fwd_pf_kernel<true>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-        else
-            hipLaunchKernelGGL((conv3_fwd_pf_kernel<false>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-    } else {
-        if (relu)
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<4, 1, true>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
-        else
-            hipLaunchKernelGGL((conv3_fwd_lds_kernel<4, 1, false>), grid4, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    const int64_t lim = (int64_t)1 << 31;
+    const int64_t pos = (int64_t)d * h * wd;
+    const int64_t apos = in.up ? (int64_t)(d / 2) * (h / 2) * (wd / 2) : pos;
+    const bool fits = apos * in.ca < lim && pos * (cin - in.ca) < lim && 27LL * cout * cin < lim;
+    if (big >= 256 && fits) {
+        launch_conv3_zp<4>(st, in, w, bias, y, n, d, h, wd, cin, cout, relu);
+        return;
     }
+    const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * d));
+    if (relu)
+        hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
+    else
+        hipLaunchKernelGGL((conv3_fwd_lds_kernel<1, 1, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout);
 }
 }  // namespace
 

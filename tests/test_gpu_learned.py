@@ -132,11 +132,11 @@ def test_conv_forward_matches_reference(n, cin, cout, relu):
 @pytest.mark.parametrize("d,h,w,cin,cout", [(128, 6, 36, 16, 64), (256, 6, 36, 16, 32),
                                              (24, 6, 36, 32, 64)])
 def test_conv_forward_tilings_match_reference(d, h, w, cin, cout):
-    """The three LDS-tiled kernels (the prefetching one for 64 or more output
-    channels, MT = 4 for 32, and MT = 1 for layers with fewer workgroups
-    than CUs), chosen by the grid's size and channels: long
-    grids ragged in x and y against the 32 x 4 x MT tiles, every output
-    within BF16 rounding of the FP64 convolution of the same inputs."""
+    """Both LDS-tiled kernels (the z-reuse kernel for layers of 256 or more
+    4-layer workgroups, with one or two output-channel tiles, and MT = 1
+    below that), chosen by the grid's size: long grids ragged in x and y
+    against the 32 x 4 x MT tiles, every output within BF16 rounding of the
+    FP64 convolution of the same inputs."""
     import torch
 
     from oracle import unet
@@ -159,6 +159,66 @@ def test_conv_forward_tilings_match_reference(d, h, w, cin, cout):
     lim = 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max()
     log("conv tiling", (d, h, w, cin, cout), "max err/lim", float((err / lim).max()))
     assert np.all(err <= lim)
+
+
+@pytest.mark.parametrize("n,d,h,w,cin,cout,relu", [(3, 42, 18, 40, 48, 32, 0),
+                                                    (2, 21, 9, 70, 32, 96, 1)])
+def test_conv_zreuse_batched_ragged_matches_reference(n, d, h, w, cin, cout, relu):
+    """The z-reuse kernel on a batch of molecules (per-molecule offsets),
+    ragged in every axis against its 32 x 4 x 4 tiles (z too), three chunks
+    of input channels (prefetch across chunks), one and three
+    output-channel tiles, with and without ReLU."""
+    import torch
+
+    from oracle import unet
+    from paper_2208_05524_amd import nn
+    r = np.random.default_rng(n * 1000 + d + cout)
+    x = _bf(r.standard_normal((n, d, h, w, cin)))
+    wt = _bf(0.1 * r.standard_normal((27, cout, cin)))
+    b = r.standard_normal(cout).astype(np.float32)
+    ref = unet.conv(torch.as_tensor(x).permute(0, 4, 1, 2, 3), unet.to_torch_weight(wt),
+                    torch.as_tensor(b.astype(np.float64)), relu=bool(relu))
+    ref = ref.permute(0, 2, 3, 4, 1).numpy()
+    L = nn.lib()
+    xd, wd = _dev_bf16(x), _dev_bf16(wt)
+    bd = torch.tensor(b, device="cuda")
+    yd = torch.full((n, d, h, w, cout), float("nan"), dtype=torch.bfloat16, device="cuda")
+    nn.check(L.vesis_nn_conv3_fwd(_stream(), nn.ptr(xd), nn.ptr(wd), nn.ptr(bd), nn.ptr(yd), n, d,
+                                  h, w, cin, cout, relu), "conv")
+    y = yd.float().cpu().numpy()
+    err = np.abs(y - ref)
+    lim = 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+    log("conv z-reuse", (n, d, h, w, cin, cout, relu), "max err/lim", float((err / lim).max()))
+    assert np.all(err <= lim)
+
+
+def test_conv_zreuse_upcat_batched_equals_concatenation():
+    """The z-reuse kernel reading [up2(a) | b] in place on a batch of two
+    ragged grids gives the convolution of the materialised concatenation
+    bit for bit."""
+    import torch
+
+    from paper_2208_05524_amd import nn
+    n, d, h, w, ca, cb, cout = 2, 26, 20, 36, 32, 16, 64
+    r = np.random.default_rng(77)
+    a = _dev_bf16(r.standard_normal((n, d // 2, h // 2, w // 2, ca)))
+    b = _dev_bf16(r.standard_normal((n, d, h, w, cb)))
+    wt = _dev_bf16(0.1 * r.standard_normal((27, cout, ca + cb)))
+    bias = torch.tensor(r.standard_normal(cout).astype(np.float32), device="cuda")
+    L = nn.lib()
+    P = d * h * w
+    up = torch.empty((n, d, h, w, ca), dtype=torch.bfloat16, device="cuda")
+    cat = torch.empty((n, d, h, w, ca + cb), dtype=torch.bfloat16, device="cuda")
+    y0 = torch.empty((n, d, h, w, cout), dtype=torch.bfloat16, device="cuda")
+    y1 = torch.full((n, d, h, w, cout), float("nan"), dtype=torch.bfloat16, device="cuda")
+    nn.check(L.vesis_nn_up2(_stream(), nn.ptr(a), nn.ptr(up), n, d, h, w, ca, 0), "up")
+    nn.check(L.vesis_nn_concat(_stream(), nn.ptr(up), ca, nn.ptr(b), cb, nn.ptr(cat), n * P), "cat")
+    nn.check(L.vesis_nn_conv3_fwd(_stream(), nn.ptr(cat), nn.ptr(wt), nn.ptr(bias), nn.ptr(y0), n,
+                                  d, h, w, ca + cb, cout, 1), "conv")
+    nn.check(L.vesis_nn_conv3_fwd_upcat(_stream(), nn.ptr(a), ca, nn.ptr(b), cb, nn.ptr(wt),
+                                        nn.ptr(bias), nn.ptr(y1), n, d, h, w, cout, 1), "upcat")
+    torch.cuda.synchronize()
+    assert torch.equal(y0.view(torch.int16), y1.view(torch.int16))
 
 
 def test_conv_gradients_match_reference():
