@@ -8,6 +8,8 @@ passes' (stored U unless inside the cell's bound, then FP64), so the end
 state must be a local minimum of the oracle's FP64 energy: no band cell with
 Delta E below -1e-12 of its terms' size.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -111,3 +113,41 @@ def test_heap_degenerate_starts():
     log("all solute", st, ost)
     assert rc == 0 and st["flips"] == ost["flips"]
     assert np.array_equal(ctx.labels(), ophi)
+
+
+def test_heap_colour_period_two_fp32():
+    """Kernel radius rho_s = 2 (a smaller support, fewer stencil shells) in
+    FP32 storage, loose start: a local minimum of the oracle's FP64 energy
+    (the labels' difference from the oracle heap's is logged)."""
+    w = ragged_small(seed=20, n=29, natoms=70)
+    w = dataclasses.replace(w, params=dataclasses.replace(w.params, rho_s=2.0))
+    phi0 = _start(w, "loose")
+    ctx = gpu_context(w, precision=32)
+    ctx.init_labels("user", user=phi0)
+    rc, gst = ctx.minimize_heap()
+    glab = ctx.labels()
+    s, ophi, orc, ost, (ulj, ucfa) = _oracle_heap(w, phi0)
+    u = ulj + ucfa
+    band = [c for c in range(w.n ** 3) if s.in_band(glab, c)]
+    worst = min((s.delta_e(glab, u, c) / (abs(w.h ** 3 * u[c]) + 1e-30) for c in band),
+                default=0.0)
+    log("heap rho_s 2", gst, "oracle", ost, "differing", int(np.count_nonzero(glab != ophi)),
+        "worst", worst)
+    assert rc == 0 and gst["converged"] == 1
+    assert worst >= -1e-12
+    assert gst["band"] == len(band)
+
+
+def test_heap_argument_errors():
+    from paper_2208_05524_amd import VesisError
+    w = ragged_small(seed=21, n=20, natoms=10)
+    ctx = gpu_context(w)
+    with pytest.raises(VesisError) as e:
+        ctx.minimize_heap()
+    assert e.value.status == -2                      # labels not initialised
+    ctx.init_labels("tight", 1.0)
+    with pytest.raises(VesisError) as e:
+        ctx.minimize_heap(max_flips=-1)
+    assert e.value.status == -1                      # negative flip budget
+    rc, st = ctx.minimize_heap(max_flips=0)
+    assert st["flips"] == 0 and rc in (0, 1)
