@@ -235,17 +235,18 @@ __global__ __launch_bounds__(CWG) void conv3_fwd_lds_kernel(const ConvIn in,
 }
 
 // The large layers: tile reuse along z, operands from LDS only.  A
-// workgroup owns TZ z-layers x 4 y-rows x 32 x-positions and 32 output
-// channels; wavefront w takes y-row w of every layer (TZ accumulators).  Per
-// chunk of 16 input channels the halo tile (TZ+2) x 6 x 34 and the chunk's
+// workgroup of ZW groups of four wavefronts owns ZW TZ z-layers x 4 y-rows
+// x 32 x-positions and 32 output channels; wavefront w of group zg takes
+// y-row w of layers zg TZ .. zg TZ + TZ - 1 (TZ accumulators).  Per chunk of
+// 16 input channels the halo tile (ZW TZ + 2) x 6 x 34 and the chunk's
 // weights (27 taps x 32 output channels x 16 channels) sit in LDS, and the
 // next chunk's are loaded into registers (every load issued before any is
 // waited for) while the current one is multiplied.  The 27 taps run as 9
 // (dy, dx) pairs: the pair's three weight fragments (dz = 0, 1, 2) are read
 // once, and each staged operand of halo layer hz (32 positions of row wv +
 // dy, shifted by dx) is read once and multiplied into output layers hz - dz
-// for all three dz: per chunk 27 TZ matrix instructions against 9 (TZ + 2)
-// + 27 operand reads.  LDS holds each operand as two planes of 8 channels
+// for all three dz: per chunk and wavefront 27 TZ matrix instructions
+// against 9 (TZ + 2) + 27 operand reads.  LDS holds each operand as two planes of 8 channels
 // (16 bytes per position), so the 16-byte reads of eight consecutive lanes
 // cover 128 contiguous bytes (no bank conflict); the second plane is offset
 // by 64 bytes so the staging writes, which alternate planes, do not
@@ -276,26 +277,27 @@ __device__ __forceinline__ void conv_fetch(u32x4 (&pa)[NA], u32x4 (&pw)[NW], con
     for (int k = 0; k < NW; ++k) pw[k] = *reinterpret_cast<const u32x4*>(Wt + ow[k] + c0);
 }
 
-template <int TZ, bool RELU>
-__global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) void conv3_fwd_zp_kernel(const ConvIn in,
+template <int TZ, int ZW, bool RELU>
+__global__ __launch_bounds__(CWG * ZW) __attribute__((amdgpu_waves_per_eu(2, 8))) void conv3_fwd_zp_kernel(const ConvIn in,
                                                            const __bf16* __restrict__ Wt,
                                                            const float* __restrict__ bias,
                                                            __bf16* __restrict__ Y, int N, int D,
                                                            int H, int W, int Cin, int Cout,
                                                            int64_t ntiles, int64_t per_die) {
-    constexpr int HZ = TZ + 2, HPOS = HZ * HY * HX;
+    constexpr int NT = CWG * ZW;             // threads: ZW groups of four wavefronts
+    constexpr int HZ = ZW * TZ + 2, HPOS = HZ * HY * HX;
     constexpr int PT = HPOS * 8 + 32;       // elements per plane of the input tile
     constexpr int PW = 27 * 32 * 8 + 32;    // elements per plane of the weights
-    constexpr int NA = (2 * HPOS + CWG - 1) / CWG;
+    constexpr int NA = (2 * HPOS + NT - 1) / NT;
     constexpr int WQ = 27 * 32 * 2;
-    constexpr int NW = (WQ + CWG - 1) / CWG;
+    constexpr int NW = (WQ + NT - 1) / NT;
     __shared__ __attribute__((aligned(16))) __bf16 tile[2 * PT];
     __shared__ __attribute__((aligned(16))) __bf16 wts[2 * PW];
     const int64_t tid = (int64_t)(blockIdx.x % NXCD_CONV) * per_die + blockIdx.x / NXCD_CONV;
     if (tid >= ntiles) return;  // whole workgroup: no barrier is skipped by part of it
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3, zg = threadIdx.x >> 8;
     const int row = lane & 31, half = lane >> 5;
-    const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
+    const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + ZW * TZ - 1) / (ZW * TZ);
     const int ncot = Cout / 32;
     int64_t r = tid;
     const int x0 = (int)(r % ntx) * TX;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     r /= nty;
     const int co0 = (int)(r % ncot) * 32;
     r /= ncot;
-    const int z0 = (int)(r % ntz) * TZ;
+    const int z0 = (int)(r % ntz) * (ZW * TZ);
     const int nb = (int)(r / ntz);
     const int cb = Cin - in.ca;
     const int Da = in.up ? D / 2 : D, Ha = in.up ? H / 2 : H, Wa = in.up ? W / 2 : W;
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     uint32_t okm = 0;
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
-        const int e = threadIdx.x + k * CWG;
+        const int e = threadIdx.x + k * NT;
         const int hp = e >> 1, hh = e & 1;
         const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
         const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     int ow[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-        const int e = threadIdx.x + k * CWG;
+        const int e = threadIdx.x + k * NT;
         const int tap = e >> 6, co = (e >> 1) & 31, hh = e & 1;
         ow[k] = e < WQ ? (tap * Cout + co0 + co) * Cin + 8 * hh : 0;
     }
@@ -346,18 +348,18 @@ __global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         __syncthreads();  // the previous chunk's LDS reads are done
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
-            const int e = threadIdx.x + k * CWG;
+            const int e = threadIdx.x + k * NT;
             if (e < 2 * HPOS) *reinterpret_cast<u32x4*>(&tile[(e & 1) * PT + (e >> 1) * 8]) = pa[k];
         }
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-            const int e = threadIdx.x + k * CWG;
+            const int e = threadIdx.x + k * NT;
             if (e < WQ) *reinterpret_cast<u32x4*>(&wts[(e & 1) * PW + (e >> 1) * 8]) = pw[k];
         }
         __syncthreads();
         if (c0 + 16 < Cin) conv_fetch(pa, pw, oa, ob, okm, ow, abase, bbase, Wt, in.ca, c0 + 16);
         const __bf16* wl = &wts[half * PW + row * 8];
-        const __bf16* tl = &tile[half * PT + (wv * HX + row) * 8];
+        const __bf16* tl = &tile[half * PT + ((zg * TZ * HY + wv) * HX + row) * 8];
 #pragma unroll
         for (int yx = 0; yx < 9; ++yx) {
             const int dy = yx / 3, dx = yx - 3 * dy;
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(CWG) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const bool full_x = x0 + TX <= W;
 #pragma unroll
     for (int i = 0; i < TZ; ++i) {
-        const int z = z0 + i, y = y0 + wv;
+        const int z = z0 + zg * TZ + i, y = y0 + wv;
         if (z >= D || y >= H) continue;
         __bf16* yr = Y + ((((int64_t)nb * D + z) * H + y) * W + x0 + 4 * half) * Cout + co0 + row;
 #pragma unroll
@@ -867,22 +869,22 @@ int head_bwd(hipStream_t st, const float* dlogit, const void* x, const float* w,
     return status(hipGetLastError());
 }
 
-// Layers with at least 256 workgroups of 4 z-layers take the z-reuse kernel
+// Layers with at least 256 tiles of 4 z-layers take the z-reuse kernel
 // (when its 32-bit element offsets fit: the inputs of one molecule and the
 // weights each below 2^31 elements); smaller ones take
 // conv3_fwd_lds_kernel<1, 1> (one z-layer per workgroup: more, smaller
 // workgroups).
-template <int TZ>
+template <int TZ, int ZW>
 void launch_conv3_zp(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
                      int n, int d, int h, int wd, int cin, int cout, int relu) {
     const int64_t ntiles = (int64_t)((wd + TX - 1) / TX) * ((h + TY - 1) / TY) * (cout / 32) *
-                           ((d + TZ - 1) / TZ) * n;
+                           ((d + ZW * TZ - 1) / (ZW * TZ)) * n;
     const int64_t per = (ntiles + NXCD_CONV - 1) / NXCD_CONV;
     const dim3 grid((unsigned)(per * NXCD_CONV));
     if (relu)
-        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, true>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
+        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, ZW, true>), grid, dim3(CWG * ZW), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
     else
-        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, false>), grid, dim3(CWG), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
+        hipLaunchKernelGGL((conv3_fwd_zp_kernel<TZ, ZW, false>), grid, dim3(CWG * ZW), 0, st, in, B(w), bias, Bm(y), n, d, h, wd, cin, cout, ntiles, per);
 }
 
 void launch_conv3_lds(hipStream_t st, const ConvIn& in, const void* w, const float* bias, void* y,
@@ -894,7 +896,14 @@ void launch_conv3_lds(hipStream_t st, const ConvIn& in, const void* w, const flo
     const int64_t apos = in.up ? (int64_t)(d / 2) * (h / 2) * (wd / 2) : pos;
     const bool fits = apos * in.ca < lim && pos * (cin - in.ca) < lim && 27LL * cout * cin < lim;
     if (big >= 256 && fits) {
-        launch_conv3_zp<4>(st, in, w, bias, y, n, d, h, wd, cin, cout, relu);
+        // 2 z-layers per wavefront: 126 registers, four wavefronts per SIMD;
+        // the tile is shared by two groups of four wavefronts (4 z-layers),
+        // or by four (8 z-layers) when the chunks are many (each chunk's
+        // staging then serves twice the outputs)
+        if (cin <= 64)
+            launch_conv3_zp<2, 2>(st, in, w, bias, y, n, d, h, wd, cin, cout, relu);
+        else
+            launch_conv3_zp<2, 4>(st, in, w, bias, y, n, d, h, wd, cin, cout, relu);
         return;
     }
     const dim3 grid(nt_xy, (unsigned)(cout / 32), (unsigned)(n * d));

@@ -162,12 +162,13 @@ def test_conv_forward_tilings_match_reference(d, h, w, cin, cout):
 
 
 @pytest.mark.parametrize("n,d,h,w,cin,cout,relu", [(3, 42, 18, 40, 48, 32, 0),
-                                                    (2, 21, 9, 70, 32, 96, 1)])
+                                                    (2, 21, 9, 70, 32, 96, 1),
+                                                    (2, 41, 14, 66, 80, 32, 0)])
 def test_conv_zreuse_batched_ragged_matches_reference(n, d, h, w, cin, cout, relu):
     """The z-reuse kernel on a batch of molecules (per-molecule offsets),
-    ragged in every axis against its 32 x 4 x 4 tiles (z too), three chunks
-    of input channels (prefetch across chunks), one and three
-    output-channel tiles, with and without ReLU."""
+    ragged in every axis against its 32 x 4 x 4 and 32 x 4 x 8 tiles (z
+    too), three and five chunks of input channels (prefetch across chunks),
+    one and three output-channel tiles, with and without ReLU."""
     import torch
 
     from oracle import unet
