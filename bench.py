@@ -66,9 +66,9 @@ def measured_traffic(kernel: str = "density_grid_f32"):
 
 def measured_flip_traffic():
     """HBM traffic of the batched colour pass on the 64-molecule workload
-    from the committed PMC summary: bytes per dispatch, average dispatch
-    time and their ratio against 8 TB/s, or None when the colour-pass source
-    has changed since the counters were taken."""
+    from the committed PMC summary: the profiled register variant, bytes per
+    dispatch, average dispatch time and their ratio against 8 TB/s, or None
+    when the colour-pass source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_batch64_flip.md")
     src = os.path.join(ROOT, "paper_2208_05524_amd", "csrc", "labels.hip")
@@ -85,8 +85,8 @@ def measured_flip_traffic():
                 return None
             b, us = float(kv["bytes_per_dispatch"]), float(kv["avg_us"])
             gbs = b / (us * 1e-6) / 1e9
-            return {"bytes_per_dispatch": b, "avg_us": us, "GB_per_s": gbs,
-                    "frac_of_8TBs": gbs / 8000.0}
+            return {"kernel": kv.get("kernel"), "bytes_per_dispatch": b, "avg_us": us,
+                    "GB_per_s": gbs, "frac_of_8TBs": gbs / 8000.0}
     return None
 
 
