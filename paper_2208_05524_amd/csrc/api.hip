@@ -2005,18 +2005,32 @@ vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_st
     hipError_t herr = hipSuccess;
     // Delta E of cell (x, y, z), decided as a colour pass decides it: the
     // stored U unless |Delta E| is within the cell's bound, then FP64 U
+    // the stencil's offsets (squared length 1..8) and, per cell, the number
+    // of solvent cells at each squared offset (outside the box: solvent),
+    // kept up to date flip by flip
+    struct Off {
+        int dx, dy, dz, q;
+    };
+    std::vector<Off> offs;
+    for (int dz = -2; dz <= 2; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+                const int q = dx * dx + dy * dy + dz * dz;
+                if (q >= 1 && q <= 8) offs.push_back({dx, dy, dz, q});
+            }
+    std::vector<uint8_t> cnt(9 * (size_t)ncell, 0);
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                uint8_t* cc9 = &cnt[9 * (size_t)(x + (int64_t)n * (y + (int64_t)n * z))];
+                for (const Off& o : offs) cc9[o.q] += label(x + o.dx, y + o.dy, z + o.dz) == 1;
+            }
     auto delta_e = [&](int x, int y, int z) -> double {
         static const int NS[9] = {0, 6, 12, 8, 6, 24, 24, 0, 12};
-        int cnt[9] = {0};
-        for (int dz = -2; dz <= 2; ++dz)
-            for (int dy = -2; dy <= 2; ++dy)
-                for (int dx = -2; dx <= 2; ++dx) {
-                    const int q = dx * dx + dy * dy + dz * dz;
-                    if (q >= 1 && q <= 8) cnt[q] += label(x + dx, y + dy, z + dz) == 1;
-                }
-        double S = 0.0;
-        for (int q = 1; q <= 8; ++q) S += ctx->sc.w[q] * (double)(2 * cnt[q] - NS[q]);
         const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
+        const uint8_t* cc9 = &cnt[9 * (size_t)c];
+        double S = 0.0;
+        for (int q = 1; q <= 8; ++q) S += ctx->sc.w[q] * (double)(2 * (int)cc9[q] - NS[q]);
         const double p = phi[c] == 1 ? 1.0 : -1.0;
         const double cS = cc * S, hU = h3 * U[c];
         const double dE = p * (cS - hU);
@@ -2067,18 +2081,29 @@ vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_st
         phi[it.idx] = (int8_t)(-phi[it.idx]);
         ++flips;
         const int x0 = (int)(it.idx % n), y0 = (int)((it.idx / n) % n), z0 = (int)(it.idx / ((int64_t)n * n));
-        for (int dz = -2; dz <= 2; ++dz)
-            for (int dy = -2; dy <= 2; ++dy)
-                for (int dx = -2; dx <= 2; ++dx) {
-                    const int x = x0 + dx, y = y0 + dy, z = z0 + dz;
-                    if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) continue;
-                    const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
-                    ++ver[c];
-                    if (in_band(x, y, z)) {
-                        heap.push_back({delta_e(x, y, z), c, ver[c]});
-                        std::push_heap(heap.begin(), heap.end(), HeapLater());
-                    }
-                }
+        // the flipped cell's stencil neighbours gain or lose a solvent cell
+        // at their offset; they and the cell itself are re-evaluated (the
+        // rest of the 5 x 5 x 5 cube keeps its Delta E and band membership)
+        auto reevaluate = [&](int x, int y, int z) {
+            const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
+            ++ver[c];
+            if (in_band(x, y, z)) {
+                heap.push_back({delta_e(x, y, z), c, ver[c]});
+                std::push_heap(heap.begin(), heap.end(), HeapLater());
+            }
+        };
+        const int add = phi[it.idx] == 1 ? 1 : -1;
+        for (const Off& o : offs) {
+            const int x = x0 + o.dx, y = y0 + o.dy, z = z0 + o.dz;
+            if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) continue;
+            cnt[9 * (size_t)(x + (int64_t)n * (y + (int64_t)n * z)) + o.q] += add;
+        }
+        reevaluate(x0, y0, z0);
+        for (const Off& o : offs) {
+            const int x = x0 + o.dx, y = y0 + o.dy, z = z0 + o.dz;
+            if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) continue;
+            reevaluate(x, y, z);
+        }
     }
     if (herr != hipSuccess)
         return fail(ctx, VESIS_E_DEVICE, std::string("FP64 near-tie density: ") + hipGetErrorString(herr));
