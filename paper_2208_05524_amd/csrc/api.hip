@@ -2003,8 +2003,6 @@ vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_st
                label(x, y + 1, z) != me || label(x, y, z - 1) != me || label(x, y, z + 1) != me;
     };
     hipError_t herr = hipSuccess;
-    // Delta E of cell (x, y, z), decided as a colour pass decides it: the
-    // stored U unless |Delta E| is within the cell's bound, then FP64 U
     // the stencil's offsets (squared length 1..8) and, per cell, the number
     // of solvent cells at each squared offset (outside the box: solvent),
     // kept up to date flip by flip
@@ -2025,6 +2023,8 @@ vesis_status vesis_minimize_heap(vesis_ctx* ctx, int64_t max_flips, vesis_min_st
                 uint8_t* cc9 = &cnt[9 * (size_t)(x + (int64_t)n * (y + (int64_t)n * z))];
                 for (const Off& o : offs) cc9[o.q] += label(x + o.dx, y + o.dy, z + o.dz) == 1;
             }
+    // Delta E of cell (x, y, z), decided as a colour pass decides it: the
+    // stored U unless |Delta E| is within the cell's bound, then FP64 U
     auto delta_e = [&](int x, int y, int z) -> double {
         static const int NS[9] = {0, 6, 12, 8, 6, 24, 24, 0, 12};
         const int64_t c = x + (int64_t)n * (y + (int64_t)n * z);
