@@ -1165,11 +1165,23 @@ vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_
         CK(launch_fill_u32(reinterpret_cast<uint32_t*>(flips), SWEEP_BATCH, 0u, st));
         {
             Timed t(ctx, K_FLIP);
-            for (int sw = 0; sw < nb; ++sw)
-                for (int c = 0; c < ncol; ++c)
-                    CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw, (sweeps + sw) * ncol + c,
-                                        bits, stamp, cf, at<double>(ctx, ctx->lay.u64cache), flips,
-                                        counters, st));
+            for (int sw = 0; sw < nb; ++sw) {
+                if (ctx->sc.p == 3) {
+                    // colour period 3: the colours sharing their rows go three
+                    // to a launch
+                    for (int grp = 0; grp < 9; ++grp)
+                        CK(launch_flip_group3(ctx->g, ctx->sc, a, ph, grp, sw,
+                                              (sweeps + sw) * ncol + 3 * grp, bits, stamp, cf,
+                                              at<double>(ctx, ctx->lay.u64cache), flips,
+                                              counters, st));
+                } else {
+                    for (int c = 0; c < ncol; ++c)
+                        CK(launch_flip_pass(ctx->g, ctx->sc, a, ph, c, sw,
+                                            (sweeps + sw) * ncol + c, bits, stamp, cf,
+                                            at<double>(ctx, ctx->lay.u64cache), flips, counters,
+                                            st));
+                }
+            }
         }
         int hf[SWEEP_BATCH];
         CK(hipMemcpyAsync(hf, flips, sizeof(int) * nb, hipMemcpyDeviceToHost, st));

@@ -171,6 +171,13 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                             int colour, int sweep, int gpass, uint32_t* bits, int* stamp,
                             const CellFields& f, double* u64cache, int* sweep_flips,
                             int64_t* counters, hipStream_t st);
+// The three colour passes 3 group + a, a = 0, 1, 2 (colour period 3: they
+// share their rows), in one launch: the same decisions, flips and stamps as
+// the three separate passes; gpass0 is the global index of the first.
+hipError_t launch_flip_group3(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
+                              int group, int sweep, int gpass0, uint32_t* bits, int* stamp,
+                              const CellFields& f, double* u64cache, int* sweep_flips,
+                              int64_t* counters, hipStream_t st);
 // FP64 density parts of cell (x, y, z) into u64cache (LJ at c, CFA at
 // ncell + c), by one workgroup, as the colour passes compute near ties.
 hipError_t launch_cell_density_f64(const Grid& g, const Atoms& a, const Physics& ph, int x, int y,

@@ -481,6 +481,222 @@ __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     if ((t & 63) == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
 }
 
+// The three colour passes (a, cb, cc), a = 0, 1, 2, of colour period 3 in
+// one launch.  They share their rows (y = cb, z = cc mod 3), and since the
+// kernel reaches two cells, a cell of one of these rows sees no label of
+// another of them: across the three passes each row depends on itself
+// only.  A workgroup owns whole rows (one lane per word, nwin lanes per row)
+// and runs the three passes back to back with its rows' words and their
+// stamps in LDS; the other rows a candidate's stencil reads do not change
+// during the launch and come from global memory.  Each decision is the one
+// the separate passes take (same stencil sums, same stored values, the same
+// FP64 near-tie path), so labels, flip counts and stamps are identical: a
+// word's stamp is the pass of the latest flip in its neighbourhood, written
+// with atomicMax at the end (within the launch only the row's own words can
+// be stamped, and those stamps are tracked in LDS).
+__global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, int cb, int cc, int sweep,
+                                                          int gpass0, int ncol,
+                                                          int64_t xcd_blocks) {
+    constexpr int P = 3, K = 11;
+    __shared__ double s_red[4 * FWG];
+    __shared__ double s_cs[K * FWG];
+    __shared__ int s_item[FWG * K];
+    __shared__ int s_wsum[FWG / 64];
+    __shared__ int s_wyz[3][FWG];
+    __shared__ uint32_t s_fm[FWG], s_tm[FWG];
+    __shared__ uint32_t s_word[FWG];  // each lane's own word, as the passes change it
+    __shared__ int s_stw[FWG];        // its stamp, with this launch's flips in the row
+    __shared__ int s_leader;
+    __shared__ int s_tie[4];
+    const MolDesc& D = one;
+    const Grid& g = D.g;
+    const Stencil& sc = D.sc;
+    const Atoms& a = D.a;
+    const Physics& ph = D.ph;
+    uint32_t* bits = D.bits;
+    int* stamp = D.stamp;
+    const CellFields& cf = D.f;
+    double* u64cache = D.u64cache;
+    int* sweep_flips = D.sweep_flips;
+    int64_t* counters = D.counters;
+    if (sweep > 0 && sweep_flips[sweep - 1] == 0) return;
+    const int nwin = g.nwin;
+    const int rpw = FWG / nwin;  // whole rows per workgroup
+    const int ny = (g.n - cb + P - 1) / P, nz = (g.n - cc + P - 1) / P;
+    const int64_t nrows = (int64_t)ny * nz;
+    const int64_t lblock = flip_block_of(blockIdx.x, xcd_blocks);
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int rl = t / nwin, w = t - rl * nwin;
+    const int64_t rid = lblock * rpw + rl;
+    const bool active = rl < rpw && rid < nrows;
+    int y = 0, z = 0;
+    if (active) {
+        y = cb + P * (int)(rid % ny);
+        z = cc + P * (int)(rid / ny);
+    }
+    const int x0 = 32 * w;
+    uint32_t* rowc = bits + g.row(y, z);
+    uint32_t C = 0, Lpad = 0, Rpad = 0, ym = 0, yp = 0, zm = 0, zp = 0;
+    int stw = 0;
+    if (active) {
+        stw = stamp[g.row(y, z) + 1 + w];
+        C = rowc[w + 1];
+        Lpad = rowc[w];      // the row's left padding word when w == 0
+        Rpad = rowc[w + 2];  // the right padding word when w == nwin - 1
+        ym = bits[g.row(y - 1, z) + w + 1];
+        yp = bits[g.row(y + 1, z) + w + 1];
+        zm = bits[g.row(y, z - 1) + w + 1];
+        zp = bits[g.row(y, z + 1) + w + 1];
+    }
+    s_word[t] = C;
+    s_stw[t] = stw;
+    s_wyz[0][t] = w;
+    s_wyz[1][t] = y;
+    s_wyz[2][t] = z;
+    int nflips = 0, last = -1;  // this lane's flips in the launch, pass of its last
+    for (int ca = 0; ca < P; ++ca) {
+        const int gpass = gpass0 + ca;
+        __syncthreads();  // the previous pass's words and stamps are in LDS
+        C = s_word[t];
+        stw = s_stw[t];
+        uint32_t cand = 0;
+        if (active) {
+            const uint32_t Lw = w == 0 ? Lpad : s_word[t - 1];
+            const uint32_t Rw = w == nwin - 1 ? Rpad : s_word[t + 1];
+            const uint32_t fresh = (gpass >= ncol && stw < gpass - ncol) ? 0u : 0xffffffffu;
+            const uint32_t left = (C << 1) | (Lw >> 31);
+            const uint32_t right = (C >> 1) | (Rw << 31);
+            const uint32_t band = (C ^ left) | (C ^ right) | (C ^ ym) | (C ^ yp) | (C ^ zm) | (C ^ zp);
+            const uint32_t cmask = 0x49249249u << (((ca - x0) % P + P) % P);
+            cand = band & cmask & valid_mask(g.n, x0) & fresh;
+        }
+        s_fm[t] = 0u;
+        s_tm[t] = 0u;
+        const int nc = __popc(cand);
+        int incl = nc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) s_wsum[wv] = incl;
+        __syncthreads();
+        int base = 0, nitems = 0;
+#pragma unroll
+        for (int v = 0; v < FWG / 64; ++v) {
+            base += v < wv ? s_wsum[v] : 0;
+            nitems += s_wsum[v];
+        }
+        {
+            int k = base + incl - nc;
+            uint32_t cm = cand;
+            while (cm) {
+                const int b = __ffs(cm) - 1;
+                cm &= cm - 1;
+                s_item[k++] = (t << 5) | b;
+            }
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < nitems; k0 += FWG) {
+            const int k = k0 + t;
+            if (k >= nitems) continue;
+            const int it = s_item[k];
+            const int b = it & 31;
+            const int to = it >> 5;
+            const int wo = s_wyz[0][to], yo = s_wyz[1][to], zo = s_wyz[2][to];
+            const int64_t c = (int64_t)(32 * wo + b) + (int64_t)g.n * (yo + (int64_t)g.n * zo);
+            Win25 Wn;
+            uint32_t Co;
+            {
+                Rows25 R;
+                load_rows(g, bits, wo, yo, zo, R);
+                // the owner's row (dy = dz = 0) as the earlier passes of this
+                // launch left it; its padding words never change
+                R.c[12] = s_word[to];
+                if (wo > 0) R.l[12] = s_word[to - 1];
+                if (wo < nwin - 1) R.r[12] = s_word[to + 1];
+                Co = R.c[12];
+                make_windows(R, Wn);
+            }
+            const double S = stencil_sum(sc, Wn, b);
+            const double phi = ((Co >> b) & 1u) ? 1.0 : -1.0;
+            const double hU =
+                ph.h3 * (cell_value(cf.ulj, cf.f32, c) + cell_value(cf.ucfa, cf.f32, c));
+            const double cS = sc.c * S;
+            const double dE = phi * (cS - hU);
+            const double tol = ph.h3 * cell_value(cf.bound, cf.f32, c) + 4.0e-16 * (fabs(cS) + fabs(hU));
+            if (!(fabs(dE) > tol)) {
+                const int b0o = ((ca - 32 * wo) % P + P) % P;
+                s_cs[((b - b0o) / P) * FWG + to] = cS;
+                atomicOr(&s_tm[to], 1u << b);
+            } else if (dE < 0.0) {
+                atomicOr(&s_fm[to], 1u << b);
+            }
+        }
+        __syncthreads();
+        uint32_t flipmask = s_fm[t], tiemask = s_tm[t];
+        const int b0 = ((ca - x0) % P + P) % P;
+        while (__syncthreads_or(tiemask != 0u)) {
+            if (t == 0) s_leader = FWG;
+            __syncthreads();
+            if (tiemask) atomicMin(&s_leader, t);
+            __syncthreads();
+            const int leader = s_leader;
+            if (t == leader) {
+                s_tie[0] = __ffs(tiemask) - 1;
+                s_tie[1] = y;
+                s_tie[2] = z;
+                s_tie[3] = x0;
+            }
+            __syncthreads();
+            const int bL = s_tie[0], yL = s_tie[1], zL = s_tie[2], xL = s_tie[3] + bL;
+            const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
+            double lj = u64cache[cL], cfa = u64cache[g.ncell() + cL];
+            if (isnan(lj)) {  // same value for every thread
+                block_density_f64<8>(g, a, ph, xL, yL, zL, s_red, lj, cfa);
+                if (t == leader) {
+                    u64cache[cL] = lj;
+                    u64cache[g.ncell() + cL] = cfa;
+                    atomicAdd((unsigned long long*)&counters[1], 1ull);
+                }
+            }
+            if (t == leader) {
+                const double cS = s_cs[((bL - b0) / P) * FWG + t];
+                const double phi = ((C >> bL) & 1u) ? 1.0 : -1.0;
+                const double dE = phi * (cS - ph.h3 * (lj + cfa));
+                if (dE < 0.0) flipmask |= 1u << bL;
+                tiemask &= ~(1u << bL);
+                atomicAdd((unsigned long long*)&counters[0], 1ull);
+            }
+        }
+        if (flipmask) {
+            C ^= flipmask;
+            s_word[t] = C;
+            nflips += __popc(flipmask);
+            last = gpass;
+            // the row's own words that this flip stamps (w - 1 .. w + 1)
+            atomicMax(&s_stw[t], gpass);
+            if (w > 0) atomicMax(&s_stw[t - 1], gpass);
+            if (w < nwin - 1) atomicMax(&s_stw[t + 1], gpass);
+        }
+    }
+    if (last >= 0) {
+        rowc[w + 1] = C;
+        for (int dz = -2; dz <= 2; ++dz)
+            for (int dy = -2; dy <= 2; ++dy) {
+                int* sr = stamp + g.row(y + dy, z + dz) + w;
+                atomicMax(&sr[0], last);
+                atomicMax(&sr[1], last);
+                atomicMax(&sr[2], last);
+            }
+    }
+    int nf = nflips;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nf += __shfl_xor(nf, off);
+    if (lane == 0 && nf) atomicAdd(&sweep_flips[sweep], nf);
+}
+
 // FP64 density parts of one cell into the near-tie cache (u64cache: LJ,
 // then CFA), by one workgroup: the value the colour passes compute for a
 // near tie, for the serial schedule's near ties.
@@ -734,6 +950,33 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
                            nullptr, nullptr, nullptr, colour, sweep, gpass, 27, xb);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_group3(const Grid& g, const Stencil& sc, const Atoms& a, const Physics& ph,
+                              int group, int sweep, int gpass0, uint32_t* bits, int* stamp,
+                              const CellFields& f, double* u64cache, int* sweep_flips,
+                              int64_t* counters, hipStream_t st) {
+    if (sc.p != 3 || group < 0 || group >= 9 || g.nwin > FWG) return hipErrorInvalidValue;
+    const int cb = group % 3, cc = group / 3;
+    const int64_t ny = (g.n - cb + 2) / 3, nz = (g.n - cc + 2) / 3;
+    const int64_t nrows = ny * nz;
+    if (nrows <= 0) return hipSuccess;
+    MolDesc d{};
+    d.g = g;
+    d.sc = sc;
+    d.a = a;
+    d.ph = ph;
+    d.f = f;
+    d.bits = bits;
+    d.stamp = stamp;
+    d.u64cache = u64cache;
+    d.sweep_flips = sweep_flips;
+    d.counters = counters;
+    const int64_t rpw = FWG / g.nwin;
+    const int64_t xb = (nblk(nrows, rpw) + NXCD - 1) / NXCD;  // logical blocks per die
+    hipLaunchKernelGGL(flip_group3_kernel, dim3((unsigned)(xb * NXCD)), dim3(FWG), 0, st, d, cb,
+                       cc, sweep, gpass0, 27, xb);
     return hipGetLastError();
 }
 
