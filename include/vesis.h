@@ -215,8 +215,10 @@ vesis_status vesis_init_labels(vesis_ctx* ctx, int32_t mode, double param, const
  * p = ceil(rho_s), in order; within a colour every band cell whose energy
  * change is negative flips (cells of one colour do not interact).  Stops
  * after a sweep with no flip (VESIS_OK) or after max_sweeps sweeps
- * (VESIS_NOT_CONVERGED; calling again resumes).  Recomputes the density
- * first if the atoms moved.  out may be NULL. */
+ * (VESIS_NOT_CONVERGED; calling again resumes).  With p = 3 the three
+ * colours that share their rows run in one launch, with the result of the
+ * sequence.  Recomputes the density first if the atoms moved.  out may be
+ * NULL. */
 vesis_status vesis_minimize_interface(vesis_ctx* ctx, int32_t max_sweeps, vesis_min_stats* out);
 
 /* Relax the interface at fixed atoms by the paper's serial flipping process
@@ -313,9 +315,12 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
 /* Autotune the batch's launch shapes.  Times each density tiling d (0: two
  * cells per lane on 16x8x4 bricks; 1: one cell per lane on 16x8x2 bricks;
  * 2: four cells per lane on 16x8x8 bricks) on the batch, and, when every
- * molecule has labels, one sweep of colour passes with each register
- * variant f (0: the compiler's allocation; 1: capped for four wavefronts
- * per SIMD) from the current labels, which are put back afterwards.
+ * molecule has labels, one sweep of colour passes with each colour-pass
+ * variant f from the current labels, which are put back afterwards: with
+ * colour period 3, f = 0 runs the three colours that share their rows in
+ * one launch and f = 1 one launch per colour (registers capped for four
+ * wavefronts per SIMD); with period 2, one launch per colour with the
+ * compiler's register allocation (f = 0) or the cap (f = 1).
  * *best = d + 3 f of the fastest of each (f = 0 when not timed), the value
  * vesis_minimize_batch takes as `variant`; ms (may be NULL, 5 entries)
  * receives the density times (ms[d]) and the sweep times (ms[3 + f], -1

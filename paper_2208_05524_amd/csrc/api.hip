@@ -1459,7 +1459,7 @@ void batch_blocks(vesis_ctx* const* c, int m, int64_t& dens, int64_t& flip, int6
     // than the even share)
     int64_t most = 0;
     for (int i = 0; i < m; ++i) {
-        const int64_t nb = flip_slots(c[i]->g, c[i]->sc.p) / FLIP_WG;
+        const int64_t nb = flip_blocks(c[i]->g, c[i]->sc.p);
         flip += nb;
         most = std::max(most, nb);
     }
@@ -1643,7 +1643,7 @@ int64_t batch_pass_tables(vesis_ctx* ctx, vesis_ctx* const* ctxs, int m, char* b
     for (int i = 0; i < m; ++i) {
         desc[i] = mol_desc(ctxs[i]);
         desc[i].slot0 = 0;
-        nbm[i] = flip_slots(ctxs[i]->g, p) / FLIP_WG;
+        nbm[i] = flip_blocks(ctxs[i]->g, p);
         order[i] = i;
         max_words = std::max(max_words, ctxs[i]->g.nwords());
     }
@@ -1665,6 +1665,26 @@ int64_t batch_pass_tables(vesis_ctx* ctx, vesis_ctx* const* ctxs, int m, char* b
     (void)hipMemcpyAsync(b + L.desc, desc, sizeof(MolDesc) * m, hipMemcpyHostToDevice, ctx->stream);
     (void)hipMemcpyAsync(b + L.fmap, map, 4 * (size_t)nmap, hipMemcpyHostToDevice, ctx->stream);
     return nmap;
+}
+
+// One sweep of colour passes over a batch.  Colour-pass variant 0 with
+// colour period 3 runs the colours that share their rows three to a launch
+// (launch_flip_group3_batch); otherwise one launch per colour, variant v
+// selecting the register budget of flip_pass_kernel.
+hipError_t launch_batch_sweep(const MolDesc* ddesc, const int* dmap, const int* ddone, const int* dpass,
+                              int64_t nblocks, int p, int sw, int fvar, hipStream_t st) {
+    const int ncol = p * p * p;
+    hipError_t e = hipSuccess;
+    if (p == 3 && fvar == 0) {
+        for (int grp = 0; grp < 9 && e == hipSuccess; ++grp)
+            e = launch_flip_group3_batch(ddesc, dmap, ddone, dpass, nblocks, grp, sw,
+                                         sw * ncol + 3 * grp, st);
+        return e;
+    }
+    for (int c = 0; c < ncol && e == hipSuccess; ++c)
+        e = launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, sw, sw * ncol + c,
+                                   fvar, st);
+    return e;
 }
 
 vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size_t bytes,
@@ -1718,7 +1738,7 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
     int fbest = 0;
     for (int v = 0; v < FLIP_VARIANTS && ms; ++v) ms[DENSITY_VARIANTS + v] = -1.0;
     if (labelled) {
-        const int p = ctx->sc.p, ncol = p * p * p;
+        const int p = ctx->sc.p;
         int64_t max_words = 0;
         MolDesc* desc = nullptr;
         const int64_t nblocks = batch_pass_tables(ctx, ctxs, m, b, L, S, max_words, desc);
@@ -1738,9 +1758,7 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
                 CK(launch_fill_u32(reinterpret_cast<uint32_t*>(dpass), 1, 0u, st));
                 CK(launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, st));
                 CK(hipEventRecord(e0, st));
-                for (int c = 0; c < ncol; ++c)
-                    CK(launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, 0, c, v,
-                                              st));
+                CK(launch_batch_sweep(ddesc, dmap, ddone, dpass, nblocks, p, 0, v, st));
                 CK(hipEventRecord(e1, st));
                 float t = 0.f;
                 CK(elapsed(t));
@@ -1823,9 +1841,7 @@ vesis_status vesis_minimize_batch(vesis_ctx* const* ctxs, int32_t m, void* bws, 
     auto enqueue_group = [&](hipStream_t s2, int nb) -> hipError_t {
         hipError_t e = launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, s2);
         for (int sw = 0; sw < nb && e == hipSuccess; ++sw)
-            for (int c = 0; c < ncol && e == hipSuccess; ++c)
-                e = launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, sw,
-                                           sw * ncol + c, fvar, s2);
+            e = launch_batch_sweep(ddesc, dmap, ddone, dpass, nblocks, p, sw, fvar, s2);
         if (e == hipSuccess) e = launch_batch_end_group(ddesc, m, nb, ncol, ddone, dpass, s2);
         if (e == hipSuccess) e = launch_batch_gather_flips(ddesc, m, SWEEP_BATCH, dflips, s2);
         return e;

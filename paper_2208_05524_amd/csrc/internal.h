@@ -189,6 +189,15 @@ constexpr int FLIP_WG = 256;
 constexpr int BATCH_MOL_BITS = 12;
 constexpr int BATCH_MOLS = 1 << BATCH_MOL_BITS;  // molecules a batch may hold
 int64_t flip_slots(const Grid& g, int p);
+// Workgroups per molecule of the batched passes' block map: enough for the
+// single-colour passes (flip_slots / FLIP_WG) and, with colour period 3, for
+// the three-colour launches (whole rows per workgroup).
+int64_t flip_blocks(const Grid& g, int p);
+// The three-colour launch of launch_flip_group3 over a batch (block map as
+// for launch_flip_pass_batch, built with flip_blocks).
+hipError_t launch_flip_group3_batch(const MolDesc* descs, const int* block_mol, const int* done,
+                                    const int* pass_base, int64_t nblocks, int group, int sweep,
+                                    int gpass_off, hipStream_t st);
 // done[k] != 0 skips molecule k; the pass index is *pass_base + gpass_off.
 // variant: 0 = registers at the compiler's choice, 1 = capped for four
 // wavefronts per SIMD (the same arithmetic, so the same labels).

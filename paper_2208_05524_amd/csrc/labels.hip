@@ -17,6 +17,7 @@
 // strided share of the atoms, fixed tree sum), caches it, and decides.
 // Cells of one colour lie outside each other's kernel support, so all
 // decisions of a pass read only labels that the pass does not change.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -494,8 +495,13 @@ __global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 // word's stamp is the pass of the latest flip in its neighbourhood, written
 // with atomicMax at the end (within the launch only the row's own words can
 // be stamped, and those stamps are tracked in LDS).
-__global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, int cb, int cc, int sweep,
-                                                          int gpass0, int ncol,
+// BATCH as for flip_pass_kernel: workgroup b takes entry block_mol[b] of
+// `descs` (a molecule and a logical block of its rows).
+template <bool BATCH>
+__global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, const MolDesc* descs,
+                                                          const int* block_mol, const int* done,
+                                                          const int* pass_base, int cb, int cc,
+                                                          int sweep, int gpass0, int ncol,
                                                           int64_t xcd_blocks) {
     constexpr int P = 3, K = 11;
     __shared__ double s_red[4 * FWG];
@@ -508,7 +514,17 @@ __global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, int cb, i
     __shared__ int s_stw[FWG];        // its stamp, with this launch's flips in the row
     __shared__ int s_leader;
     __shared__ int s_tie[4];
-    const MolDesc& D = one;
+    int mol = 0;
+    int64_t lblock = flip_block_of(blockIdx.x, xcd_blocks);
+    if (BATCH) {
+        const int ent = block_mol[blockIdx.x];
+        if (ent < 0) return;  // padding at the end of a shorter XCD's list
+        mol = ent & (BATCH_MOLS - 1);
+        lblock = ent >> BATCH_MOL_BITS;
+        if (done[mol]) return;
+        gpass0 += *pass_base;
+    }
+    const MolDesc& D = BATCH ? descs[mol] : one;
     const Grid& g = D.g;
     const Stencil& sc = D.sc;
     const Atoms& a = D.a;
@@ -524,7 +540,6 @@ __global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, int cb, i
     const int rpw = FWG / nwin;  // whole rows per workgroup
     const int ny = (g.n - cb + P - 1) / P, nz = (g.n - cc + P - 1) / P;
     const int64_t nrows = (int64_t)ny * nz;
-    const int64_t lblock = flip_block_of(blockIdx.x, xcd_blocks);
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int rl = t / nwin, w = t - rl * nwin;
@@ -654,7 +669,7 @@ __global__ __launch_bounds__(FWG) void flip_group3_kernel(MolDesc one, int cb, i
             const int64_t cL = (int64_t)xL + (int64_t)g.n * (yL + (int64_t)g.n * zL);
             double lj = u64cache[cL], cfa = u64cache[g.ncell() + cL];
             if (isnan(lj)) {  // same value for every thread
-                block_density_f64<8>(g, a, ph, xL, yL, zL, s_red, lj, cfa);
+                block_density_f64<BATCH ? 2 : 8>(g, a, ph, xL, yL, zL, s_red, lj, cfa);
                 if (t == leader) {
                     u64cache[cL] = lj;
                     u64cache[g.ncell() + cL] = cfa;
@@ -975,9 +990,30 @@ hipError_t launch_flip_group3(const Grid& g, const Stencil& sc, const Atoms& a, 
     d.counters = counters;
     const int64_t rpw = FWG / g.nwin;
     const int64_t xb = (nblk(nrows, rpw) + NXCD - 1) / NXCD;  // logical blocks per die
-    hipLaunchKernelGGL(flip_group3_kernel, dim3((unsigned)(xb * NXCD)), dim3(FWG), 0, st, d, cb,
-                       cc, sweep, gpass0, 27, xb);
+    hipLaunchKernelGGL(flip_group3_kernel<false>, dim3((unsigned)(xb * NXCD)), dim3(FWG), 0, st, d,
+                       nullptr, nullptr, nullptr, nullptr, cb, cc, sweep, gpass0, 27, xb);
     return hipGetLastError();
+}
+
+hipError_t launch_flip_group3_batch(const MolDesc* descs, const int* block_mol, const int* done,
+                                    const int* pass_base, int64_t nblocks, int group, int sweep,
+                                    int gpass_off, hipStream_t st) {
+    if (group < 0 || group >= 9) return hipErrorInvalidValue;
+    if (nblocks <= 0) return hipSuccess;
+    MolDesc unused{};
+    hipLaunchKernelGGL(flip_group3_kernel<true>, dim3((unsigned)nblocks), dim3(FWG), 0, st, unused,
+                       descs, block_mol, done, pass_base, group % 3, group / 3, sweep, gpass_off,
+                       27, (int64_t)0);
+    return hipGetLastError();
+}
+
+int64_t flip_blocks(const Grid& g, int p) {
+    int64_t nb = flip_slots(g, p) / FWG;
+    if (p == 3 && g.nwin <= FWG) {
+        const int64_t ny = (g.n + 2) / 3, rpw = FWG / g.nwin;
+        nb = std::max(nb, (ny * ny + rpw - 1) / rpw);
+    }
+    return nb;
 }
 
 static_assert(FWG == FLIP_WG, "flip-pass workgroup size");
