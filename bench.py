@@ -64,11 +64,12 @@ def measured_traffic(kernel: str = "density_grid_f32"):
     return None
 
 
-def measured_flip_traffic():
-    """HBM traffic of the batched colour pass on the 64-molecule workload
-    from the committed PMC summary: the profiled register variant, bytes per
-    dispatch, average dispatch time and their ratio against 8 TB/s, or None
-    when the colour-pass source has changed since the counters were taken."""
+def measured_flip_traffic(colour_variant: int = 0):
+    """HBM traffic of the batched colour-pass launch of the given colour-pass
+    variant on the 64-molecule workload, from the committed PMC summary: the
+    kernel, bytes per dispatch, average dispatch time and their ratio against
+    8 TB/s, or None when the colour-pass source has changed since the
+    counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_batch64_flip.md")
     src = os.path.join(ROOT, "paper_2208_05524_amd", "csrc", "labels.hip")
@@ -81,6 +82,8 @@ def measured_flip_traffic():
         f = ln.split()
         if len(f) > 2 and f[0] == "traffic" and f[1] == "flip_pass_batch":
             kv = dict(x.split("=", 1) for x in f[2:])
+            if int(kv.get("variant", "-1")) != colour_variant:
+                continue
             if kv.get("source_sha256") != sha:
                 return None
             b, us = float(kv["bytes_per_dispatch"]), float(kv["avg_us"])
@@ -88,6 +91,44 @@ def measured_flip_traffic():
             return {"kernel": kv.get("kernel"), "bytes_per_dispatch": b, "avg_us": us,
                     "GB_per_s": gbs, "frac_of_8TBs": gbs / 8000.0}
     return None
+
+
+def colour_variant_runs(rounds: int = 3):
+    """The 64-molecule batch relaxed from the tight start with each
+    colour-pass variant (density tiling 0), rounds times each: the time per
+    relaxation and whether the labels agree between the variants."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_05524_amd import Batch, Context
+
+    ws = synth.batch_conformations()
+    ctxs = []
+    for w in ws:
+        c = Context(0)
+        c.setup(w, precision=32)
+        ctxs.append(c)
+    b = Batch(ctxs)
+    out, labels = {}, []
+    for f in range(Batch.FLIP_VARIANTS):
+        ms = []
+        for r in range(rounds):
+            for w, c in zip(ws, ctxs):
+                c.set_positions(w.xyz)
+                c.init_labels("tight", 1.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.minimize(variant=Batch.DENSITY_VARIANTS * f)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        out[f"colour_variant_{f}_ms"] = ms
+        labels.append([c.labels() for c in ctxs])
+    out["labels_identical"] = all(all(np.array_equal(a, x) for a, x in zip(labels[0], l))
+                                  for l in labels[1:])
+    for c in ctxs:
+        c.close()
+    return out
 
 
 def batch_comparison(rounds: int = 2):
@@ -167,8 +208,8 @@ def batch_comparison(rounds: int = 2):
            "variant": {"code": best, "density_tiling": best % Batch.DENSITY_VARIANTS,
                        "colour_pass": best // Batch.DENSITY_VARIANTS},
            "tune_ms": {"density_tilings": tune_ms[:Batch.DENSITY_VARIANTS],
-                       "one_sweep_per_colour_pass_variant": tune_ms[Batch.DENSITY_VARIANTS:]},
-           "flip_pass_hbm": measured_flip_traffic(),
+                       "four_sweeps_per_colour_pass_variant": tune_ms[Batch.DENSITY_VARIANTS:]},
+           "flip_pass_hbm": measured_flip_traffic(best // Batch.DENSITY_VARIANTS),
            "sweeps_max": max(x["sweeps"] for x in st), "converged": rc == 0,
            "labels_identical": bool(same), "max_rel_dG": rel}
     for c in ctxs:
@@ -386,7 +427,13 @@ def main():
                          "runs that should see the two-globule kernels only)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--colour-variants", action="store_true",
+                    help="only relax the 64-molecule batch with each colour-pass variant "
+                         "(counter runs of the batched colour passes)")
     args = ap.parse_args()
+    if args.colour_variants:
+        print(json.dumps(colour_variant_runs()), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

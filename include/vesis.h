@@ -315,8 +315,9 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
 /* Autotune the batch's launch shapes.  Times each density tiling d (0: two
  * cells per lane on 16x8x4 bricks; 1: one cell per lane on 16x8x2 bricks;
  * 2: four cells per lane on 16x8x8 bricks) on the batch, and, when every
- * molecule has labels, one sweep of colour passes with each colour-pass
- * variant f from the current labels, which are put back afterwards: with
+ * molecule has labels, the first four sweeps of colour passes with each
+ * colour-pass variant f from the current labels, which are put back
+ * afterwards: with
  * colour period 3, f = 0 runs the three colours that share their rows in
  * one launch and f = 1 one launch per colour (registers capped for four
  * wavefronts per SIMD); with period 2, one launch per colour with the

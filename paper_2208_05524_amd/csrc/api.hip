@@ -1671,6 +1671,9 @@ int64_t batch_pass_tables(vesis_ctx* ctx, vesis_ctx* const* ctxs, int m, char* b
 // colour period 3 runs the colours that share their rows three to a launch
 // (launch_flip_group3_batch); otherwise one launch per colour, variant v
 // selecting the register budget of flip_pass_kernel.
+constexpr int TUNE_SWEEPS = 4;  // colour-pass sweeps the tuner times
+static_assert(TUNE_SWEEPS <= SWEEP_BATCH, "the sweep flip counts the tuner clears");
+
 hipError_t launch_batch_sweep(const MolDesc* ddesc, const int* dmap, const int* ddone, const int* dpass,
                               int64_t nblocks, int p, int sw, int fvar, hipStream_t st) {
     const int ncol = p * p * p;
@@ -1729,8 +1732,8 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
             dbest = v;
         }
     }
-    // colour-pass register variants: one sweep of every colour over the
-    // batch from its current labels, which are saved first and put back
+    // colour-pass variants: the first TUNE_SWEEPS sweeps over the batch
+    // from its current labels, which are saved first and put back
     // after each run (in each molecule's force staging scratch, which no
     // result depends on between calls).  Needs labels on every molecule.
     bool labelled = s == VESIS_OK;
@@ -1758,7 +1761,10 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
                 CK(launch_fill_u32(reinterpret_cast<uint32_t*>(dpass), 1, 0u, st));
                 CK(launch_batch_clear_flips(ddesc, m, SWEEP_BATCH, st));
                 CK(hipEventRecord(e0, st));
-                CK(launch_batch_sweep(ddesc, dmap, ddone, dpass, nblocks, p, 0, v, st));
+                // the first sweeps from the start: the first, where every
+                // band cell is a candidate, and the lighter ones after it
+                for (int sw = 0; sw < TUNE_SWEEPS; ++sw)
+                    CK(launch_batch_sweep(ddesc, dmap, ddone, dpass, nblocks, p, sw, v, st));
                 CK(hipEventRecord(e1, st));
                 float t = 0.f;
                 CK(elapsed(t));
