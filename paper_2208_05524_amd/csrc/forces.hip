@@ -11,17 +11,24 @@
 // r2_min floor the LJ part is constant and E_n = Q_n d / r_min^3.
 //
 // Layout.  A staging kernel first compacts, per chunk of cells (a cubic
-// 16^3 brick of the grid, or a run of 4096 far-field nodes), the cells with
-// nonzero weight in cell order, as (position relative to the chunk centre,
-// w) and w E in the working precision (for grid cells w = 1: their common
-// weight h^3 multiplies the sums of each tile instead, which saves a
-// multiply per pair); it writes the count per chunk.  The
+// 16^3 brick of the grid, or a run of 4096 far-field nodes), what the force
+// sum visits, in the working precision.  A grid chunk keeps its x-rows of 16
+// cells that hold at least one solvent cell, in row order: per row its
+// (y, z) relative to the chunk centre, per cell (x relative to the centre,
+// E); a solute cell of a kept row is staged at x = BIG with E = 0, where
+// every term of the pair underflows to exactly zero (the weight h^3 common
+// to grid cells multiplies the sums of each tile instead).  Far-field nodes
+// are compacted one by one as (position, w) and w E.  The
 // force kernel gives a workgroup 512 atoms (two per lane: every cell read
-// from LDS serves two pairs, which halves the LDS traffic that bounds the
-// loop) and a group of consecutive chunks; the staged cells of each chunk stream through a
-// double-buffered LDS tile of 256 (the next tile is fetched into registers
-// while the current one is summed, one barrier per tile) and are read by
-// broadcast.  Every lane keeps FP32 partials per tile, folded into FP64.  Per
+// from LDS serves two pairs, which halves the LDS traffic) and a group of
+// consecutive chunks; the staged data of each chunk stream through a
+// double-buffered LDS tile of 32 rows or 256 nodes (the next tile is fetched
+// into registers while the current one is summed, one barrier per tile) and
+// are read by broadcast.  The cells of a row share dy, dz and dy^2 + dz^2
+// with an atom, and the y and z parts of the sum along d are the row's
+// coefficient sum times dy and dz, so a grid pair costs about 20 VALU
+// instructions against 24 for a node.  Every lane keeps FP32 partials per
+// tile, folded into FP64.  Per
 // pair the LJ term and the (E.d) d part of the CFA term share one
 // coefficient along d; the E/r^3 part is summed separately.  The r2_min
 // floor can only bind for an atom within the chunk's extent (plus a margin):
@@ -37,9 +44,13 @@ namespace {
 
 constexpr int AWG = 256;        // lanes per workgroup
 constexpr int APL = 2;          // atoms per lane
-constexpr int CT = 256;         // staged cells per LDS tile
+constexpr int CT = 256;         // staged far-field nodes per LDS tile
 constexpr int CB = 16;          // grid chunk edge (cells)
 constexpr int CB3 = CB * CB * CB;
+constexpr int RT = 2 * CT / CB; // staged grid rows per LDS tile (same LDS as CT nodes)
+static_assert(CB * CB == 256, "the staging kernel gives one thread each row of a chunk");
+static_assert(AWG == CT, "a force workgroup loads one tile unit per thread");
+static_assert(CB <= 16 && 32 % CB == 0, "a chunk row lies within one label word");
 constexpr int FAR_CHUNK = 4096; // far-field nodes per chunk
 constexpr int GROUP = 4;        // chunks per force workgroup
 constexpr int RSPLIT = 8;       // group slices per atom in the reduction
@@ -51,7 +62,8 @@ struct ChunkPlan {
     int64_t nfar_chunks;  // far-field chunks
     int64_t nchunks() const { return ngrid + nfar_chunks; }
     int64_t ngroups() const { return (nchunks() + GROUP - 1) / GROUP; }
-    // staged slots (each slot is two 4-vectors)
+    // staged slots (each slot is two 4-vectors; a grid chunk's cells fill
+    // the first CB3 4-vectors of its 2 CB3, its rows' (y, z) the rest)
     int64_t slots() const { return ngrid * CB3 + nfar_chunks * FAR_CHUNK; }
 };
 
@@ -80,17 +92,29 @@ struct ForceArgs {
     int64_t ngrid;        // grid chunks
     int64_t nchunks;      // grid + far chunks
     void* staged;         // [slot][2] 4-vectors of the working precision
-    int* count;           // staged cells per chunk
+    int* count;           // staged rows (grid chunk) or nodes (far chunk)
     double* partial;      // [group][atom][3]
 };
 
 template <typename T>
 struct V4 {};
 template <>
-struct V4<float> { using type = float4; };
+struct V4<float> {
+    using type = float4;
+    using half = float2;
+    // |d| at which r^-3 (hence every term but the r^-3-times-zero-field
+    // ones) underflows to exactly zero in this precision
+    static constexpr float BIG = 1e18f;
+};
 template <>
-struct V4<double> { using type = double4; };
+struct V4<double> {
+    using type = double4;
+    using half = double2;
+    static constexpr double BIG = 1e110;
+};
 
+__device__ inline float2 mk2(float a, float b) { return make_float2(a, b); }
+__device__ inline double2 mk2(double a, double b) { return make_double2(a, b); }
 __device__ inline float4 mk4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
 __device__ inline double4 mk4(double a, double b, double c, double d) {
     return make_double4(a, b, c, d);
@@ -124,59 +148,83 @@ __device__ inline void chunk_origin(const ForceArgs& f, int64_t chunk, double& o
     }
 }
 
-// One workgroup per chunk: compact the cells with nonzero weight in cell order.
+// One workgroup per chunk.  Grid chunk: its x-rows with a solvent cell, in
+// row order (one thread per row finds them, then 16 threads per row write
+// the row's cells).  Far chunk: its nodes in order.
 template <typename T>
 __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
     using T4 = typename V4<T>::type;
+    using T2 = typename V4<T>::half;
     __shared__ int wcnt[4];
     __shared__ int run;
+    __shared__ uint32_t s_seg[CB * CB];
+    __shared__ int s_row[CB * CB];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t chunk = blockIdx.x;
     const Grid& g = f.g;
     T4* out = static_cast<T4*>(f.staged) + 2 * chunk_slot0(f, chunk);
-    const bool is_grid = chunk < f.ngrid;
-    int ci = 0, cj = 0, ck = 0;
-    int64_t far0 = 0, ncells;
+    if (chunk < f.ngrid) {
+        const int ci = (int)(chunk % f.ncx), cj = (int)((chunk / f.ncx) % f.ncx),
+                  ck = (int)(chunk / ((int64_t)f.ncx * f.ncx));
+        const int x0 = ci * CB;
+        const int ly = t % CB, lz = t / CB, y = cj * CB + ly, z = ck * CB + lz;
+        uint32_t seg = 0;  // solvent bits of the row's cells
+        if (y < g.n && z < g.n) {
+            const uint32_t word = f.bits[g.row(y, z) + 1 + (x0 >> 5)];
+            seg = (word >> (x0 & 31)) & ((1u << CB) - 1u);
+            if (g.n - x0 < CB) seg &= (1u << (g.n - x0)) - 1u;
+        }
+        const bool keep = seg != 0;
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int k = __popcll(bal & ((1ull << lane) - 1ull)), nrows = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            k += (v < wv) ? wcnt[v] : 0;
+            nrows += wcnt[v];
+        }
+        T2* rowpos = reinterpret_cast<T2*>(out + CB3);
+        if (keep) {
+            s_seg[k] = seg;
+            s_row[k] = t;
+            rowpos[k] = mk2((T)((ly - 0.5 * (CB - 1)) * g.h), (T)((lz - 0.5 * (CB - 1)) * g.h));
+        }
+        __syncthreads();
+        const int lx = t % CB;
+        const T xrel = (T)((lx - 0.5 * (CB - 1)) * g.h);
+        for (int k0 = 0; k0 < nrows; k0 += 256 / CB) {
+            const int kr = k0 + t / CB;
+            if (kr >= nrows) break;
+            T4 e = mk4(V4<T>::BIG, (T)0, (T)0, (T)0);
+            if ((s_seg[kr] >> lx) & 1u) {
+                const int r = s_row[kr];
+                const int64_t c = (int64_t)(x0 + lx) +
+                                  (int64_t)g.n * (cj * CB + r % CB + (int64_t)g.n * (ck * CB + r / CB));
+                e = mk4(xrel, static_cast<const T*>(f.ex)[c], static_cast<const T*>(f.ey)[c],
+                        static_cast<const T*>(f.ez)[c]);
+            }
+            out[kr * CB + lx] = e;
+        }
+        if (t == 0) f.count[chunk] = nrows;
+        return;
+    }
     double ox, oy, oz;
     chunk_origin(f, chunk, ox, oy, oz);
-    if (is_grid) {
-        ci = (int)(chunk % f.ncx);
-        cj = (int)((chunk / f.ncx) % f.ncx);
-        ck = (int)(chunk / ((int64_t)f.ncx * f.ncx));
-        ncells = CB3;
-    } else {
-        far0 = (chunk - f.ngrid) * FAR_CHUNK;
-        ncells = f.nfar - far0 < FAR_CHUNK ? f.nfar - far0 : FAR_CHUNK;
-    }
+    const int64_t far0 = (chunk - f.ngrid) * FAR_CHUNK;
+    const int64_t ncells = f.nfar - far0 < FAR_CHUNK ? f.nfar - far0 : FAR_CHUNK;
     if (t == 0) run = 0;
     for (int64_t base = 0; base < ncells; base += 256) {
         const int64_t li = base + t;
         T4 a = mk4((T)0, (T)0, (T)0, (T)0), b = a;
         bool keep = false;
         if (li < ncells) {
-            if (is_grid) {
-                const int lx = (int)(li % CB), ly = (int)((li / CB) % CB), lz = (int)(li / (CB * CB));
-                const int x = ci * CB + lx, y = cj * CB + ly, z = ck * CB + lz;
-                if (x < g.n && y < g.n && z < g.n) {
-                    const uint32_t word = f.bits[g.row(y, z) + 1 + (x >> 5)];
-                    if ((word >> (x & 31)) & 1u) {
-                        // weight h^3 left out: applied to the sums of the tile
-                        const int64_t c = (int64_t)x + (int64_t)g.n * (y + (int64_t)g.n * z);
-                        a = mk4((T)((lx - 0.5 * (CB - 1)) * g.h), (T)((ly - 0.5 * (CB - 1)) * g.h),
-                                (T)((lz - 0.5 * (CB - 1)) * g.h), (T)1);
-                        b = mk4(static_cast<const T*>(f.ex)[c], static_cast<const T*>(f.ey)[c],
-                                static_cast<const T*>(f.ez)[c], (T)0);
-                        keep = true;
-                    }
-                }
-            } else {
-                const int64_t pidx = far0 + li;
-                const double4 p = f.far_pts[pidx];
-                a = mk4((T)(p.x - ox), (T)(p.y - oy), (T)(p.z - oz), (T)p.w);
-                b = mk4((T)(p.w * f.far_ex[pidx]), (T)(p.w * f.far_ey[pidx]),
-                        (T)(p.w * f.far_ez[pidx]), (T)0);
-                keep = true;
-            }
+            const int64_t pidx = far0 + li;
+            const double4 p = f.far_pts[pidx];
+            a = mk4((T)(p.x - ox), (T)(p.y - oy), (T)(p.z - oz), (T)p.w);
+            b = mk4((T)(p.w * f.far_ex[pidx]), (T)(p.w * f.far_ey[pidx]),
+                    (T)(p.w * f.far_ez[pidx]), (T)0);
+            keep = true;
         }
         const uint64_t bal = __ballot(keep);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
@@ -184,9 +232,9 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
         __syncthreads();
         int off = run, tot = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            off += (k < wv) ? wcnt[k] : 0;
-            tot += wcnt[k];
+        for (int v = 0; v < 4; ++v) {
+            off += (v < wv) ? wcnt[v] : 0;
+            tot += wcnt[v];
         }
         if (keep) {
             out[2 * (off + before)] = a;
@@ -199,18 +247,18 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
     if (t == 0) f.count[chunk] = run;
 }
 
-// Pairs of one staged tile for the APL atoms of a lane: each staged cell is
-// read from LDS once and serves APL pairs (the LDS, not the VALU, bounds a
-// loop with one pair per read).  FLOOR: apply the r2_min floor (only needed
-// when an atom of the wave may lie within sqrt(r2_min) of a cell of the
-// chunk).  With c1 = 48 rho_w eps sigma^12 and c2 = 24 rho_w eps sigma^6 the
-// LJ part of the coefficient along d is w r^-8 (c1 r^-6 - c2) and the CFA
-// part -k3 (wE.d) r^-5, so the coefficient is r^-5 [w r^-3 (c1 r^-6 - c2) -
-// k3 (wE.d)] (powers from r^-1: r^-2, r^-3, r^-5 = r^-2 r^-3, r^-6 =
-// (r^-3)^2).  UNIT_W: the staged weights are all 1 (grid cells, whose
-// common weight h^3 is applied to the tile's sums instead).
-template <typename T, bool FLOOR, bool UNIT_W>
-__device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int cnt,
+// Pairs of one staged tile for the APL atoms of a lane: each staged cell or
+// node is read from LDS once and serves APL pairs.  With c1 = 48 rho_w eps
+// sigma^12 and c2 = 24 rho_w eps sigma^6 the LJ part of the coefficient
+// along d is w r^-8 (c1 r^-6 - c2) and the CFA part -k3 (wE.d) r^-5, so the
+// coefficient is r^-5 [w r^-3 (c1 r^-6 - c2) - k3 (wE.d)] (powers from
+// r^-1: r^-2, r^-3, r^-5 = r^-2 r^-3, r^-6 = (r^-3)^2).  FLOOR: apply the
+// r2_min floor (only needed when an atom of the wave may lie within
+// sqrt(r2_min) of a cell of the chunk).
+//
+// Far-field nodes: (position, w) and w E per node.
+template <typename T>
+__device__ __forceinline__ void tile_nodes(const typename V4<T>::type* sc, int cnt,
                                            const T (&ax)[APL], const T (&ay)[APL],
                                            const T (&az)[APL], const T (&c1)[APL],
                                            const T (&c2)[APL], const T (&k3)[APL], T r2min,
@@ -228,22 +276,15 @@ __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int c
         for (int q = 0; q < APL; ++q) {
             const T dx = c.x - ax[q], dy = c.y - ay[q], dz = c.z - az[q];
             const T r2 = dx * dx + dy * dy + dz * dz;
-            bool inside = false;
-            T ir;
-            if (FLOOR) {
-                inside = r2 < r2min;
-                ir = rsq<T>(inside ? r2min : r2);
-            } else {
-                ir = rsq<T>(r2);
-            }
+            const bool inside = r2 < r2min;
+            const T ir = rsq<T>(inside ? r2min : r2);
             const T ir2 = ir * ir;
             const T ir3 = ir2 * ir;
             const T ir5 = ir3 * ir2;
             const T ir6 = ir3 * ir3;
             const T ed = e.x * dx + e.y * dy + e.z * dz;
-            const T lj3 = (UNIT_W ? ir3 : c.w * ir3) * (c1[q] * ir6 - c2[q]);
-            T coef = ir5 * (lj3 - k3[q] * ed);
-            if (FLOOR) coef = inside ? (T)0 : coef;
+            const T lj3 = c.w * ir3 * (c1[q] * ir6 - c2[q]);
+            const T coef = inside ? (T)0 : ir5 * (lj3 - k3[q] * ed);
             s[q][0] += coef * dx;
             s[q][1] += coef * dy;
             s[q][2] += coef * dz;
@@ -258,10 +299,84 @@ __device__ __forceinline__ void tile_pairs(const typename V4<T>::type* sc, int c
         for (int k = 0; k < 6; ++k) acc[q][k] = s[q][k];
 }
 
+// Grid rows: (y, z) per row, (x, E) per cell, unit weight.  Per row and atom
+// dy, dz and dy^2 + dz^2 once; per pair dx, r^2 = dx^2 + (dy^2 + dz^2), the
+// coefficient, its x part and its running sum over the row, whose y and z
+// parts are taken once at the end of the row.
+template <typename T, bool FLOOR>
+__device__ __forceinline__ void tile_rows(const typename V4<T>::type* sc,
+                                          const typename V4<T>::half* rows, int nrows,
+                                          const T (&ax)[APL], const T (&ay)[APL],
+                                          const T (&az)[APL], const T (&c1)[APL],
+                                          const T (&c2)[APL], const T (&k3)[APL], T r2min,
+                                          T (&acc)[APL][6]) {
+    using T4 = typename V4<T>::type;
+    using T2 = typename V4<T>::half;
+    T s[APL][6];
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[q][k] = 0;
+    for (int r = 0; r < nrows; ++r) {
+        const T2 yz = rows[r];
+        T dy[APL], dz[APL], ryz[APL], cs[APL];
+#pragma unroll
+        for (int q = 0; q < APL; ++q) {
+            dy[q] = yz.x - ay[q];
+            dz[q] = yz.y - az[q];
+            ryz[q] = dy[q] * dy[q] + dz[q] * dz[q];
+            cs[q] = 0;
+        }
+        // two cells per iteration: the fully unrolled row (16 cells, ~1,300
+        // instructions per floor variant) ran 25 % slower than this
+#pragma unroll 2
+        for (int lx = 0; lx < CB; ++lx) {
+            const T4 c = sc[r * CB + lx];  // x, Ex, Ey, Ez
+#pragma unroll
+            for (int q = 0; q < APL; ++q) {
+                const T dx = c.x - ax[q];
+                const T r2 = dx * dx + ryz[q];
+                bool inside = false;
+                T ir;
+                if (FLOOR) {
+                    inside = r2 < r2min;
+                    ir = rsq<T>(inside ? r2min : r2);
+                } else {
+                    ir = rsq<T>(r2);
+                }
+                const T ir2 = ir * ir;
+                const T ir3 = ir2 * ir;
+                const T ir5 = ir3 * ir2;
+                const T ir6 = ir3 * ir3;
+                const T ed = c.y * dx + c.z * dy[q] + c.w * dz[q];
+                const T lj3 = ir3 * (c1[q] * ir6 - c2[q]);
+                T coef = ir5 * (lj3 - k3[q] * ed);
+                if (FLOOR) coef = inside ? (T)0 : coef;
+                s[q][0] += coef * dx;
+                cs[q] += coef;
+                s[q][3] += ir3 * c.y;
+                s[q][4] += ir3 * c.z;
+                s[q][5] += ir3 * c.w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < APL; ++q) {
+            s[q][1] += cs[q] * dy[q];
+            s[q][2] += cs[q] * dz[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[q][k] = s[q][k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     using T4 = typename V4<T>::type;
-    __shared__ T4 sbuf[2][2 * CT];
+    using T2 = typename V4<T>::half;
+    __shared__ T4 sbuf[2][2 * CT];  // 2 CT 4-vectors: CT nodes or RT rows of cells
+    __shared__ T2 srow[2][RT];
     const int t = threadIdx.x;
     const Grid& g = f.g;
     const T4* staged = static_cast<const T4*>(f.staged);
@@ -321,29 +436,41 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         const bool floor = !is_grid || __ballot(near) != 0;
         const double wscale = is_grid ? f.ph.h3 : 1.0;
         const T4* src = staged + 2 * chunk_slot0(f, chunk);
-        const int ntiles = (cnt + CT - 1) / CT;
+        const T2* rsrc = reinterpret_cast<const T2*>(src + CB3);
+        // a tile is CT units of two 4-vectors: CT nodes, or RT rows of CB
+        // cells (a row is CB / 2 units); rows are CT / RT units apart
+        const int per = is_grid ? RT : CT;             // rows or nodes per tile
+        const int units = is_grid ? cnt * (CB / 2) : cnt;
+        const int ntiles = (cnt + per - 1) / per;
         T4 ra = mk4((T)0, (T)0, (T)0, (T)0), rb = ra;
-        if (t < cnt) {
+        T2 rr = mk2((T)0, (T)0);
+        if (t < units) {
             ra = src[2 * t];
             rb = src[2 * t + 1];
         }
+        if (is_grid && t < RT && t < cnt) rr = rsrc[t];
         sbuf[0][2 * t] = ra;
         sbuf[0][2 * t + 1] = rb;
+        if (t < RT) srow[0][t] = rr;
         __syncthreads();
         for (int tile = 0; tile < ntiles; ++tile) {
             const int nxt = (tile + 1) * CT + t;
-            if (tile + 1 < ntiles && nxt < cnt) {
+            if (tile + 1 < ntiles && nxt < units) {
                 ra = src[2 * nxt];
                 rb = src[2 * nxt + 1];
             }
-            const int m = cnt - tile * CT < CT ? cnt - tile * CT : CT;
+            const int nr = (tile + 1) * RT + t;
+            if (is_grid && tile + 1 < ntiles && t < RT && nr < cnt) rr = rsrc[nr];
+            const int m = cnt - tile * per < per ? cnt - tile * per : per;
             T acc[APL][6];
             if (!is_grid)
-                tile_pairs<T, true, false>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+                tile_nodes<T>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else if (floor)
-                tile_pairs<T, true, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+                tile_rows<T, true>(sbuf[tile & 1], srow[tile & 1], m, ax, ay, az, c1, c2, k3,
+                                   r2min, acc);
             else
-                tile_pairs<T, false, true>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
+                tile_rows<T, false>(sbuf[tile & 1], srow[tile & 1], m, ax, ay, az, c1, c2, k3,
+                                    r2min, acc);
 #pragma unroll
             for (int q = 0; q < APL; ++q)
 #pragma unroll
@@ -356,6 +483,7 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
                 // barrier that ended it
                 sbuf[(tile + 1) & 1][2 * t] = ra;
                 sbuf[(tile + 1) & 1][2 * t + 1] = rb;
+                if (t < RT) srow[(tile + 1) & 1][t] = rr;
             }
             __syncthreads();
         }
