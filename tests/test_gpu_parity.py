@@ -265,6 +265,39 @@ def test_forces_match_oracle(precision):
     assert e["total"] == pytest.approx(ref["total"], rel=1e-6)
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("n,h,pattern", [(37, 0.06, "random"), (37, 0.06, "checker"),
+                                         (37, 0.06, "solute"), (12, 0.12, "random")])
+def test_forces_label_patterns_match_oracle(precision, n, h, pattern):
+    """The force sum over label fields that exercise its staging of x-rows
+    of 16 cells, on a 37^3 grid whose last chunk along each axis is
+    partial (and a 12^3 grid, one partial chunk): outside the tight
+    start's solute core, random labels (rows
+    mixing solute and solvent cells in every chunk) or alternating ones
+    along x (every kept row half solute); or every cell solute (no row
+    kept: the far field only).  The core keeps solvent cells off the atom
+    centres, where the LJ gradient is astronomically large; no bonds, so
+    the comparison is of the solvent forces alone."""
+    w = synth.random_small(n, 40, 23, h=h)
+    s = oracle_system(w)
+    core = s.init_tight() == -1
+    if pattern == "random":
+        out = np.where(np.random.default_rng(29).random(n ** 3) < 0.5, 1, -1)
+    elif pattern == "checker":
+        out = np.where(np.arange(n ** 3) % n % 2 == 0, 1, -1)   # x fastest
+    else:
+        out = np.full(n ** 3, -1)
+    phi = np.where(core, -1, out).astype(np.int8)
+    ctx = gpu_context(w, precision=precision)
+    ctx.init_labels("user", user=phi)
+    fg = ctx.forces()
+    fo = s.forces(phi)
+    ok, rel = force_close(fg, fo, 1e-4 if precision == 32 else 1e-9)
+    log("labels", pattern, "precision", precision, "solvent cells", int((phi == 1).sum()),
+        "force max rel err", float(rel.max()), "max |F|", float(np.abs(fo).max()))
+    assert ok.all()
+
+
 def test_atom_step_matches_oracle():
     w = _small_bonded(seed=14)
     s = oracle_system(w, with_bonds=True)
