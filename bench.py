@@ -187,7 +187,7 @@ def batch_comparison(rounds: int = 2):
         b.minimize(variant=best, graph=False)
         torch.cuda.synchronize()
         t5 = time.perf_counter()
-        if r > 0:  # round 0 warms up
+        if r > 0:  # the first repetition warms up
             plain_ms.append(1e3 * (t1 - t0))
             batch_ms.append(1e3 * (t3 - t2))
             eager_ms.append(1e3 * (t5 - t4))
