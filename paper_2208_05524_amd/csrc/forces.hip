@@ -18,7 +18,7 @@
 // E); a solute cell of a kept row is staged at x = BIG with E = 0, where
 // every term of the pair underflows to exactly zero (the weight h^3 common
 // to grid cells multiplies the sums of each tile instead).  Far-field nodes
-// are compacted one by one as (position, w) and w E.  The
+// are staged one by one as (position, w) and w E.  The
 // force kernel gives a workgroup 512 atoms (two per lane: every cell read
 // from LDS serves two pairs, which halves the LDS traffic) and a group of
 // consecutive chunks; the staged data of each chunk stream through a
