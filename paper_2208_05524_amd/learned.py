@@ -10,7 +10,8 @@ convolutions + ReLU per level, 2x2x2 average pooling down, nearest 2x
 upsampling + channel concatenation with the skip up, a 1x1x1 head to one
 logit per cell (solute where positive).  Input: 32 channels on the cell
 grid, of which channel 0 is the Gaussian-smeared atom density and channel 1
-the smeared charge (vesis_nn_featurize), the rest zero.
+the smeared charge (vesis_nn_featurize), the rest zero; inference takes the
+first 16 of them (the same logits, half the first convolution's work).
 
 Every layer runs in the library's HIP kernels (include/vesis_nn.h); torch
 tensors serve only as device memory.
@@ -25,6 +26,10 @@ import numpy as np
 from . import nn as N
 
 IN_C = 32
+# Inference reads the input as one 16-channel chunk: only channels 0 and 1
+# are ever nonzero, so the first convolution's second chunk of 16 input
+# channels adds exact zeros, and leaving it out changes no logit.
+INFER_C = 16
 LEVELS = (32, 64, 128, 256)
 
 
@@ -74,6 +79,10 @@ class UNet:
             if train:
                 self.p[name].update(gw=torch.zeros(27 * cout * cin, **f32),
                                     gb=torch.zeros(cout, **f32))
+        # the first convolution's weights on the inference input's channels
+        self.p["e1a"].update(
+            wf_in=torch.empty(27 * LEVELS[0] * INFER_C, dtype=torch.bfloat16, device=self.dev),
+            wb_in=torch.empty(27 * LEVELS[0] * INFER_C, dtype=torch.bfloat16, device=self.dev))
         hw, hb = w0["head"]
         self.p["head"] = dict(w=torch.tensor(np.asarray(hw, np.float32), **f32),
                               bias=torch.tensor(np.asarray(hb, np.float32), **f32))
@@ -126,18 +135,28 @@ class UNet:
                             device=self.dev)
 
     def prep(self):
-        """BF16 forward and data-gradient weights from the FP32 masters."""
+        """BF16 forward and data-gradient weights from the FP32 masters (and
+        the first convolution's on the inference input's channels)."""
         for name, cin, cout in self.specs:
             q = self.p[name]
             N.check(self.L.vesis_nn_prep_weights(self._s(), N.ptr(q["w"]), cout, cin,
                                                  N.ptr(q["wf"]), N.ptr(q["wb"])), "prep")
+        q = self.p["e1a"]
+        w_in = q["w"].reshape(27, q["cout"], q["cin"])[:, :, :INFER_C].contiguous()
+        N.check(self.L.vesis_nn_prep_weights(self._s(), N.ptr(w_in), q["cout"], INFER_C,
+                                             N.ptr(q["wf_in"]), N.ptr(q["wb_in"])), "prep")
 
     def conv(self, name, x, relu=True):
         q = self.p[name]
         s = x.shape[1]
+        cin, wf = q["cin"], q["wf"]
+        if name == "e1a" and x.shape[4] == INFER_C:
+            cin, wf = INFER_C, q["wf_in"]
+        elif x.shape[4] != cin:
+            raise ValueError(f"conv {name}: {x.shape[4]} input channels, expected {cin}")
         y = self._act(s, q["cout"])
-        N.check(self.L.vesis_nn_conv3_fwd(self._s(), N.ptr(x), N.ptr(q["wf"]), N.ptr(q["bias"]),
-                                          N.ptr(y), self.b, s, s, s, q["cin"], q["cout"],
+        N.check(self.L.vesis_nn_conv3_fwd(self._s(), N.ptr(x), N.ptr(wf), N.ptr(q["bias"]),
+                                          N.ptr(y), self.b, s, s, s, cin, q["cout"],
                                           1 if relu else 0), "conv " + name)
         return y
 
@@ -174,21 +193,28 @@ class UNet:
         return y
 
     # ------------------------------------------------------------ forward
-    def featurize(self, pos4, sigma, q, h, center, out=None):
-        """Input channels for one molecule (device FP64 arrays) on this grid."""
-        x = out if out is not None else self._act(self.n, IN_C)
+    def featurize(self, pos4, sigma, q, h, center, out=None, channels=IN_C):
+        """Input channels for one molecule (device FP64 arrays) on this grid:
+        IN_C for training, INFER_C for inference (forward with keep=False)."""
+        x = out if out is not None else self._act(self.n, channels)
+        if x.shape[4] != channels:
+            raise ValueError("featurize: the output tensor's channels differ from `channels`")
         cen = (C.c_double * 3)(*[float(v) for v in center])
         N.check(self.L.vesis_nn_featurize(self._s(), N.ptr(pos4), N.ptr(sigma), N.ptr(q),
                                           int(sigma.numel()), self.n, float(h),
-                                          C.cast(cen, C.c_void_p), IN_C, N.ptr(x)), "featurize")
+                                          C.cast(cen, C.c_void_p), channels, N.ptr(x)),
+                "featurize")
         return x
 
     def forward(self, x, keep: bool = True):
-        """x: (b, n, n, n, 32) BF16.  Returns logits (b n^3 FP32).  keep: hold
-        the activations for backward; without it (inference) the decoder
-        convolutions read [up2(deeper) | skip] in place."""
+        """x: (b, n, n, n, IN_C) BF16, or (b, n, n, n, INFER_C) for
+        inference.  Returns logits (b n^3 FP32).  keep: hold the activations
+        for backward; without it (inference) the decoder convolutions read
+        [up2(deeper) | skip] in place."""
         if not keep:
             return self._infer(x)
+        if x.shape[4] != IN_C:
+            raise ValueError(f"forward with keep=True takes {IN_C} input channels")
         a = {"x": x}
         a["a1"] = self.conv("e1a", x)
         a["s1"] = self.conv("e1b", a["a1"])
@@ -353,15 +379,6 @@ class UNet:
                                          self.step_count), "adam")
         self.prep()
 
-    def weights(self):
-        """FP32 master weights as numpy, in init_weights' format."""
-        out = {}
-        for name, cin, cout in self.specs:
-            q = self.p[name]
-            out[name] = (q["w"].cpu().numpy().reshape(27, cout, cin), q["bias"].cpu().numpy())
-        out["head"] = (self.p["head"]["w"].cpu().numpy(), self.p["head"]["bias"].cpu().numpy())
-        return out
-
     def grads(self):
         out = {}
         for name, cin, cout in self.specs:
@@ -433,7 +450,7 @@ def train(model: UNet, samples, steps: int, lr: float = 1e-3, pos_weight: float 
 
 
 def predict_logits(model: UNet, pos4, sigma, q, h, center):
-    x = model.featurize(pos4, sigma, q, h, center)
+    x = model.featurize(pos4, sigma, q, h, center, channels=INFER_C)
     return model.forward(x, keep=False)
 
 
@@ -513,7 +530,7 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
     b = Batch(ctxs)
     times = {}
     inf = UNet(128, batch=len(test_set), weights=model.weights(), train=False)
-    xb = inf._act(128, IN_C)
+    xb = inf._act(128, INFER_C)
     n3 = 128 ** 3
     for rep in range(2):
         for c, w in zip(ctxs, test_set):
@@ -538,7 +555,7 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for i, (w, a) in enumerate(zip(test_set, arrays)):
-            inf.featurize(a[0], a[1], a[2], w.h, w.center, out=xb[i:i + 1])
+            inf.featurize(a[0], a[1], a[2], w.h, w.center, out=xb[i:i + 1], channels=INFER_C)
         logits = inf.forward(xb, keep=False)
         for i, c in enumerate(ctxs):
             c.init_labels_logits(logits[i * n3:(i + 1) * n3])
@@ -566,12 +583,15 @@ def warm_start_experiment(n_train: int = 2000, n_test: int = 32, epochs: int = 1
         **times, "rows": rows}
 
 
-def conv_flops(n: int, batch: int = 1) -> float:
+def conv_flops(n: int, batch: int = 1, in_c: int = IN_C) -> float:
     """Multiply-add work (2 flops each) of the network's 3x3x3 convolutions at
-    grid n: 27 cin cout per position at each layer's resolution."""
+    grid n: 27 cin cout per position at each layer's resolution, the first
+    layer reading in_c channels (INFER_C for inference)."""
     total = 0.0
     for name, cin, cout in layer_specs():
         s = n >> (int(name[1]) - 1)
+        if name == "e1a":
+            cin = in_c
         total += 2.0 * 27 * cin * cout * batch * s ** 3
     return total
 
@@ -579,13 +599,13 @@ def conv_flops(n: int, batch: int = 1) -> float:
 def inference_timing(n: int = 128, batch: int = 16, reps: int = 5, seed: int = 0):
     """Device time of the inference forward pass (keep=False) of an
     inference-only network (initial weights) on random BF16 input of `batch`
-    grids of n^3 cells; returns ms per batch, ms per molecule and the
-    convolutions' TFLOP/s."""
+    grids of n^3 cells and INFER_C channels; returns ms per batch, ms per
+    molecule and the convolutions' TFLOP/s."""
     import time
 
     import torch
     m = UNet(n, batch=batch, seed=seed, train=False)
-    x = m._act(n, IN_C)
+    x = m._act(n, INFER_C)
     g = torch.Generator(device=m.dev).manual_seed(seed)
     x.copy_(torch.rand(x.shape, generator=g, device=m.dev).to(torch.bfloat16))
     m.forward(x, keep=False)
@@ -596,8 +616,8 @@ def inference_timing(n: int = 128, batch: int = 16, reps: int = 5, seed: int = 0
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
     return {"grid": n, "batch": batch, "ms_per_batch": ms, "ms_per_molecule": ms / batch,
-            "conv_tflops": conv_flops(n, batch) / (ms * 1e-3) / 1e12,
-            "conv_flop_per_molecule": conv_flops(n)}
+            "conv_tflops": conv_flops(n, batch, INFER_C) / (ms * 1e-3) / 1e12,
+            "conv_flop_per_molecule": conv_flops(n, 1, INFER_C)}
 
 
 if __name__ == "__main__":

@@ -96,6 +96,38 @@ def test_batched_inference_equals_one_molecule_at_a_time():
         assert torch.equal(lb[i * n3:(i + 1) * n3], one[i]), i
 
 
+@pytest.mark.parametrize("n,batch", [(64, 2), (16, 1)])
+def test_inference_on_the_featurised_chunk_equals_the_full_input(n, batch):
+    """Inference reads the featurised input as one 16-channel chunk (only
+    channels 0 and 1 are nonzero) with the first convolution's weights on
+    those channels: the logits equal those from the 32-channel input bit for
+    bit, for weights with nonzero biases, through the z-reuse kernel (64^3,
+    batch 2) and the one-layer-per-workgroup kernel (16^3)."""
+    import torch
+
+    from paper_2208_05524_amd.learned import IN_C, INFER_C, UNet, molecule_arrays
+    rng = np.random.default_rng(11)
+    w0 = {}
+    m0 = UNet(n, seed=12)
+    for k, (wk, bk) in m0.weights().items():
+        w0[k] = (wk, (0.05 * rng.standard_normal(bk.shape)).astype(np.float32))
+    m = UNet(n, batch=batch, weights=w0, train=False)
+    ws = [synth.random_small(n, 30 + 20 * i, seed=71 + i, h=0.1) for i in range(batch)]
+    x32 = m._act(n, IN_C)
+    x16 = m._act(n, INFER_C)
+    for i, w in enumerate(ws):
+        pos4, sig, q = molecule_arrays(w, torch.device("cuda"))
+        m.featurize(pos4, sig, q, w.h, w.center, out=x32[i:i + 1])
+        m.featurize(pos4, sig, q, w.h, w.center, out=x16[i:i + 1], channels=INFER_C)
+    torch.cuda.synchronize()
+    assert torch.equal(x32[..., :INFER_C], x16)
+    l32 = m.forward(x32, keep=False).clone()
+    l16 = m.forward(x16, keep=False)
+    torch.cuda.synchronize()
+    assert torch.equal(l32, l16)
+    assert float(l32.std()) > 0
+
+
 @pytest.mark.parametrize("n,cin,cout,relu", [(8, 32, 64, 1), (6, 16, 32, 0), (5, 96, 32, 1),
                                              (16, 32, 64, 1), (20, 32, 32, 1), (18, 16, 64, 0),
                                              (24, 96, 32, 1)])
