@@ -52,7 +52,8 @@ static_assert(CB * CB == 256, "the staging kernel gives one thread each row of a
 static_assert(AWG == CT, "a force workgroup loads one tile unit per thread");
 static_assert(CB <= 16 && 32 % CB == 0, "a chunk row lies within one label word");
 constexpr int FAR_CHUNK = 4096; // far-field nodes per chunk
-constexpr int GROUP = 4;        // chunks per force workgroup
+constexpr int GROUP = 4;        // chunks per force workgroup (at least)
+constexpr int64_t MAX_GRID_Y = 65535;  // launch limit of the second grid dimension
 constexpr int RSPLIT = 8;       // group slices per atom in the reduction
 constexpr int RATOMS = 32;      // atoms per reduction workgroup
 
@@ -61,7 +62,13 @@ struct ChunkPlan {
     int64_t ngrid;        // grid chunks
     int64_t nfar_chunks;  // far-field chunks
     int64_t nchunks() const { return ngrid + nfar_chunks; }
-    int64_t ngroups() const { return (nchunks() + GROUP - 1) / GROUP; }
+    // chunks per group: GROUP, or more where the groups would not fit the
+    // second grid dimension (grids above ~1000 cells per axis)
+    int64_t group() const {
+        const int64_t g = (nchunks() + MAX_GRID_Y - 1) / MAX_GRID_Y;
+        return g > GROUP ? g : GROUP;
+    }
+    int64_t ngroups() const { return (nchunks() + group() - 1) / group(); }
     // staged slots (each slot is two 4-vectors; a grid chunk's cells fill
     // the first CB3 4-vectors of its 2 CB3, its rows' (y, z) the rest)
     int64_t slots() const { return ngrid * CB3 + nfar_chunks * FAR_CHUNK; }
@@ -91,6 +98,7 @@ struct ForceArgs {
     int ncx;              // grid chunks per axis
     int64_t ngrid;        // grid chunks
     int64_t nchunks;      // grid + far chunks
+    int64_t group;        // chunks per force workgroup
     void* staged;         // [slot][2] 4-vectors of the working precision
     int* count;           // staged rows (grid chunk) or nodes (far chunk)
     double* partial;      // [group][atom][3]
@@ -415,8 +423,8 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) gd[q][k] = ge[q][k] = 0.0;
 
-    const int64_t ch0 = (int64_t)blockIdx.y * GROUP;
-    const int64_t ch1 = ch0 + GROUP < f.nchunks ? ch0 + GROUP : f.nchunks;
+    const int64_t ch0 = (int64_t)blockIdx.y * f.group;
+    const int64_t ch1 = ch0 + f.group < f.nchunks ? ch0 + f.group : f.nchunks;
     for (int64_t chunk = ch0; chunk < ch1; ++chunk) {
         const int cnt = f.count[chunk];
         if (cnt == 0) continue;  // uniform over the workgroup
@@ -617,6 +625,7 @@ hipError_t launch_forces(const Grid& g, const Atoms& a, const Physics& ph, int p
     f.ncx = p.ncx;
     f.ngrid = p.ngrid;
     f.nchunks = p.nchunks();
+    f.group = p.group();
     f.staged = scr.staged;
     f.count = scr.count;
     f.partial = scr.partial;
