@@ -317,11 +317,9 @@ vesis_status vesis_batch_workspace_size(vesis_ctx* const* ctxs, int32_t m, size_
  * 2: four cells per lane on 16x8x8 bricks) on the batch, and, when every
  * molecule has labels, the first four sweeps of colour passes with each
  * colour-pass variant f from the current labels, which are put back
- * afterwards: with
- * colour period 3, f = 0 runs the three colours that share their rows in
- * one launch and f = 1 one launch per colour (registers capped for four
- * wavefronts per SIMD); with period 2, one launch per colour with the
- * compiler's register allocation (f = 0) or the cap (f = 1).
+ * afterwards: with colour period 3, f = 0 runs the three colours that share
+ * their rows in one launch and f = 1 one launch per colour; with period 2
+ * both launch one colour at a time, and only f = 0 is timed.
  * *best = d + 3 f of the fastest of each (f = 0 when not timed), the value
  * vesis_minimize_batch takes as `variant`; ms (may be NULL, 5 entries)
  * receives the density times (ms[d]) and the sweep times (ms[3 + f], -1

@@ -1686,7 +1686,7 @@ hipError_t launch_batch_sweep(const MolDesc* ddesc, const int* dmap, const int* 
     }
     for (int c = 0; c < ncol && e == hipSuccess; ++c)
         e = launch_flip_pass_batch(ddesc, dmap, ddone, dpass, nblocks, p, c, sw, sw * ncol + c,
-                                   fvar, st);
+                                   st);
     return e;
 }
 
@@ -1753,7 +1753,9 @@ vesis_status vesis_batch_tune(vesis_ctx* const* ctxs, int32_t m, void* bws, size
             CK(hipMemcpyAsync(ctxs[i]->ws + ctxs[i]->lay.fstage, desc[i].bits,
                               4 * (size_t)ctxs[i]->g.nwords(), hipMemcpyDeviceToDevice, st));
         double fb = 0.0;
-        for (int v = 0; v < FLIP_VARIANTS; ++v) {
+        // with colour period 2 both variants launch one colour at a time
+        const int nfv = p == 3 ? FLIP_VARIANTS : 1;
+        for (int v = 0; v < nfv; ++v) {
             double tv = 1e300;
             for (int rep = 0; rep < 2; ++rep) {
                 CK(launch_batch_prepare(ddesc, m, max_words, st));

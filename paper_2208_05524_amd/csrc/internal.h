@@ -198,13 +198,15 @@ int64_t flip_blocks(const Grid& g, int p);
 hipError_t launch_flip_group3_batch(const MolDesc* descs, const int* block_mol, const int* done,
                                     const int* pass_base, int64_t nblocks, int group, int sweep,
                                     int gpass_off, hipStream_t st);
-// done[k] != 0 skips molecule k; the pass index is *pass_base + gpass_off.
-// variant: 0 = registers at the compiler's choice, 1 = capped for four
-// wavefronts per SIMD (the same arithmetic, so the same labels).
-constexpr int FLIP_VARIANTS = 2;
+// One colour pass over a batch: done[k] != 0 skips molecule k; the pass
+// index is *pass_base + gpass_off.
 hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
                                   const int* pass_base, int64_t nblocks, int p, int colour,
-                                  int sweep, int gpass_off, int variant, hipStream_t st);
+                                  int sweep, int gpass_off, hipStream_t st);
+// Colour-pass variants of a batch: 0 = the three colours that share their
+// rows in one launch (colour period 3; one colour per launch with period 2),
+// 1 = one colour per launch.
+constexpr int FLIP_VARIANTS = 2;
 // End of a group of nsweeps sweeps: flag molecules that had a sweep without
 // flips, advance *pass_base by nsweeps * ncol.
 hipError_t launch_batch_end_group(const MolDesc* descs, int m, int nsweeps, int ncol, int* done,

@@ -282,10 +282,8 @@ __device__ inline int64_t flip_block_of(unsigned b, int64_t xcd_blocks) {
 // and the host chooses which die runs which molecule.  In a batch, molecules
 // flagged in `done` are skipped and the pass index is *pass_base + gpass, so
 // that one captured sequence of passes can be replayed.
-// W: the fewest wavefronts per SIMD the register allocation must allow (1:
-// the compiler's choice; 4 caps the kernel at 128 VGPRs).
-template <bool BATCH, int P, int W>
-__global__ __launch_bounds__(FWG) __attribute__((amdgpu_waves_per_eu(W, 8))) void flip_pass_kernel(
+template <bool BATCH, int P>
+__global__ __launch_bounds__(FWG) void flip_pass_kernel(
     MolDesc one, const MolDesc* descs, const int* block_mol, const int* done,
     const int* pass_base, int colour, int sweep, int gpass, int ncol, int64_t xcd_blocks) {
     constexpr int K = (32 + P - 1) / P;  // cells of one colour in a word
@@ -958,10 +956,10 @@ hipError_t launch_flip_pass(const Grid& g, const Stencil& sc, const Atoms& a, co
     const int64_t xb = (nblk(total, FWG) + NXCD - 1) / NXCD;  // logical blocks per die
     const dim3 grid((unsigned)(xb * NXCD));
     if (p == 2)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 2, 1>), grid, dim3(FWG), 0, st, d, nullptr,
+        hipLaunchKernelGGL((flip_pass_kernel<false, 2>), grid, dim3(FWG), 0, st, d, nullptr,
                            nullptr, nullptr, nullptr, colour, sweep, gpass, 8, xb);
     else if (p == 3)
-        hipLaunchKernelGGL((flip_pass_kernel<false, 3, 1>), grid, dim3(FWG), 0, st, d, nullptr,
+        hipLaunchKernelGGL((flip_pass_kernel<false, 3>), grid, dim3(FWG), 0, st, d, nullptr,
                            nullptr, nullptr, nullptr, colour, sweep, gpass, 27, xb);
     else
         return hipErrorInvalidValue;
@@ -1042,21 +1040,15 @@ hipError_t launch_cell_density_f64(const Grid& g, const Atoms& a, const Physics&
 
 hipError_t launch_flip_pass_batch(const MolDesc* descs, const int* block_mol, const int* done,
                                   const int* pass_base, int64_t nblocks, int p, int colour,
-                                  int sweep, int gpass_off, int variant, hipStream_t st) {
+                                  int sweep, int gpass_off, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     MolDesc unused{};
     const dim3 grid((unsigned)nblocks);
-    if (p == 2 && variant == 0)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 2, 1>), grid, dim3(FWG), 0, st, unused, descs,
+    if (p == 2)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 2>), grid, dim3(FWG), 0, st, unused, descs,
                            block_mol, done, pass_base, colour, sweep, gpass_off, 8, (int64_t)0);
-    else if (p == 2 && variant == 1)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 2, 4>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 8, (int64_t)0);
-    else if (p == 3 && variant == 0)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 3, 1>), grid, dim3(FWG), 0, st, unused, descs,
-                           block_mol, done, pass_base, colour, sweep, gpass_off, 27, (int64_t)0);
-    else if (p == 3 && variant == 1)
-        hipLaunchKernelGGL((flip_pass_kernel<true, 3, 4>), grid, dim3(FWG), 0, st, unused, descs,
+    else if (p == 3)
+        hipLaunchKernelGGL((flip_pass_kernel<true, 3>), grid, dim3(FWG), 0, st, unused, descs,
                            block_mol, done, pass_base, colour, sweep, gpass_off, 27, (int64_t)0);
     else
         return hipErrorInvalidValue;
