@@ -14,10 +14,12 @@
 // 16^3 brick of the grid, or a run of 4096 far-field nodes), what the force
 // sum visits, in the working precision.  A grid chunk keeps its x-rows of 16
 // cells that hold at least one solvent cell, in row order: per row its
-// (y, z) relative to the chunk centre, per cell (x relative to the centre,
-// E); a solute cell of a kept row is staged at x = BIG with E = 0, where
-// every term of the pair underflows to exactly zero (the weight h^3 common
-// to grid cells multiplies the sums of each tile instead).  Far-field nodes
+// (y, z) relative to the chunk centre and the span of its solvent cells
+// (from the first to the last, widened to whole pairs), per cell (x
+// relative to the centre, E); a solute cell of a kept row is staged at
+// x = BIG with E = 0, where every term of the pair underflows to exactly
+// zero, and the pairs outside the span are not visited (the weight h^3
+// common to grid cells multiplies the sums of each tile instead).  Far-field nodes
 // are staged one by one as (position, w) and w E.  The
 // force kernel gives a workgroup 512 atoms (two per lane: every cell read
 // from LDS serves two pairs, which halves the LDS traffic) and a group of
@@ -70,7 +72,8 @@ struct ChunkPlan {
     }
     int64_t ngroups() const { return (nchunks() + group() - 1) / group(); }
     // staged slots (each slot is two 4-vectors; a grid chunk's cells fill
-    // the first CB3 4-vectors of its 2 CB3, its rows' (y, z) the rest)
+    // the first CB3 4-vectors of its 2 CB3, its rows' (y, z) and spans the
+    // rest)
     int64_t slots() const { return ngrid * CB3 + nfar_chunks * FAR_CHUNK; }
 };
 
@@ -193,10 +196,16 @@ __global__ __launch_bounds__(256) void force_stage_kernel(ForceArgs f) {
             nrows += wcnt[v];
         }
         T2* rowpos = reinterpret_cast<T2*>(out + CB3);
+        int* rowrange = reinterpret_cast<int*>(rowpos + CB * CB);
         if (keep) {
             s_seg[k] = seg;
             s_row[k] = t;
             rowpos[k] = mk2((T)((ly - 0.5 * (CB - 1)) * g.h), (T)((lz - 0.5 * (CB - 1)) * g.h));
+            // the row's solvent cells lie in [first, last]; taken as whole
+            // pairs (first even, last odd), the cells between being
+            // sentinels that add exact zeros
+            const int first = __builtin_ctz(seg) & ~1, last = (31 - __builtin_clz(seg)) | 1;
+            rowrange[k] = first | (last << 8);
         }
         __syncthreads();
         const int lx = t % CB;
@@ -307,13 +316,15 @@ __device__ __forceinline__ void tile_nodes(const typename V4<T>::type* sc, int c
         for (int k = 0; k < 6; ++k) acc[q][k] = s[q][k];
 }
 
-// Grid rows: (y, z) per row, (x, E) per cell, unit weight.  Per row and atom
-// dy, dz and dy^2 + dz^2 once; per pair dx, r^2 = dx^2 + (dy^2 + dz^2), the
+// Grid rows: (y, z) and the span [first, last] (packed first | last << 8)
+// per row, (x, E) per cell, unit weight.  Per row and atom dy, dz and
+// dy^2 + dz^2 once; per pair of the span dx, r^2 = dx^2 + (dy^2 + dz^2), the
 // coefficient, its x part and its running sum over the row, whose y and z
 // parts are taken once at the end of the row.
 template <typename T, bool FLOOR>
 __device__ __forceinline__ void tile_rows(const typename V4<T>::type* sc,
-                                          const typename V4<T>::half* rows, int nrows,
+                                          const typename V4<T>::half* rows, const int* ranges,
+                                          int nrows,
                                           const T (&ax)[APL], const T (&ay)[APL],
                                           const T (&az)[APL], const T (&c1)[APL],
                                           const T (&c2)[APL], const T (&k3)[APL], T r2min,
@@ -335,10 +346,12 @@ __device__ __forceinline__ void tile_rows(const typename V4<T>::type* sc,
             ryz[q] = dy[q] * dy[q] + dz[q] * dz[q];
             cs[q] = 0;
         }
+        const int rg = ranges[r];
+        const int lx1 = rg >> 8;
         // two cells per iteration: the fully unrolled row (16 cells, ~1,300
         // instructions per floor variant) ran 25 % slower than this
 #pragma unroll 2
-        for (int lx = 0; lx < CB; ++lx) {
+        for (int lx = rg & 255; lx <= lx1; ++lx) {
             const T4 c = sc[r * CB + lx];  // x, Ex, Ey, Ez
 #pragma unroll
             for (int q = 0; q < APL; ++q) {
@@ -385,6 +398,7 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
     using T2 = typename V4<T>::half;
     __shared__ T4 sbuf[2][2 * CT];  // 2 CT 4-vectors: CT nodes or RT rows of cells
     __shared__ T2 srow[2][RT];
+    __shared__ int srng[2][RT];
     const int t = threadIdx.x;
     const Grid& g = f.g;
     const T4* staged = static_cast<const T4*>(f.staged);
@@ -445,6 +459,7 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         const double wscale = is_grid ? f.ph.h3 : 1.0;
         const T4* src = staged + 2 * chunk_slot0(f, chunk);
         const T2* rsrc = reinterpret_cast<const T2*>(src + CB3);
+        const int* gsrc = reinterpret_cast<const int*>(rsrc + CB * CB);
         // a tile is CT units of two 4-vectors: CT nodes, or RT rows of CB
         // cells (a row is CB / 2 units); rows are CT / RT units apart
         const int per = is_grid ? RT : CT;             // rows or nodes per tile
@@ -452,14 +467,21 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
         const int ntiles = (cnt + per - 1) / per;
         T4 ra = mk4((T)0, (T)0, (T)0, (T)0), rb = ra;
         T2 rr = mk2((T)0, (T)0);
+        int rq = 0;
         if (t < units) {
             ra = src[2 * t];
             rb = src[2 * t + 1];
         }
-        if (is_grid && t < RT && t < cnt) rr = rsrc[t];
+        if (is_grid && t < RT && t < cnt) {
+            rr = rsrc[t];
+            rq = gsrc[t];
+        }
         sbuf[0][2 * t] = ra;
         sbuf[0][2 * t + 1] = rb;
-        if (t < RT) srow[0][t] = rr;
+        if (t < RT) {
+            srow[0][t] = rr;
+            srng[0][t] = rq;
+        }
         __syncthreads();
         for (int tile = 0; tile < ntiles; ++tile) {
             const int nxt = (tile + 1) * CT + t;
@@ -468,17 +490,20 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
                 rb = src[2 * nxt + 1];
             }
             const int nr = (tile + 1) * RT + t;
-            if (is_grid && tile + 1 < ntiles && t < RT && nr < cnt) rr = rsrc[nr];
+            if (is_grid && tile + 1 < ntiles && t < RT && nr < cnt) {
+                rr = rsrc[nr];
+                rq = gsrc[nr];
+            }
             const int m = cnt - tile * per < per ? cnt - tile * per : per;
             T acc[APL][6];
             if (!is_grid)
                 tile_nodes<T>(sbuf[tile & 1], m, ax, ay, az, c1, c2, k3, r2min, acc);
             else if (floor)
-                tile_rows<T, true>(sbuf[tile & 1], srow[tile & 1], m, ax, ay, az, c1, c2, k3,
-                                   r2min, acc);
+                tile_rows<T, true>(sbuf[tile & 1], srow[tile & 1], srng[tile & 1], m, ax, ay, az,
+                                   c1, c2, k3, r2min, acc);
             else
-                tile_rows<T, false>(sbuf[tile & 1], srow[tile & 1], m, ax, ay, az, c1, c2, k3,
-                                    r2min, acc);
+                tile_rows<T, false>(sbuf[tile & 1], srow[tile & 1], srng[tile & 1], m, ax, ay,
+                                    az, c1, c2, k3, r2min, acc);
 #pragma unroll
             for (int q = 0; q < APL; ++q)
 #pragma unroll
@@ -491,7 +516,10 @@ __global__ __launch_bounds__(AWG) void force_adjoint_kernel(ForceArgs f) {
                 // barrier that ended it
                 sbuf[(tile + 1) & 1][2 * t] = ra;
                 sbuf[(tile + 1) & 1][2 * t + 1] = rb;
-                if (t < RT) srow[(tile + 1) & 1][t] = rr;
+                if (t < RT) {
+                    srow[(tile + 1) & 1][t] = rr;
+                    srng[(tile + 1) & 1][t] = rq;
+                }
             }
             __syncthreads();
         }
